@@ -1,0 +1,280 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* closed forms at beta = 1 (mu_j = j!): D_m = (m!)^2 and L_ri = C(r,i) r!/i!
+  exactly, det H_N = prod (m!)^2;
+* exact rational LDL^T for tiny N (beta = 1/2, irrational-free but with
+  non-integer factors), within the contract's rounding bound;
+* the brute-force characteristic polynomial for N <= 8 (sympy's independent
+  routine and the Sturm-isolated smallest root);
+* the values printed in Table 2 at N = 500;
+* agreement at doubled precision;
+* interlacing (trunc <= 0), positivity of pivots, the error paths.
+"""
+import math
+from fractions import Fraction
+
+import mpmath
+import pytest
+
+from hankel_inputs import moments
+from oracle import contract as C
+from oracle import exact as X
+
+
+def _mu(beta, N, bits=0):
+    return moments(beta, 2 * N - 1, mant_bits=bits)
+
+
+# ------------------------------------------------------------------ beta = 1 closed forms
+
+@pytest.mark.parametrize("N,P", [(32, 2048), (64, 4096)])
+def test_beta1_pivots_and_multipliers_closed_form(N, P):
+    f = C.factor(_mu(1, N), N, P, E=16)
+    W = f.W
+    for m in range(N):
+        assert f.d[m] == math.factorial(m) ** 2 << (W - 2 * f.s[m])
+    for i in range(N):
+        for r in range(i + 1, N):
+            L = math.comb(r, i) * math.factorial(r) // math.factorial(i)
+            ex = f.s[i] + f.h[i] - f.s[r]
+            assert ex >= 0
+            assert f.b[i][r] == L << ex
+
+
+def test_exact_ldl_beta1_and_determinant():
+    N = 9
+    H = X.hankel([m.to_fraction() for m in _mu(1, N)], N)
+    L, D = X.ldl(H)
+    assert D == [Fraction(math.factorial(m) ** 2) for m in range(N)]
+    for r in range(N):
+        for i in range(r):
+            assert L[r][i] == math.comb(r, i) * Fraction(math.factorial(r), math.factorial(i))
+    # det H_N = prod D = prod (m!)^2, against sympy's determinant
+    import sympy
+    det = sympy.Matrix([[sympy.Integer(int(v)) for v in row] for row in H]).det()
+    assert det == math.prod(math.factorial(m) ** 2 for m in range(N))
+
+
+def test_exact_linv_beta1_closed_form():
+    # (L^-1)_ij = (-1)^(i-j) C(i,j) i!/j! for the Laguerre moments
+    N = 9
+    H = X.hankel([m.to_fraction() for m in _mu(1, N)], N)
+    L, D = X.ldl(H)
+    Xi = X.linv_cols(L, 4)
+    for a in range(4):
+        for r in range(N):
+            want = 0 if r < a else (-1) ** (r - a) * math.comb(r, a) * Fraction(math.factorial(r), math.factorial(a))
+            assert Xi[r][a] == want
+
+
+# ------------------------------------------------------------------ exact rationals, beta = 1/2
+
+@pytest.mark.parametrize("N,P,E", [(12, 1024, 1), (20, 2048, 16), (24, 2048, 4)])
+def test_contract_matches_exact_rationals(N, P, E):
+    mu = _mu(Fraction(1, 2), N)
+    f = C.factor(mu, N, P, E)
+    H = X.hankel([m.to_fraction() for m in mu], N)
+    L, D = X.ldl(H)
+    for i in range(N):
+        rel = abs(C.D_value(f, i) / D[i] - 1)
+        assert rel < Fraction(1, 2 ** (P // 2)), (i, float(rel))
+    for i in range(N):
+        for r in range(i + 1, N):
+            assert abs(C.L_value(f, r, i) - L[r][i]) <= abs(L[r][i]) * Fraction(1, 2 ** (P // 2)) + Fraction(1, 2 ** (P // 2))
+
+
+def test_block_matches_exact_hinv():
+    N, P, k = 16, 2048, 6
+    mu = _mu(Fraction(1, 2), N)
+    f = C.factor(mu, N, P, 16)
+    sv = C.solve(f, k)
+    bl = C.block(f, sv)
+    H = X.hankel([m.to_fraction() for m in mu], N)
+    L, D = X.ldl(H)
+    Hi = X.hinv_block(X.linv_cols(L, k), D, k)
+    scale = Fraction(2) ** bl.blk_exp if bl.blk_exp >= 0 else Fraction(1, 2 ** -bl.blk_exp)
+    top = max(abs(v) for row in Hi for v in row)
+    for a in range(k):
+        for b in range(k):
+            assert abs(bl.blk[a][b] * scale - Hi[a][b]) <= top * Fraction(1, 2 ** (P // 2))
+
+
+# ------------------------------------------------------------------ brute-force characteristic polynomial
+
+@pytest.mark.parametrize("beta", [Fraction(1, 2), Fraction(1), Fraction(1, 3)])
+@pytest.mark.parametrize("N", [4, 8])
+def test_lambda1_against_characteristic_polynomial(beta, N):
+    mu = _mu(beta, N)
+    H = X.hankel([m.to_fraction() for m in mu], N)
+    c = X.charpoly(H)
+    import sympy
+    x = sympy.symbols("x")
+    sp = sympy.Matrix([[sympy.Rational(v.numerator, v.denominator) for v in row] for row in H]).charpoly(x).all_coeffs()[::-1]
+    assert [Fraction(int(sympy.numer(v)), int(sympy.denom(v))) for v in sp] == c
+    tr = sum(H[i][i] for i in range(N))
+    lam = X.smallest_root(c, tr, bits=400 + int(tr).bit_length())
+    P = 1024
+    f, sv, bl, ev = C.lambda_min(mu, N, N, P, E=1)   # k = N: the block is all of H^-1
+    with mpmath.workprec(600):
+        ref = mpmath.mpf(lam.numerator) / lam.denominator
+        assert abs(ev.lam1 / ref - 1) < mpmath.mpf(10) ** -90
+
+
+# ------------------------------------------------------------------ doubled precision, full-matrix eigenvalues
+
+def test_doubled_precision_agreement_c1():
+    mu = _mu(Fraction(1, 2), 64)
+    _, _, _, a = C.lambda_min(mu, 64, 8, 2048, 16)
+    _, _, _, b = C.lambda_min(mu, 64, 8, 4096, 16)
+    with mpmath.workprec(9000):
+        assert abs(a.lam1 / b.lam1 - 1) < mpmath.mpf(10) ** -300
+        assert a.trunc <= 0 and b.trunc <= 0
+        assert abs(a.trunc / b.trunc - 1) < mpmath.mpf(10) ** -200
+
+
+def test_truncation_against_full_matrix_eigenvalue():
+    # untruncated lambda_1 of H_32 by a dense eigen-solver on the exact matrix
+    N = 32
+    mu = _mu(Fraction(1, 2), N)
+    with mpmath.workprec(1500):
+        M = mpmath.matrix(N, N)
+        for i in range(N):
+            for j in range(N):
+                M[i, j] = mpmath.mpf(mu[i + j].M)
+        lam_full = min(mpmath.eigsy(M, eigvals_only=True))
+    _, _, _, ev_full = C.lambda_min(mu, N, N, 2048, 16)
+    _, _, _, ev8 = C.lambda_min(mu, N, 8, 2048, 16)
+    with mpmath.workprec(1500):
+        assert abs(ev_full.lam1 / lam_full - 1) < mpmath.mpf(10) ** -100
+        err8 = ev8.lam1 - lam_full
+        assert err8 >= 0                      # truncating H^-1 can only raise 1/lambda_max
+        assert err8 < abs(ev8.trunc) * 10     # the k-1 difference bounds the k error
+
+
+# ------------------------------------------------------------------ Table 2
+
+@pytest.mark.slow
+def test_table2_n500():
+    # Table 2, N = 500, beta = 1/2: smallest eigenvalue 0.1204653471966412 with
+    # truncation error -6.52e-16 (k = 8; the paper reports 16 digits from a
+    # double-precision eigen-solve, so 1e-15 relative is the comparison bar).
+    mu = _mu(Fraction(1, 2), 500)
+    _, _, _, ev = C.lambda_min(mu, 500, 8, 1280, E=1)
+    assert abs(float(ev.lam1) / 0.1204653471966412 - 1) < 1e-15
+    assert -7.5e-16 < float(ev.trunc) < -5.5e-16
+
+
+# ------------------------------------------------------------------ invariants and error paths
+
+def test_pivots_positive_and_reconstruction():
+    N, P = 24, 1024
+    mu = _mu(Fraction(1, 2), N)
+    f = C.factor(mu, N, P, 4)
+    assert all(v > 0 for v in f.d)
+    H = X.hankel([m.to_fraction() for m in mu], N)
+    for r in range(N):
+        for c in range(r + 1):
+            v = sum((C.L_value(f, r, i) if r != i else 1) * C.D_value(f, i) * (C.L_value(f, c, i) if c != i else 1)
+                    for i in range(c + 1))
+            assert abs(v / H[r][c] - 1) < Fraction(1, 2 ** (P // 2))
+
+
+def test_not_positive_definite_input():
+    # mu_2 < mu_1^2 / mu_0 breaks positive definiteness at pivot 1
+    from hankel_inputs import Dyadic
+    mu = [Dyadic(4, 0), Dyadic(4, 0), Dyadic(3, 0), Dyadic(9, 0), Dyadic(30, 0)]
+    with pytest.raises(C.ContractError) as e:
+        C.factor(mu, 3, 256, 1)
+    assert e.value.code == C.ENOTPD and e.value.index == 1
+
+
+def test_precision_too_small_is_reported():
+    mu = _mu(Fraction(1, 2), 64)
+    with pytest.raises(C.ContractError) as e:
+        C.factor(mu, 64, 128, 16)
+    assert e.value.code in (C.ENOTPD, C.EOVERFLOW)
+
+
+def test_bad_arguments():
+    with pytest.raises(C.ContractError) as e:
+        C.factor(_mu(1, 4), 4, 100, 1)
+    assert e.value.code == C.EINVAL
+
+
+def test_right_and_left_looking_agree_bit_for_bit():
+    # the update is exact, so a left-looking order (all earlier columns applied
+    # to column i just before it is factored) must give identical d, h, b
+    N, P, E = 40, 1024, 8
+    mu = _mu(Fraction(1, 2), N)
+    f = C.factor(mu, N, P, E)
+    s = C.scales(mu, N, E)
+    A = C.load(mu, N, P, s)
+    d, h, B, U = [], [], [], []
+    for i in range(N):
+        col = [A[r][i] if r >= i else None for r in range(N)]
+        for j in range(i):
+            for r in range(i, N):
+                col[r] -= B[j][r] * U[j][i]
+        di = col[i]
+        hi = di.bit_length() // 2
+        wi = C.rnd_div(1 << (2 * hi + P), di)
+        u = {r: C.rnd_shift(col[r], hi) for r in range(i + 1, N)}
+        b = {r: C.rnd_shift(u[r] * wi, P) for r in range(i + 1, N)}
+        u[i] = 0
+        d.append(di); h.append(hi); B.append(b); U.append(u)
+    assert d == f.d and h == f.h and B == f.b
+
+
+# ------------------------------------------------------------------ rounding helpers and planted mistakes
+
+def test_rounding_helpers_against_fractions():
+    import random
+    rng = random.Random(7)
+    for _ in range(2000):
+        a = rng.randrange(-(1 << 200), 1 << 200)
+        d = rng.randrange(1, 1 << 120)
+        q = C.rnd_div(a, d)
+        fr = Fraction(a, d)
+        assert abs(fr - q) <= Fraction(1, 2)
+        if abs(fr - q) == Fraction(1, 2):
+            assert abs(q) > abs(fr)            # ties away from zero
+        s = rng.randrange(1, 90)
+        q2 = C.rnd_shift(a, s)
+        fr2 = Fraction(a, 1 << s)
+        assert abs(fr2 - q2) <= Fraction(1, 2)
+        if abs(fr2 - q2) == Fraction(1, 2):
+            assert abs(q2) > abs(fr2)
+    assert C.rnd_shift(5, 1) == 3 and C.rnd_shift(-5, 1) == -3 and C.rnd_shift(3, -2) == 12
+
+
+@pytest.mark.parametrize("mutation", ["sign", "index", "no_scale"])
+def test_planted_mistakes_are_caught(monkeypatch, mutation):
+    """A copy of the factor loop with one plausible mistake must fail the
+    closed-form / exact-rational pins that the real oracle passes."""
+    N, P = 12, 1024
+    mu = _mu(1, N)
+    s = C.scales(mu, N, 4)
+    # "no_scale": one global binary point instead of the per-row scales
+    A = C.load(mu, N, P, s if mutation != "no_scale" else [max(s)] * N)
+    d = []
+    for i in range(N):
+        di = A[i][i]
+        if di <= 0:          # the mistake already broke positive definiteness
+            d.append(di)
+            break
+        hi = di.bit_length() // 2
+        wi = C.rnd_div(1 << (2 * hi + P), di)
+        u = {r: C.rnd_shift(A[r][i], hi) for r in range(i + 1, N)}
+        b = {r: C.rnd_shift(u[r] * wi, P) for r in range(i + 1, N)}
+        for c in range(i + 1, N):
+            for r in range(c, N):
+                if mutation == "sign":
+                    A[r][c] += b[r] * u[c]
+                elif mutation == "index":
+                    A[r][c] -= b[c] * u[c]
+                else:
+                    A[r][c] -= b[r] * u[c]
+        d.append(di)
+    W = 2 * P - 4
+    ok = all(d[m] == math.factorial(m) ** 2 << (W - 2 * C.scales(mu, N, 4)[m]) for m in range(N))
+    assert not ok
