@@ -1,0 +1,181 @@
+/*
+ * hl.h -- C ABI of libhankel: the smallest eigenvalue of the moment Hankel
+ * matrix H_N = (mu_{i+j}) of the weight exp(-x^beta) on [0, inf), by an
+ * extreme-precision LDL^T factorisation, the top-left k x k block of H_N^-1 and
+ * the largest eigenvalue of that block (Chen, Sikorowski, Zhu, "Smallest
+ * eigenvalue of large Hankel matrices at critical point", Sections 2 and 4).
+ *
+ * Plain C: no C++ types, no exceptions, no torch types.  Every pointer is either
+ * host memory or device (HIP) memory as stated; the library never allocates
+ * device memory after hl_create.  The caller owns every buffer.
+ *
+ * Numbers.  A "P-bit number" is nl = P/32 little-endian uint32 limbs in two's
+ * complement.  A "2P-bit number" is 2*nl limbs.  The precision P must be a
+ * multiple of 128 and at least 256.
+ *
+ * Scaled fixed point (Section 4.1, eq. precision, with the diagonal scaling of
+ * Section 6.2 restricted to powers of two).  Row j carries a scale exponent s_j
+ * shared by a block of E rows; the factorisation works on the integers
+ * a_rc = rnd(mu_{r+c} 2^(W - s_r - s_c)), W = 2P - 4, and returns
+ *   pivots       d_i  with  D_i  = d_i  2^(2 s_i - W),
+ *   multipliers  b_ri with  L_ri = b_ri 2^(s_r - s_i - h_i),
+ * where h_i = bitlen(d_i) / 2.  The update a_rc -= b_ri u_ci is exact; rounding
+ * (to nearest, ties away from zero) happens only at the load, at the two
+ * factor columns u, b of each pivot, at each entry of the first k columns of
+ * L^-1, and at the final block.  Results are deterministic: the same inputs give
+ * the same bits whatever the form (MFMA or VALU) or launch shape.
+ *
+ * Errors.  Calls are stream ordered and asynchronous unless stated.  Argument
+ * errors return immediately.  Errors found on the device (a pivot that is not
+ * positive, a factor that exceeds its P bits) are recorded in a status word in
+ * the workspace; every later kernel of the same workspace returns at once, and
+ * the status is returned by the next synchronising call (hl_sync,
+ * hl_lambda_min).
+ */
+#ifndef HL_H
+#define HL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HL_OK = 0,
+  HL_EINVAL = 1,    /* bad argument (sizes, null pointers, precision)            */
+  HL_ENOTPD = 2,    /* pivot d_i <= 0: precision too low or input not positive definite */
+  HL_EOVERFLOW = 3, /* a P-bit quantity reached 3 * 2^(P-3): head room exhausted   */
+  HL_ENOCONV = 4,   /* the eigen-step did not converge within its iteration limit */
+  HL_EHIP = 5,      /* a HIP runtime call failed                                  */
+  HL_ENOMEM = 6     /* a caller buffer is smaller than hl_get_sizes asks for      */
+} hl_status;
+
+enum { HL_FORM_MFMA8 = 0, HL_FORM_VALU = 1 };
+
+typedef struct hl_ctx hl_ctx;
+
+/* Problem shape. */
+typedef struct {
+  int32_t N;         /* order of H_N, 1 <= N <= 8192                                 */
+  int32_t k;         /* size of the top-left block of H_N^-1, 1 <= k <= min(N, 32)    */
+  int32_t prec_bits; /* P, multiple of 128, 256 <= P <= 65536                         */
+  int32_t exp_block; /* E, rows sharing one scale exponent, >= 1                      */
+  int32_t form;      /* HL_FORM_MFMA8: Schur update as exact int8 MFMA GEMMs;
+                        HL_FORM_VALU: limb products on the vector ALU               */
+} hl_shape;
+
+/* Buffer sizes for a shape (all counts in elements of the stated type). */
+typedef struct {
+  size_t workspace_bytes; /* device workspace for hl_factor / hl_inv_block / hl_lambda_min */
+  size_t d_words;         /* uint32: pivots, N x 2nl                                     */
+  size_t l_words;         /* uint32: multipliers, N x NT x nl                            */
+  size_t x_words;         /* uint32: first k columns of L^-1, NT x k x nl                */
+  size_t blk_words;       /* uint32: block, k x k x nl                                   */
+  int32_t nl;             /* limbs per P-bit number                                      */
+  int32_t NT;             /* N rounded up to a multiple of 32                            */
+  int32_t mu_limbs_min;   /* not used (moments may have any width w >= 1)                */
+  int32_t reserved;
+} hl_sizes;
+
+/* Device views of the factorisation, all owned by the caller. */
+typedef struct {
+  uint32_t *d; /* device, N x 2nl limbs: pivot d_i at d + i*2nl                        */
+  int32_t *h;  /* device, N: h_i = bitlen(d_i) / 2                                       */
+  int32_t *s;  /* device, N: row scale exponents s_j                                     */
+  uint32_t *l; /* device, N x NT x nl limbs: b_ri at l + (i*NT + r)*nl, two's
+                  complement; entries with r <= i or r >= N are zero                    */
+} hl_factor_t;
+
+/* Result of the eigen-step (host). */
+typedef struct {
+  double lambda1;     /* 1 / lambda_max(k x k block of H^-1), rounded to double          */
+  double lambda1_km1; /* the same from the leading (k-1) x (k-1) block (k >= 2)          */
+  double trunc;       /* lambda1 - lambda1_km1 (<= 0), the truncation-error estimate     */
+  int64_t exp;        /* lambda1 = lam_mant * 2^exp (lam_mant: nl limbs, unsigned)       */
+  int64_t exp_km1;    /* lambda1_km1 = lam_mant_km1 * 2^exp_km1                          */
+  int32_t iterations; /* eigen-step iterations used (both blocks)                        */
+  int32_t reserved;
+} hl_lambda_t;
+
+/* Context: selects the device and holds timers.  Not thread safe. */
+hl_status hl_create(hl_ctx **ctx, int device);
+hl_status hl_destroy(hl_ctx *ctx);
+
+/* Human-readable detail of the last non-OK status of this thread. */
+const char *hl_last_error(void);
+
+/* Sizes of every buffer for a shape; EINVAL if the shape is not supported. */
+hl_status hl_get_sizes(const hl_shape *sh, hl_sizes *out);
+
+/*
+ * hl_factor -- Algorithm 1 (serial LDL^T, no pivoting, Section 4.3) of the
+ * scaled Hankel matrix, blocked in panels of 16 columns.
+ *   mu      device, (2N-1) x w uint32 limbs: mantissa M_m of moment m (unsigned)
+ *   mu_exp  device, 2N-1 int64: mu_m = M_m * 2^mu_exp[m]; every M_m must be > 0
+ *   ws      device workspace of at least hl_sizes.workspace_bytes; it carries the
+ *           status word and must be passed unchanged to hl_inv_block and
+ *           hl_lambda_min of the same factorisation
+ *   out     device views, sized by hl_get_sizes
+ *   stream  hipStream_t (NULL: the null stream)
+ * Device errors: HL_ENOTPD (index = pivot), HL_EOVERFLOW (index = column).
+ */
+hl_status hl_factor(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, const int64_t *mu_exp,
+                    int32_t w, void *ws, size_t ws_bytes, const hl_factor_t *out, void *stream);
+
+/*
+ * hl_inv_block -- first k columns of L^-1 (Algorithm 4, Section 4.4) and the
+ * top-left k x k block of H^-1 (eq. equ:index, Section 4.5).
+ *   x        device, NT x k x nl limbs: x_rm at x + (r*k + m)*nl, the scaled
+ *            entries of L^-1 (x_mm = 2^(Q - h_m), Q = W - G, G = max_{m<k} s_m + 64)
+ *   blk      device, k x k x nl limbs: (H^-1)_ab ~= blk_ab * 2^blk_exp, |blk_ab| <= 2^(P-2)
+ *   blk_exp  device, 1 int64
+ * Device errors: HL_EOVERFLOW (index = row of L^-1).
+ */
+hl_status hl_inv_block(hl_ctx *ctx, const hl_shape *sh, const hl_factor_t *f, void *ws,
+                       size_t ws_bytes, uint32_t *x, uint32_t *blk, int64_t *blk_exp, void *stream);
+
+/*
+ * hl_lambda_min -- lambda_1 ~= 1 / lambda_max(block), and the same from the
+ * leading (k-1) x (k-1) block for the truncation estimate (Sections 4.2 and 4.5),
+ * by shifted inverse iteration with Rayleigh quotients in multiprecision
+ * floating point, every shift certified by the signs of an LDL^T.  Synchronises
+ * the stream; returns the first device error of the workspace if there is one.
+ *   lam_mant, lam_mant_km1  optional device outputs, nl limbs each (NULL: skip)
+ *   out                     host
+ */
+hl_status hl_lambda_min(hl_ctx *ctx, const hl_shape *sh, const uint32_t *blk, const int64_t *blk_exp,
+                        void *ws, size_t ws_bytes, uint32_t *lam_mant, uint32_t *lam_mant_km1,
+                        hl_lambda_t *out, void *stream);
+
+/* Wait for the stream and return the status word of the workspace (index of
+ * the failing pivot or column in *index if not NULL). */
+hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
+
+/* Per-stage device time of the last hl_factor / hl_inv_block / hl_lambda_min on
+ * this context, measured with HIP events on the caller's stream when timing is
+ * enabled (hl_set_timing(ctx, 1)).  ms[0] Schur update, ms[1] panel (pivots,
+ * factor columns, in-panel updates), ms[2] triangular solve, ms[3] block,
+ * ms[4] eigen-step, ms[5] load; launches[0] = Schur-update launches. */
+typedef struct {
+  double ms[8];
+  int64_t launches[4];
+  double schur_limb_macs; /* algorithmic limb multiply-adds of the Schur updates */
+} hl_timing_t;
+hl_status hl_set_timing(hl_ctx *ctx, int enable);
+hl_status hl_get_timing(hl_ctx *ctx, hl_timing_t *out);
+
+/* Test hooks (not part of the method): exact products and the pivot
+ * reciprocal on the device, for checking the multi-limb primitives against
+ * host integers. */
+hl_status hl_debug_mul(const uint32_t *a, int32_t na, const uint32_t *b, int32_t nb, uint32_t *out,
+                       int32_t nout, void *stream);
+hl_status hl_debug_recip(const uint32_t *d, int32_t nd, int32_t P, uint32_t *omega, int32_t *h,
+                         void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HL_H */

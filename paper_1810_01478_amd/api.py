@@ -1,0 +1,238 @@
+"""Python front end of libhankel: torch supplies device memory and the stream,
+the library does all the arithmetic.
+
+    ctx = Context()
+    fac = ctx.factor(moments(Fraction(1, 2), 127), N=64, k=8, P=2048)
+    res = ctx.lambda_min(fac)          # factor -> block -> eigen-step
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+from fractions import Fraction
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from hankel_inputs import moments as _moments, pack_limbs, unpack_limbs
+
+from . import _lib as L
+
+FORMS = {"mfma": L.HL_FORM_MFMA8, "mfma8": L.HL_FORM_MFMA8, "valu": L.HL_FORM_VALU}
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _u32_tensor(arr: np.ndarray, device) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.uint32).view(np.int32)).to(device)
+
+
+def _ints(t: torch.Tensor, limbs: int, signed: bool) -> List[int]:
+    a = t.detach().cpu().numpy().view(np.uint32).reshape(-1, limbs)
+    return unpack_limbs(a, signed=signed)
+
+
+@dataclass
+class Factorization:
+    shape: L.hl_shape
+    sizes: L.hl_sizes
+    ws: torch.Tensor
+    d: torch.Tensor
+    h: torch.Tensor
+    s: torch.Tensor
+    l: torch.Tensor
+    x: Optional[torch.Tensor] = None
+    blk: Optional[torch.Tensor] = None
+    blk_exp: Optional[torch.Tensor] = None
+    views: L.hl_factor_t = field(default_factory=L.hl_factor_t)
+
+    @property
+    def N(self):
+        return self.shape.N
+
+    @property
+    def nl(self):
+        return self.sizes.nl
+
+    @property
+    def NT(self):
+        return self.sizes.NT
+
+    # host views for checks ---------------------------------------------------
+    def pivots(self) -> List[int]:
+        return _ints(self.d, 2 * self.nl, signed=True)
+
+    def h_list(self) -> List[int]:
+        return self.h.cpu().tolist()
+
+    def s_list(self) -> List[int]:
+        return self.s.cpu().tolist()
+
+    def multipliers(self, i: int, rows: Optional[Sequence[int]] = None) -> List[int]:
+        """b_ri for the given rows (default: all rows r > i) of column i."""
+        nl, NT = self.nl, self.NT
+        col = self.l.view(-1)[i * NT * nl:(i + 1) * NT * nl]
+        vals = _ints(col, nl, signed=True)
+        if rows is None:
+            rows = range(i + 1, self.N)
+        return [vals[r] for r in rows]
+
+    def block(self):
+        k, nl = self.shape.k, self.nl
+        vals = _ints(self.blk, nl, signed=True)
+        return [vals[a * k:(a + 1) * k] for a in range(k)], int(self.blk_exp.cpu().item())
+
+    def linv(self):
+        k, nl = self.shape.k, self.nl
+        vals = _ints(self.x, nl, signed=True)
+        return [vals[r * k:(r + 1) * k] for r in range(self.N)]
+
+
+class Context:
+    """One device, one library context."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libhankel runs on gfx950 only")
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        L.check(L.lib().hl_create(ctypes.byref(h), device))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            L.lib().hl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------------
+    @staticmethod
+    def shape(N, k, P, E=16, form="mfma") -> L.hl_shape:
+        return L.hl_shape(N=N, k=k, prec_bits=P, exp_block=E, form=FORMS[form] if isinstance(form, str) else form)
+
+    @staticmethod
+    def sizes(sh: L.hl_shape) -> L.hl_sizes:
+        out = L.hl_sizes()
+        L.check(L.lib().hl_get_sizes(ctypes.byref(sh), ctypes.byref(out)))
+        return out
+
+    def pack_moments(self, mu):
+        mants = [m.M for m in mu]
+        if any(v <= 0 for v in mants):
+            raise ValueError("moments must be positive")
+        w = max(1, max((v.bit_length() + 31) // 32 for v in mants))
+        limbs = _u32_tensor(pack_limbs(mants, w), self.device)
+        exps = torch.tensor([m.e for m in mu], dtype=torch.int64, device=self.device)
+        return limbs, exps, w
+
+    def alloc(self, sh: L.hl_shape) -> Factorization:
+        sz = self.sizes(sh)
+        dev = self.device
+        ws = torch.empty(sz.workspace_bytes, dtype=torch.uint8, device=dev)
+        d = torch.empty(sz.d_words, dtype=torch.int32, device=dev)
+        h = torch.empty(sh.N, dtype=torch.int32, device=dev)
+        s = torch.empty(sh.N, dtype=torch.int32, device=dev)
+        l = torch.empty(sz.l_words, dtype=torch.int32, device=dev)
+        f = Factorization(shape=sh, sizes=sz, ws=ws, d=d, h=h, s=s, l=l)
+        f.views = L.hl_factor_t(d=d.data_ptr(), h=h.data_ptr(), s=s.data_ptr(), l=l.data_ptr())
+        f.x = torch.empty(max(1, sz.x_words), dtype=torch.int32, device=dev)
+        f.blk = torch.empty(max(1, sz.blk_words), dtype=torch.int32, device=dev)
+        f.blk_exp = torch.zeros(1, dtype=torch.int64, device=dev)
+        return f
+
+    def factor(self, mu, N, k, P, E=16, form="mfma", fac: Optional[Factorization] = None,
+               packed=None, stream=None) -> Factorization:
+        sh = self.shape(N, k, P, E, form)
+        if fac is None:
+            fac = self.alloc(sh)
+        limbs, exps, w = packed if packed is not None else self.pack_moments(mu[:2 * N - 1])
+        fac._mu = (limbs, exps, w)
+        L.check(L.lib().hl_factor(self.h, ctypes.byref(sh), _ptr(limbs), _ptr(exps), w, _ptr(fac.ws),
+                                  fac.ws.numel(), ctypes.byref(fac.views), _stream(stream)))
+        return fac
+
+    def sync(self, fac: Factorization, stream=None):
+        idx = ctypes.c_int32(0)
+        code = L.lib().hl_sync(self.h, _ptr(fac.ws), _stream(stream), ctypes.byref(idx))
+        if code != L.HL_OK:
+            raise L.HLError(code, L.lib().hl_last_error().decode() + " (index %d)" % idx.value)
+
+    def inv_block(self, fac: Factorization, stream=None) -> Factorization:
+        L.check(L.lib().hl_inv_block(self.h, ctypes.byref(fac.shape), ctypes.byref(fac.views), _ptr(fac.ws),
+                                     fac.ws.numel(), _ptr(fac.x), _ptr(fac.blk), _ptr(fac.blk_exp),
+                                     _stream(stream)))
+        return fac
+
+    def eigen(self, fac: Factorization, want_mant=True, stream=None):
+        out = L.hl_lambda_t()
+        nl = fac.nl
+        m1 = torch.zeros(nl, dtype=torch.int32, device=self.device) if want_mant else None
+        m2 = torch.zeros(nl, dtype=torch.int32, device=self.device) if want_mant else None
+        code = L.lib().hl_lambda_min(self.h, ctypes.byref(fac.shape), _ptr(fac.blk), _ptr(fac.blk_exp),
+                                     _ptr(fac.ws), fac.ws.numel(),
+                                     _ptr(m1) if m1 is not None else None,
+                                     _ptr(m2) if m2 is not None else None,
+                                     ctypes.byref(out), _stream(stream))
+        if code != L.HL_OK:
+            raise L.HLError(code, L.lib().hl_last_error().decode())
+        res = {"lambda1": out.lambda1, "lambda1_km1": out.lambda1_km1, "trunc": out.trunc,
+               "exp": out.exp, "exp_km1": out.exp_km1, "iterations": out.iterations}
+        if want_mant:
+            res["mant"] = _ints(m1, nl, signed=False)[0]
+            res["mant_km1"] = _ints(m2, nl, signed=False)[0]
+        return res
+
+    def lambda_min(self, fac: Factorization, stream=None):
+        self.inv_block(fac, stream)
+        return self.eigen(fac, stream=stream)
+
+    # timing ------------------------------------------------------------------
+    def set_timing(self, on: bool):
+        L.check(L.lib().hl_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        t = L.hl_timing_t()
+        L.check(L.lib().hl_get_timing(self.h, ctypes.byref(t)))
+        return {"ms": list(t.ms), "launches": list(t.launches), "schur_limb_macs": t.schur_limb_macs}
+
+    # test hooks ----------------------------------------------------------------
+    def debug_mul(self, a: int, b: int, na: int, nb: int, nout: int) -> int:
+        A = _u32_tensor(pack_limbs([a], na), self.device)
+        B = _u32_tensor(pack_limbs([b], nb), self.device)
+        O = torch.zeros(nout, dtype=torch.int32, device=self.device)
+        L.check(L.lib().hl_debug_mul(_ptr(A), na, _ptr(B), nb, _ptr(O), nout, _stream()))
+        torch.cuda.synchronize()
+        return _ints(O, nout, signed=False)[0]
+
+    def debug_recip(self, d: int, P: int):
+        nl = P // 32
+        nd = max(1, (d.bit_length() + 31) // 32)
+        D = _u32_tensor(pack_limbs([d], nd), self.device)
+        O = torch.zeros(nl + 4, dtype=torch.int32, device=self.device)
+        H = torch.zeros(1, dtype=torch.int32, device=self.device)
+        L.check(L.lib().hl_debug_recip(_ptr(D), nd, P, _ptr(O), _ptr(H), _stream()))
+        torch.cuda.synchronize()
+        return _ints(O, nl + 4, signed=False)[0], int(H.cpu().item())
+
+
+def lambda_min(beta, N: int, k: int, P: int, E: int = 16, form: str = "mfma", mant_bits: int = 0,
+               ctx: Optional[Context] = None):
+    """lambda_1 of H_N for the weight exp(-x^beta), end to end on the GPU."""
+    ctx = ctx or Context()
+    mu = _moments(beta, 2 * N - 1, mant_bits=mant_bits or 2 * P)
+    fac = ctx.factor(mu, N, k, P, E, form)
+    return ctx.lambda_min(fac)

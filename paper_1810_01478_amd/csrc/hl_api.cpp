@@ -1,0 +1,323 @@
+// C ABI of libhankel: argument checking, workspace layout and the launch
+// sequence of the path (load -> panels of Algorithm 1 -> Algorithm 4 -> block ->
+// eigen-step).  All device memory is the caller's.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hl_kernels.hpp"
+#include "hl_host.hpp"
+
+using namespace hl;
+
+struct hl_ctx {
+  int device = 0;
+  int timing = 0;
+  hl_timing_t t{};
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+};
+
+static thread_local std::string g_err;
+
+namespace hl {
+hl_status fail(hl_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+}  // namespace hl
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) return fail(HL_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* hl_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// shape -> dims and workspace layout
+namespace hl {
+
+hl_status make_dims(const hl_shape* sh, Dims* dm) {
+  if (!sh) return fail(HL_EINVAL, "null shape");
+  if (sh->N < 1 || sh->N > 8192) return fail(HL_EINVAL, "N=%d out of range [1, 8192]", sh->N);
+  if (sh->k < 1 || sh->k > sh->N || sh->k > 32) return fail(HL_EINVAL, "k=%d out of range", sh->k);
+  if (sh->prec_bits % 128 || sh->prec_bits < 256 || sh->prec_bits > kMaxPrec)
+    return fail(HL_EINVAL, "prec_bits=%d must be a multiple of 128 in [256, %d]", sh->prec_bits, kMaxPrec);
+  if (sh->exp_block < 1) return fail(HL_EINVAL, "exp_block must be >= 1");
+  if (sh->form != HL_FORM_MFMA8 && sh->form != HL_FORM_VALU) return fail(HL_EINVAL, "bad form");
+  dm->N = sh->N;
+  dm->NT = (sh->N + 31) / 32 * 32;
+  dm->nt = dm->NT / 32;
+  dm->P = sh->prec_bits;
+  dm->nl = sh->prec_bits / 32;
+  dm->nw = 2 * dm->nl;
+  dm->S = 4 * dm->nl;
+  dm->E = sh->exp_block;
+  dm->k = sh->k;
+  dm->W = 2 * sh->prec_bits - 4;
+  return HL_OK;
+}
+
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout make_layout(const Dims& dm) {
+  Layout L{};
+  size_t off = 0;
+  L.status = off;
+  off += 256;
+  L.tiles = off;
+  off += al((size_t)dm.nt * (dm.nt + 1) / 2 * tile_words(dm.nw) * 4);
+  L.upanel = off;
+  off += al((size_t)16 * dm.NT * dm.nl * 4);
+  L.omega_stride = dm.nl + 4;
+  L.omega = off;
+  off += al((size_t)dm.N * L.omega_stride * 4);
+  // int8 digit panels for the MFMA form, padded by kDigitPad slices at both ends
+  L.digit_slices = dm.S + 2 * kDigitPad;
+  L.bdig = off;
+  off += al((size_t)L.digit_slices * dm.NT * 16);
+  L.udig = off;
+  off += al((size_t)L.digit_slices * dm.NT * 16);
+  L.carry = off;
+  off += al((size_t)kMaxRanges * dm.nt * (dm.nt + 1) / 2 * 1024 * 8);
+  // block: per pair and row chunk partial sums of 3nl + 8 limbs
+  const int npairs = dm.k * (dm.k + 1) / 2;
+  L.blk_stride = 3 * dm.nl + 16;
+  L.blk_chunks = (dm.N + kBlockRows - 1) / kBlockRows;
+  L.blk_part = off;
+  off += al((size_t)npairs * L.blk_chunks * L.blk_stride * 4);
+  L.blk_sum = off;
+  off += al((size_t)npairs * (L.blk_stride + 64) * 4);
+  L.eig = off;
+  off += al(eig_ws_bytes(dm));
+  L.total = off;
+  return L;
+}
+
+}  // namespace hl
+
+extern "C" hl_status hl_get_sizes(const hl_shape* sh, hl_sizes* out) {
+  Dims dm;
+  hl_status s = make_dims(sh, &dm);
+  if (s != HL_OK) return s;
+  if (!out) return fail(HL_EINVAL, "null output");
+  Layout L = make_layout(dm);
+  memset(out, 0, sizeof *out);
+  out->workspace_bytes = L.total;
+  out->d_words = (size_t)dm.N * dm.nw;
+  out->l_words = (size_t)dm.N * dm.NT * dm.nl;
+  out->x_words = (size_t)dm.NT * dm.k * dm.nl;
+  out->blk_words = (size_t)dm.k * dm.k * dm.nl;
+  out->nl = dm.nl;
+  out->NT = dm.NT;
+  return HL_OK;
+}
+
+extern "C" hl_status hl_create(hl_ctx** ctx, int device) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(HL_EINVAL, "device %d of %d", device, n);
+  HIPCHK(hipSetDevice(device));
+  hl_ctx* c = new hl_ctx();
+  c->device = device;
+  *ctx = c;
+  return HL_OK;
+}
+
+extern "C" hl_status hl_destroy(hl_ctx* ctx) {
+  if (!ctx) return HL_OK;
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return HL_OK;
+}
+
+extern "C" hl_status hl_set_timing(hl_ctx* ctx, int enable) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  ctx->timing = enable;
+  return HL_OK;
+}
+
+extern "C" hl_status hl_get_timing(hl_ctx* ctx, hl_timing_t* out) {
+  if (!ctx || !out) return fail(HL_EINVAL, "null argument");
+  *out = ctx->t;
+  return HL_OK;
+}
+
+// event helpers: pairs recorded around stages, summed at the next sync
+namespace hl {
+struct Stamp {
+  hl_ctx* ctx;
+  hipStream_t s;
+  int slot;
+  hipEvent_t a = nullptr, b = nullptr;
+  Stamp(hl_ctx* c, hipStream_t st, int sl) : ctx(c), s(st), slot(sl) {
+    if (!ctx->timing) return;
+    if (ctx->used + 2 > ctx->pool.size()) {
+      for (int j = 0; j < 64; ++j) {
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        ctx->pool.push_back(e);
+      }
+    }
+    a = ctx->pool[ctx->used++];
+    b = ctx->pool[ctx->used++];
+    (void)hipEventRecord(a, s);
+  }
+  void end() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    ctx->t.ms[slot] += ms;
+    ctx->used -= 2;
+    a = nullptr;
+  }
+};
+}  // namespace hl
+
+static hl_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(HL_EINVAL, "null workspace");
+  if (ws_bytes < L.total) return fail(HL_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  return HL_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* mu, const int64_t* mu_exp,
+                               int32_t w, void* ws, size_t ws_bytes, const hl_factor_t* out, void* stream) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  Dims dm;
+  hl_status s = make_dims(sh, &dm);
+  if (s != HL_OK) return s;
+  if (!mu || !mu_exp || w < 1) return fail(HL_EINVAL, "bad moments");
+  if (!out || !out->d || !out->h || !out->s || !out->l) return fail(HL_EINVAL, "null factor output");
+  Layout L = make_layout(dm);
+  if ((s = check_ws(L, ws, ws_bytes)) != HL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  DevStatus* dst = (DevStatus*)(base + L.status);
+  u32* A = (u32*)(base + L.tiles);
+  u32* up = (u32*)(base + L.upanel);
+  u32* omega = (u32*)(base + L.omega);
+  ctx->t = hl_timing_t{};
+
+  Stamp total(ctx, st, 7);
+  Stamp ld(ctx, st, 5);
+  HIPCHK(launch_fill((u32*)dst, 64, 0u, st));
+  HIPCHK(launch_fill(out->l, (size_t)dm.N * dm.NT * dm.nl, 0u, st));
+  HIPCHK(launch_scales(mu, mu_exp, w, dm.N, dm.E, out->s, dst, st));
+  HIPCHK(launch_load(mu, mu_exp, w, out->s, dm, A, dst, st));
+  ld.end();
+
+  const size_t ldb = (size_t)dm.NT * dm.nl;
+  for (int i0 = 0; i0 < dm.N; i0 += 16) {
+    const int npan = dm.N - i0 < 16 ? dm.N - i0 : 16;
+    Stamp pn(ctx, st, 1);
+    for (int il = 0; il < npan; ++il) {
+      const int i = i0 + il;
+      HIPCHK(launch_pivot(A, dm, i, out->d, out->h, omega, L.omega_stride, dst, st));
+      HIPCHK(launch_col(A, dm, i, i0, out->h, omega, L.omega_stride, up + (size_t)il * ldb,
+                        out->l + (size_t)i * ldb, dst, st));
+      if (il + 1 < npan) {
+        UpdArgs g{};
+        g.A = A;
+        g.tri = 1;
+        g.nw = dm.nw;
+        g.nl = dm.nl;
+        g.Bop = out->l + (size_t)i * ldb;
+        g.ldb = ldb;
+        g.Uop = up + (size_t)il * ldb;
+        g.ldu = ldb;
+        g.npan = 1;
+        g.r_lo = i + 1;
+        g.r_hi = dm.N;
+        g.c_lo = i + 1;
+        g.c_hi = i0 + npan;
+        g.st = dst;
+        HIPCHK(launch_upd_valu(g, st));
+      }
+    }
+    pn.end();
+    if (i0 + npan < dm.N) {
+      Stamp su(ctx, st, 0);
+      UpdArgs g{};
+      g.A = A;
+      g.tri = 1;
+      g.nw = dm.nw;
+      g.nl = dm.nl;
+      g.Bop = out->l + (size_t)i0 * ldb;
+      g.ldb = ldb;
+      g.Uop = up;
+      g.ldu = ldb;
+      g.npan = npan;
+      g.r_lo = i0 + npan;
+      g.r_hi = dm.N;
+      g.c_lo = i0 + npan;
+      g.c_hi = dm.N;
+      g.st = dst;
+      hipError_t e;
+      if (sh->form == HL_FORM_MFMA8) {
+        MfmaArgs m{};
+        m.g = g;
+        m.bdig = (int8_t*)(base + L.bdig);
+        m.udig = (int8_t*)(base + L.udig);
+        m.slices = L.digit_slices;
+        m.pad = kDigitPad;
+        m.S = dm.S;
+        m.NT = dm.NT;
+        m.carry = (long long*)(base + L.carry);
+        m.max_ranges = kMaxRanges;
+        e = launch_upd_mfma(m, st);
+      } else {
+        e = launch_upd_valu(g, st);
+      }
+      HIPCHK(e);
+      ctx->t.launches[0] += 1;
+      const double rows = dm.N - (i0 + npan);
+      ctx->t.schur_limb_macs += (double)npan * rows * (rows + 1) / 2 * (double)dm.nl * dm.nl;
+      su.end();
+    }
+  }
+  total.end();
+  return HL_OK;
+}
+
+extern "C" hl_status hl_sync(hl_ctx* ctx, void* ws, void* stream, int32_t* index) {
+  if (!ctx || !ws) return fail(HL_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  unsigned long long v = 0;
+  HIPCHK(hipMemcpy(&v, ws, 8, hipMemcpyDeviceToHost));
+  const int code = (int)(v >> 32);
+  const int idx = (int)(v & 0xffffffffu);
+  if (index) *index = idx;
+  if (code) return fail((hl_status)code, "device status %d at index %d", code, idx);
+  return HL_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" hl_status hl_debug_mul(const uint32_t* a, int32_t na, const uint32_t* b, int32_t nb, uint32_t* out,
+                                  int32_t nout, void* stream) {
+  if (!a || !b || !out || na < 1 || nb < 1 || nout < 1) return fail(HL_EINVAL, "bad debug_mul args");
+  HIPCHK(launch_debug_mul(a, na, b, nb, out, nout, (hipStream_t)stream));
+  return HL_OK;
+}
+
+extern "C" hl_status hl_debug_recip(const uint32_t* d, int32_t nd, int32_t P, uint32_t* omega, int32_t* h,
+                                    void* stream) {
+  if (!d || !omega || !h || P % 128 || P < 256 || P > kMaxPrec || nd < 1 || nd > 2 * (P / 32))
+    return fail(HL_EINVAL, "bad debug_recip args");
+  HIPCHK(launch_debug_recip(d, nd, P, omega, P / 32 + 4, h, (hipStream_t)stream));
+  return HL_OK;
+}

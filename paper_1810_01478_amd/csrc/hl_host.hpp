@@ -1,0 +1,26 @@
+// Host-side constants and the workspace layout.
+#pragma once
+#include <stddef.h>
+#include "hl_internal.hpp"
+
+namespace hl {
+
+constexpr int kMaxPrec = 57344;   // pivot kernel keeps ~9 (P/32 + 8) words in LDS
+constexpr int kDigitPad = 32;     // zero digit slices below 0 and above S-1
+constexpr int kMaxRanges = 16;    // output-limb ranges per tile in the MFMA update
+constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
+
+struct Layout {
+  size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
+  int omega_stride;
+  int digit_slices;
+  int blk_stride;
+  int blk_chunks;
+};
+
+hl_status fail(hl_status s, const char* fmt, ...);
+hl_status make_dims(const hl_shape* sh, Dims* dm);
+Layout make_layout(const Dims& dm);
+size_t eig_ws_bytes(const Dims& dm);
+
+}  // namespace hl

@@ -1,0 +1,43 @@
+// Kernel launchers shared between the kernel files and the host API.
+#pragma once
+#include <climits>
+#include "mp.hpp"
+#include "hl_internal.hpp"
+
+namespace hl {
+
+size_t pivot_lds_bytes(int nl);
+size_t col_lds_bytes(int nl);
+
+hipError_t launch_scales(const u32* mu, const i64* mu_exp, int w, int N, int E, i32* s, DevStatus* st,
+                         hipStream_t stream);
+hipError_t launch_load(const u32* mu, const i64* mu_exp, int w, const i32* s, const Dims& dm, u32* A,
+                       DevStatus* st, hipStream_t stream);
+hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
+                        DevStatus* st, hipStream_t stream);
+hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
+                      int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
+hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream);
+hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout,
+                            hipStream_t stream);
+hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_omega, i32* h,
+                              hipStream_t stream);
+
+// exact update A[r][c] -= sum_i b_ri u_ci on the vector ALU
+hipError_t launch_upd_valu(const UpdArgs& g, hipStream_t stream);
+
+}  // namespace hl
+
+namespace hl {
+// exact update with int8-digit MFMA GEMMs
+struct MfmaArgs {
+  UpdArgs g;
+  int8_t* bdig;       // [slices][NT][16] digits of b (slice index = digit + pad)
+  int8_t* udig;       // [slices][NT][16] digits of u
+  int slices, pad, S, NT;
+  long long* carry;   // per (tile, range, entry) carries between limb ranges
+  int max_ranges;
+};
+hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream);
+size_t eig_ws_bytes_impl(int nl, int k);
+}  // namespace hl

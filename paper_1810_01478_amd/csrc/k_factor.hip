@@ -1,0 +1,431 @@
+// Load of the scaled Hankel matrix and the per-pivot steps of Algorithm 1
+// (serial LDL^T, Section 4.3): the pivot, its rounded reciprocal, and the two
+// factor columns u (the paper's A_i[j], cut to P bits) and b (the paper's
+// B_i[k] = A_i[k] / A_i[i], scaled by 2^h_i).
+#include "hl_kernels.hpp"
+
+namespace hl {
+
+// ---------------------------------------------------------------------------
+// Row scale exponents: s_j = ceil(t_J / 2), t_J = max_{j in J} bitlen(mu_2j),
+// for blocks J of E rows (power-of-two form of the diagonal preconditioner of
+// Section 6.2).
+__global__ void k_scales(const u32* __restrict__ mu, const i64* __restrict__ mu_exp, int w, int N,
+                         int E, i32* __restrict__ s_out, DevStatus* st) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nJ = (N + E - 1) / E;
+  if (J >= nJ) return;
+  long tJ = LONG_MIN;
+  const int j1 = min(N, J * E + E);
+  for (int j = J * E; j < j1; ++j) {
+    const u32* m = mu + (size_t)(2 * j) * w;
+    int top = w - 1;
+    while (top >= 0 && m[top] == 0) --top;
+    if (top < 0) {
+      set_status(st, HL_EINVAL, 2 * j);
+      return;
+    }
+    const long bl = (long)top * 32 + (32 - __clz((int)m[top])) + mu_exp[2 * j];
+    tJ = bl > tJ ? bl : tJ;
+  }
+  const long sJ = -((-tJ) >> 1);  // ceil(tJ / 2), arithmetic shift floors
+  for (int j = J * E; j < j1; ++j) s_out[j] = (i32)sJ;
+}
+
+// ---------------------------------------------------------------------------
+// a_rc = rnd(mu_{r+c} 2^(W - s_r - s_c)) for r >= c (Section 2, eq. matrix);
+// entries outside the N x N matrix are zero.  One thread per tile entry.
+__global__ void k_load(const u32* __restrict__ mu, const i64* __restrict__ mu_exp, int w,
+                       const i32* __restrict__ s, Dims dm, u32* __restrict__ A, DevStatus* st) {
+  const size_t t = blockIdx.x;
+  // invert t = R (R + 1) / 2 + C by bisection on R
+  int lo = 0, hi = dm.nt;  // R in [lo, hi)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if ((size_t)mid * (mid + 1) / 2 <= t) lo = mid; else hi = mid;
+  }
+  const int R = lo;
+  const int C = (int)(t - (size_t)R * (R + 1) / 2);
+  const int r = R * 32 + (threadIdx.x >> 5), c = C * 32 + (threadIdx.x & 31);
+  u32* base = A + t * tile_words(dm.nw);
+  const int nq = dm.nw / 4;
+  if (r >= dm.N || c >= dm.N || c > r) {
+    for (int q = 0; q < nq; ++q)
+      *(uint4*)(base + in_tile(r, c, 4 * q)) = make_uint4(0, 0, 0, 0);
+    return;
+  }
+  const int m = r + c;
+  const u32* M = mu + (size_t)m * w;
+  const long sig = mu_exp[m] + (long)dm.W - s[r] - s[c];
+  int top = w - 1;
+  while (top >= 0 && M[top] == 0) --top;
+  const long bl = top < 0 ? 0 : (long)top * 32 + (32 - __clz((int)M[top])) + sig;
+  if (bl > (long)dm.W + 1) {
+    set_status(st, HL_EOVERFLOW, r);
+    return;
+  }
+  u32 carry = 0;
+  if (sig < 0) carry = get_bit(M, w, -sig - 1);  // round half up (M >= 0)
+  for (int q = 0; q < nq; ++q) {
+    u32 v[4];
+    for (int j = 0; j < 4; ++j) {
+      const int l = 4 * q + j;
+      u32 x = sig >= 0 ? limb_shl(M, w, sig, l) : limb_shr(M, w, -sig, l);
+      u64 s2 = (u64)x + carry;
+      v[j] = (u32)s2;
+      carry = (u32)(s2 >> 32);
+    }
+    *(uint4*)(base + in_tile(r, c, 4 * q)) = make_uint4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pivot reciprocal.  For the pivot d (nw limbs in LDS, positive) computes
+//   h = bitlen(d) / 2, and w = rnd(2^(2h+P) / d~) where d~ is d cut to its top
+//   P + 64 bits: d~ = floor(d / 2^m), m = max(0, bitlen(d) - P - 64), and the
+//   power is lowered by m as well.
+// Newton's iteration y <- y + y (1 - delta y) for y ~ 1/delta, delta = d~ /
+// 2^bitlen(d~), with the working precision roughly doubled per step; the
+// quotient is then corrected to the exact floor with the remainder.
+// LDS needs 9 * (nl + 8) words (see pivot_lds_words).
+struct PivotOut {
+  int h;
+  int ok;
+};
+
+__device__ void sub_from_pow2(long e, const u32* T, int nT, u32* out, int n) {
+  // out = 2^e - T (mod 2^(32n)), T zero-extended from nT
+  u32 carry = 1;
+  for (int base = 0; base < n; base += WAVE) {
+    const int p = base + lane_id();
+    u64 v = 0;
+    if (p < n) {
+      u32 tp = p < nT ? T[p] : 0u;
+      v = (u64)(~tp);
+      if ((long)p == (e >> 5)) v += (u64)1 << (e & 31);
+    }
+    const u32 limb = w_resolve(v, carry);
+    if (p < n) out[p] = limb;
+  }
+}
+
+// x += d (two's complement add of a sign-extended small signed value), n limbs
+__device__ void add_i32(u32* x, int n, int d) {
+  u32 carry = 0;
+  const u32 ext = d < 0 ? 0xffffffffu : 0u;
+  for (int base = 0; base < n; base += WAVE) {
+    const int p = base + lane_id();
+    u64 v = 0;
+    if (p < n) v = (u64)x[p] + (p == 0 ? (u32)d : ext);
+    const u32 limb = w_resolve(v, carry);
+    if (p < n) x[p] = limb;
+  }
+}
+
+__device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_omega, u32* lds,
+                                int nl) {
+  PivotOut res{0, 1};
+  const int NB = nl + 8;
+  u32* D = lds;            // d~
+  u32* Y = D + NB;
+  u32* Yn = Y + NB;
+  u32* dq = Yn + NB;
+  u32* Z = dq + NB;
+  u32* T = Z + NB;         // 2 NB
+  u32* T2 = T + 2 * NB;    // 2 NB
+  const int Ld = w_bitlen(d, nw);
+  const int h = Ld / 2;
+  res.h = h;
+  const long m = Ld - (long)P - 64 > 0 ? Ld - (long)P - 64 : 0;
+  const int nd = nl + 2;
+  w_shift_right(d, nw, m, D, nd);
+  __syncthreads();
+  const int LD = w_bitlen(D, nd);
+  const long e = 2L * h + P - m;
+  const long pf = e - LD + 40;   // final precision of y
+  // initial 30-bit estimate from the top 32 bits of D
+  {
+    const u32 dtop = LD >= 32 ? limb_shr(D, nd, LD - 32, 0) : limb_shl(D, nd, 32 - LD, 0);
+    const u64 y0 = ((u64)1 << 62) / (u64)dtop;
+    if (lane_id() == 0) Y[0] = (u32)y0;
+    for (int p = 1 + lane_id(); p < NB; p += WAVE) Y[p] = 0;
+  }
+  __syncthreads();
+  long p = 30;
+  int ny = 1;
+  while (p < pf) {
+    long pn = 2 * p - 12;
+    if (pn > pf) pn = pf;
+    const long q = pn + 8;
+    const int nq = (int)(q / 32) + 2;
+    // dq = floor(D * 2^(q - LD))
+    w_shift_right(D, nd, LD - q, dq, nq);
+    __syncthreads();
+    // T = dq * Y
+    const int nT = nq + ny;
+    w_mul(dq, nq, Y, ny, T, nT);
+    __syncthreads();
+    // E = 2^(p+q) - T  (two's complement over nT + 1 limbs)
+    const int nE = nT + 1;
+    sub_from_pow2(p + q, T, nT, T, nE);
+    __syncthreads();
+    const bool neg = (T[nE - 1] >> 31) != 0;
+    if (neg) w_neg(T, nE);
+    __syncthreads();
+    // T2 = Y * |E|, then shifted
+    int ne = (w_bitlen(T, nE) + 31) / 32;
+    if (ne < 1) ne = 1;
+    if (ne > nq + 2) {  // |1 - delta y| is not small: the iteration has diverged
+      res.ok = 0;
+      break;
+    }
+    const int nT2 = ny + ne;
+    w_mul(Y, ny, T, ne, T2, nT2);
+    __syncthreads();
+    const int nyn = (int)((pn + 2) / 32) + 2;
+    // Yn = Y << (pn - p);   Z = T2 >> (2p + q - pn)
+    w_shift_right(Y, ny, -(pn - p), Yn, nyn);
+    w_shift_right(T2, nT2, 2 * p + q - pn, Z, nyn);
+    __syncthreads();
+    if (neg) {
+      w_sub(Yn, Z, Y, nyn);
+    } else {
+      w_add(Yn, nyn, Z, nyn, Y, nyn);
+    }
+    __syncthreads();
+    for (int j = nyn + lane_id(); j < NB; j += WAVE) Y[j] = 0;
+    ny = nyn;
+    p = pn;
+    __syncthreads();
+  }
+  // Z = Y >> (pf - (e - LD))  ~ 2^e / D
+  const int nz = nl + 3;
+  w_shift_right(Y, ny, pf - (e - LD), Z, nz);
+  __syncthreads();
+  // R = 2^e - Z D, exact, over nR limbs
+  const int nR = (int)(e / 32) + 3;
+  w_mul(Z, nz, D, nd, T, nR);
+  __syncthreads();
+  sub_from_pow2(e, T, nR, T, nR);
+  __syncthreads();
+  // T2 = D zero-extended to nR
+  for (int j = lane_id(); j < nR; j += WAVE) T2[j] = j < nd ? D[j] : 0u;
+  __syncthreads();
+  int guard = 0;
+  while (true) {
+    const bool rneg = (T[nR - 1] >> 31) != 0;
+    if (rneg) {
+      add_i32(Z, nz, -1);
+      __syncthreads();
+      w_add(T, nR, T2, nR, T, nR);
+      __syncthreads();
+    } else if (w_cmp(T, T2, nR) >= 0) {
+      add_i32(Z, nz, 1);
+      __syncthreads();
+      w_sub(T, T2, T, nR);
+      __syncthreads();
+    } else {
+      break;
+    }
+    if (++guard > 16) {
+      res.ok = 0;
+      break;
+    }
+  }
+  // omega = Z + [2R >= D]
+  w_shift_right(T, nR, -1, Yn, nR > NB ? NB : nR);  // 2R fits: R < D < 2^(P+64)
+  __syncthreads();
+  for (int j = nd + lane_id(); j < NB; j += WAVE) T2[j] = 0;
+  __syncthreads();
+  const bool up = w_cmp(Yn, T2, nd + 1) >= 0;
+  if (up) add_i32(Z, nz, 1);
+  __syncthreads();
+  for (int j = lane_id(); j < n_omega; j += WAVE) omega[j] = j < nz ? Z[j] : 0u;
+  __syncthreads();
+  return res;
+}
+
+// One wave: pivot i of the trailing matrix.
+__global__ __launch_bounds__(64) void k_pivot(u32* __restrict__ A, Dims dm, int i,
+                                              u32* __restrict__ d_out, i32* __restrict__ h_out,
+                                              u32* __restrict__ omega_tab, int omega_stride,
+                                              DevStatus* st) {
+  if (has_error(st)) return;
+  extern __shared__ u32 lds[];
+  const int nw = dm.nw, nl = dm.nl;
+  u32* dl = lds + 9 * (nl + 8);
+  const u32* src = A + tri_tile_index(i >> 5, i >> 5) * tile_words(nw);
+  for (int l = lane_id(); l < nw; l += WAVE) dl[l] = src[in_tile(i, i, l)];
+  __syncthreads();
+  const bool neg = (dl[nw - 1] >> 31) != 0;
+  if (neg || w_is_zero(dl, nw)) {
+    if (lane_id() == 0) set_status(st, HL_ENOTPD, i);
+    return;
+  }
+  for (int l = lane_id(); l < nw; l += WAVE) d_out[(size_t)i * nw + l] = dl[l];
+  PivotOut po = pivot_recip(dl, nw, dm.P, omega_tab + (size_t)i * omega_stride, omega_stride, lds, nl);
+  if (lane_id() == 0) {
+    h_out[i] = po.h;
+    if (!po.ok) set_status(st, HL_ENOCONV, i);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factor columns of pivot i for rows r in [r0, NT):
+//   u_r = rnd(a_ri / 2^h_i),  b_r = rnd(u_r w_i / 2^P),
+// both two's complement over nl limbs; rows r <= i and r >= N give zeros.
+// u goes to the panel buffer, b to the multiplier array L (column i).
+__global__ __launch_bounds__(64) void k_col(const u32* __restrict__ A, Dims dm, int i, int r0,
+                                            const i32* __restrict__ h_tab,
+                                            const u32* __restrict__ omega_tab, int omega_stride,
+                                            u32* __restrict__ u_out, u32* __restrict__ l_col,
+                                            DevStatus* st) {
+  if (has_error(st)) return;
+  const int r = r0 + blockIdx.x;
+  const int nl = dm.nl, nw = dm.nw;
+  u32* uo = u_out + (size_t)r * nl;
+  u32* bo = l_col + (size_t)r * nl;
+  if (r <= i || r >= dm.N) {
+    for (int l = lane_id(); l < nl; l += WAVE) {
+      uo[l] = 0;
+      bo[l] = 0;
+    }
+    return;
+  }
+  extern __shared__ u32 lds[];
+  u32* As = lds;                 // nw + 4
+  u32* Us = As + nw + 4;         // nl + 4
+  u32* Ws = Us + nl + 4;         // nl + 4
+  u32* Bs = Ws + nl + 4;         // nl + 4
+  const u32* src = A + tri_tile_index(r >> 5, i >> 5) * tile_words(nw);
+  for (int l = lane_id(); l < nw; l += WAVE) As[l] = src[in_tile(r, i, l)];
+  const u32* om = omega_tab + (size_t)i * omega_stride;
+  for (int l = lane_id(); l < nl + 4; l += WAVE) Ws[l] = l < omega_stride ? om[l] : 0u;
+  __syncthreads();
+  const bool neg = (As[nw - 1] >> 31) != 0;
+  if (neg) w_neg(As, nw);
+  __syncthreads();
+  const int h = h_tab[i];
+  if (h > 0) w_add_word(As, nw, (h - 1) >> 5, 1u << ((h - 1) & 31));
+  __syncthreads();
+  w_shift_right(As, nw, h, Us, nl + 1);
+  __syncthreads();
+  const u32 lim_top = 0x60000000u;  // 3 * 2^(P-3) in the top limb
+  if (Us[nl] != 0 || Us[nl - 1] >= lim_top) {
+    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
+    return;
+  }
+  // Bs = (Us * w + 2^(P-1)) >> P : limbs nl .. 2nl of the sum
+  const int nch = (2 * nl + 1 + WAVE - 1) / WAVE;
+  w_mul_stream(
+      Us, nl, Ws, nl + 1, nch,
+      [&](int ch, u32 limb) {
+        const int p = ch * WAVE + lane_id();
+        if (p >= nl && p <= 2 * nl) Bs[p - nl] = limb;
+      },
+      [&](int ch, u64& lo, u32& hi) {
+        const int t = ch * WAVE + lane_id();
+        if (t == nl - 1) {
+          const u64 s2 = lo + 0x80000000ull;
+          hi += (s2 < lo) ? 1u : 0u;
+          lo = s2;
+        }
+      });
+  __syncthreads();
+  if (Bs[nl] != 0 || Bs[nl - 1] >= lim_top) {
+    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
+    return;
+  }
+  if (neg) {
+    w_neg(Us, nl);
+    w_neg(Bs, nl);
+  }
+  __syncthreads();
+  for (int l = lane_id(); l < nl; l += WAVE) {
+    uo[l] = Us[l];
+    bo[l] = Bs[l];
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(u32* __restrict__ p, size_t n, u32 v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// test hooks
+__global__ __launch_bounds__(64) void k_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out,
+                                                  int nout) {
+  w_mul(a, na, b, nb, out, nout);
+}
+
+__global__ __launch_bounds__(64) void k_debug_recip(const u32* d, int nd, int P, int nl, u32* omega,
+                                                    int n_omega, i32* h) {
+  extern __shared__ u32 lds[];
+  u32* dl = lds + 9 * (nl + 8);
+  for (int l = lane_id(); l < 2 * nl; l += WAVE) dl[l] = l < nd ? d[l] : 0u;
+  __syncthreads();
+  PivotOut po = pivot_recip(dl, 2 * nl, P, omega, n_omega, lds, nl);
+  if (lane_id() == 0) h[0] = po.ok ? po.h : -1;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+size_t pivot_lds_bytes(int nl) { return (size_t)(9 * (nl + 8) + 2 * nl + 8) * 4; }
+size_t col_lds_bytes(int nl) { return (size_t)(2 * nl + 4 + 3 * (nl + 4)) * 4; }
+
+hipError_t launch_scales(const u32* mu, const i64* mu_exp, int w, int N, int E, i32* s, DevStatus* st,
+                         hipStream_t stream) {
+  const int nJ = (N + E - 1) / E;
+  hipLaunchKernelGGL(k_scales, dim3((nJ + 255) / 256), dim3(256), 0, stream, mu, mu_exp, w, N, E, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_load(const u32* mu, const i64* mu_exp, int w, const i32* s, const Dims& dm, u32* A,
+                       DevStatus* st, hipStream_t stream) {
+  const size_t ntiles = (size_t)dm.nt * (dm.nt + 1) / 2;
+  hipLaunchKernelGGL(k_load, dim3((unsigned)ntiles), dim3(1024), 0, stream, mu, mu_exp, w, s, dm, A, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
+                        DevStatus* st, hipStream_t stream) {
+  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(64), pivot_lds_bytes(dm.nl), stream, A, dm, i, d_out, h_out,
+                     omega, ostride, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
+                      int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream) {
+  const int nrows = dm.NT - r0;
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col, dim3(nrows), dim3(64), col_lds_bytes(dm.nl), stream, A, dm, i, r0, h, omega,
+                     ostride, u_out, l_col, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_debug_mul, dim3(1), dim3(64), 0, stream, a, na, b, nb, out, nout);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_omega, i32* h,
+                              hipStream_t stream) {
+  const int nl = P / 32;
+  hipLaunchKernelGGL(k_debug_recip, dim3(1), dim3(64), pivot_lds_bytes(nl), stream, d, nd, P, nl, omega,
+                     n_omega, h);
+  return hipGetLastError();
+}
+
+}  // namespace hl

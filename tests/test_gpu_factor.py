@@ -1,0 +1,96 @@
+"""GPU parity of hl_factor against the oracle: pivots d_i, balance exponents h_i,
+scales s_j and multipliers b_ri must be bit-exact (the contract is exact integer
+arithmetic with fixed rounding points)."""
+import math
+import random
+from fractions import Fraction
+
+import pytest
+
+from hankel_inputs import moments
+from oracle import contract as C
+
+from gpu_util import ctx, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("na,nb", [(1, 1), (3, 5), (64, 64), (65, 63), (200, 131), (512, 514)])
+def test_debug_mul_matches_host(na, nb):
+    say("debug_mul", na, nb)
+    rng = random.Random(na * 1000 + nb)
+    for _ in range(4):
+        a = rng.getrandbits(32 * na)
+        b = rng.getrandbits(32 * nb)
+        if rng.random() < 0.3:
+            a = (1 << (32 * na)) - 1
+            b = (1 << (32 * nb)) - 1
+        got = ctx().debug_mul(a, b, na, nb, na + nb)
+        assert got == a * b
+
+
+@pytest.mark.parametrize("P", [256, 2048, 8192])
+def test_debug_pivot_reciprocal(P):
+    say("debug_recip", P)
+    rng = random.Random(P)
+    for j in range(12):
+        bits = rng.randrange(2, 2 * P - 3)
+        d = rng.getrandbits(bits) | (1 << (bits - 1))
+        w, h = ctx().debug_recip(d, P)
+        hh, ww = C.pivot_reciprocal(d, P)
+        assert h == hh
+        assert w == ww, (bits, j)
+
+
+def _check_factor(fac, f, N):
+    assert fac.s_list() == f.s
+    assert fac.h_list() == f.h
+    piv = fac.pivots()
+    assert piv == f.d
+    for i in range(N - 1):
+        assert fac.multipliers(i) == [f.b[i][r] for r in range(i + 1, N)], i
+
+
+@pytest.mark.parametrize("beta,N,P,E,form", [
+    (Fraction(1, 2), 64, 2048, 16, "valu"),
+    (Fraction(1, 2), 80, 1024, 7, "valu"),
+    (Fraction(1, 3), 45, 1536, 1, "valu"),
+])
+def test_factor_bit_exact_vs_oracle(beta, N, P, E, form):
+    say("factor", beta, N, P, E, form)
+    mu = moments(beta, 2 * N - 1)
+    f = C.factor(mu, N, P, E)
+    fac = ctx().factor(mu, N, 8, P, E, form)
+    ctx().sync(fac)
+    _check_factor(fac, f, N)
+
+
+def test_beta1_pivots_closed_form_n128():
+    # D_m = (m!)^2 exactly: every intermediate is an integer, no rounding occurs
+    N, P = 128, 4096
+    say("beta1 closed form", N, P)
+    mu = moments(1, 2 * N - 1)
+    fac = ctx().factor(mu, N, 8, P, 16, "valu")
+    ctx().sync(fac)
+    s = fac.s_list()
+    W = 2 * P - 4
+    piv = fac.pivots()
+    for m in range(N):
+        assert piv[m] == math.factorial(m) ** 2 << (W - 2 * s[m]), m
+    h = fac.h_list()
+    for i in (0, 5, 63, 100):
+        got = fac.multipliers(i)
+        for r, v in zip(range(i + 1, N), got):
+            L = math.comb(r, i) * math.factorial(r) // math.factorial(i)
+            assert v == L << (s[i] + h[i] - s[r])
+
+
+def test_not_positive_definite_reports_pivot():
+    from hankel_inputs import Dyadic
+    from paper_1810_01478_amd._lib import HLError, HL_ENOTPD
+    mu = [Dyadic(4, 0), Dyadic(4, 0), Dyadic(3, 0), Dyadic(9, 0), Dyadic(30, 0)]
+    say("not PD")
+    fac = ctx().factor(mu, 3, 1, 256, 1, "valu")
+    with pytest.raises(HLError) as e:
+        ctx().sync(fac)
+    assert e.value.code == HL_ENOTPD and "index 1" in str(e.value)

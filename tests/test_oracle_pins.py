@@ -216,8 +216,7 @@ def test_right_and_left_looking_agree_bit_for_bit():
             for r in range(i, N):
                 col[r] -= B[j][r] * U[j][i]
         di = col[i]
-        hi = di.bit_length() // 2
-        wi = C.rnd_div(1 << (2 * hi + P), di)
+        hi, wi = C.pivot_reciprocal(di, P)
         u = {r: C.rnd_shift(col[r], hi) for r in range(i + 1, N)}
         b = {r: C.rnd_shift(u[r] * wi, P) for r in range(i + 1, N)}
         u[i] = 0
@@ -262,8 +261,7 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         if di <= 0:          # the mistake already broke positive definiteness
             d.append(di)
             break
-        hi = di.bit_length() // 2
-        wi = C.rnd_div(1 << (2 * hi + P), di)
+        hi, wi = C.pivot_reciprocal(di, P)
         u = {r: C.rnd_shift(A[r][i], hi) for r in range(i + 1, N)}
         b = {r: C.rnd_shift(u[r] * wi, P) for r in range(i + 1, N)}
         for c in range(i + 1, N):
@@ -278,3 +276,16 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
     W = 2 * P - 4
     ok = all(d[m] == math.factorial(m) ** 2 << (W - 2 * C.scales(mu, N, 4)[m]) for m in range(N))
     assert not ok
+
+
+def test_pivot_reciprocal_against_exact_quotient():
+    # the cut to P + 64 bits must leave w equal to the exactly rounded quotient
+    # except within 2^-60 of a tie; random pivots of 2P bits never hit one
+    import random
+    rng = random.Random(11)
+    for P in (256, 2048):
+        for _ in range(300):
+            d = rng.randrange(1 << (2 * P - 40), 1 << (2 * P - 4))
+            h, w = C.pivot_reciprocal(d, P)
+            assert w == C.rnd_div(1 << (2 * h + P), d)
+            assert (1 << (P - 1)) < w <= (1 << (P + 1))
