@@ -3,6 +3,7 @@
 // eigen-step).  All device memory is the caller's.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -319,5 +320,148 @@ extern "C" hl_status hl_debug_recip(const uint32_t* d, int32_t nd, int32_t P, ui
   if (!d || !omega || !h || P % 128 || P < 256 || P > kMaxPrec || nd < 1 || nd > 2 * (P / 32))
     return fail(HL_EINVAL, "bad debug_recip args");
   HIPCHK(launch_debug_recip(d, nd, P, omega, P / 32 + 4, h, (hipStream_t)stream));
+  return HL_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_factor_t* f, void* ws, size_t ws_bytes,
+                                  uint32_t* x, uint32_t* blk, int64_t* blk_exp, void* stream) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  Dims dm;
+  hl_status s = make_dims(sh, &dm);
+  if (s != HL_OK) return s;
+  if (!f || !f->d || !f->h || !f->s || !f->l || !x || !blk || !blk_exp) return fail(HL_EINVAL, "null argument");
+  Layout L = make_layout(dm);
+  if ((s = check_ws(L, ws, ws_bytes)) != HL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  DevStatus* dst = (DevStatus*)(base + L.status);
+  u32* ACC = (u32*)(base + L.tiles);  // the trailing matrix is finished: reuse as accumulators
+  u32* omega = (u32*)(base + L.omega);
+  const size_t ldb = (size_t)dm.NT * dm.nl;
+  const size_t ldx = (size_t)dm.k * dm.nl;
+
+  Stamp ts(ctx, st, 2);
+  HIPCHK(launch_fill(ACC, (size_t)dm.nt * tile_words(dm.nw), 0u, st));
+  for (int R0 = 0; R0 < dm.N; R0 += 16) {
+    const int nb = dm.N - R0 < 16 ? dm.N - R0 : 16;
+    for (int j = 0; j < nb; ++j) {
+      const int r = R0 + j;
+      HIPCHK(launch_trsm_row(ACC, dm, r, f->s, f->h, x, dst, st));
+      if (j + 1 < nb) {
+        UpdArgs g{};
+        g.A = ACC;
+        g.tri = 0;
+        g.ntc = 1;
+        g.nw = dm.nw;
+        g.nl = dm.nl;
+        g.Bop = f->l + (size_t)r * ldb;
+        g.ldb = ldb;
+        g.Uop = x + (size_t)r * ldx;
+        g.ldu = ldx;
+        g.npan = 1;
+        g.r_lo = r + 1;
+        g.r_hi = R0 + nb;
+        g.c_lo = 0;
+        g.c_hi = dm.k;
+        g.st = dst;
+        HIPCHK(launch_upd_valu(g, st));
+      }
+    }
+    if (R0 + nb < dm.N) {
+      UpdArgs g{};
+      g.A = ACC;
+      g.tri = 0;
+      g.ntc = 1;
+      g.nw = dm.nw;
+      g.nl = dm.nl;
+      g.Bop = f->l + (size_t)R0 * ldb;
+      g.ldb = ldb;
+      g.Uop = x + (size_t)R0 * ldx;
+      g.ldu = ldx;
+      g.npan = nb;
+      g.r_lo = R0 + nb;
+      g.r_hi = dm.N;
+      g.c_lo = 0;
+      g.c_hi = dm.k;
+      g.st = dst;
+      HIPCHK(launch_upd_valu(g, st));
+    }
+  }
+  ts.end();
+  Stamp tb(ctx, st, 3);
+  HIPCHK(launch_block(x, dm, omega, L.omega_stride, f->s, (u32*)(base + L.blk_part), L.blk_stride, L.blk_chunks,
+                      kBlockRows, (u32*)(base + L.blk_sum), L.blk_stride + 64, blk, blk_exp, dst, st));
+  tb.end();
+  return HL_OK;
+}
+
+// value (sign, exponent, mantissa top limbs) of a device float -> double and P-bit mantissa
+static double fp_to_double(int sign, long e, const std::vector<uint32_t>& m) {
+  // m: NWM limbs, top bit of m.back() set; value = (M / 2^(32 NWM)) 2^e
+  const size_t n = m.size();
+  const uint64_t top = ((uint64_t)m[n - 1] << 32) | m[n - 2];
+  double v = std::ldexp((double)(top >> 11), (int)(e - 53));
+  return sign ? -v : v;
+}
+
+extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32_t* blk, const int64_t* blk_exp,
+                                   void* ws, size_t ws_bytes, uint32_t* lam_mant, uint32_t* lam_mant_km1,
+                                   hl_lambda_t* out, void* stream) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  Dims dm;
+  hl_status s = make_dims(sh, &dm);
+  if (s != HL_OK) return s;
+  if (!blk || !blk_exp || !out) return fail(HL_EINVAL, "null argument");
+  Layout L = make_layout(dm);
+  if ((s = check_ws(L, ws, ws_bytes)) != HL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  DevStatus* dst = (DevStatus*)(base + L.status);
+  void* ews = base + L.eig;
+  Stamp te(ctx, st, 4);
+  HIPCHK(launch_eig(blk, dm, ews, dst, st));
+  te.end();
+  int32_t idx = 0;
+  if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;
+  int64_t bexp = 0;
+  HIPCHK(hipMemcpy(&bexp, blk_exp, 8, hipMemcpyDeviceToHost));
+  const int NWM = dm.nl + 4;
+  memset(out, 0, sizeof *out);
+  for (int which = 0; which < 3; ++which) {
+    if (which > 0 && dm.k < 2) {
+      if (which == 1) out->lambda1_km1 = std::nan("");
+      if (which == 2) out->trunc = std::nan("");
+      continue;
+    }
+    int* hdr = nullptr;
+    u32* mant = nullptr;
+    eig_result_refs(dm, ews, which, &hdr, &mant);
+    int h2[2];
+    std::vector<uint32_t> m(NWM);
+    HIPCHK(hipMemcpy(h2, hdr, 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(m.data(), mant, (size_t)NWM * 4, hipMemcpyDeviceToHost));
+    double v;
+    long e = (long)h2[1] - bexp;  // lambda_1 = (1 / lambda_max(blk)) 2^-blk_exp
+    if (h2[0] == 2) {
+      v = 0.0;
+    } else {
+      v = fp_to_double(h2[0], e, m);
+    }
+    uint32_t* dstm = which == 0 ? lam_mant : (which == 1 ? lam_mant_km1 : nullptr);
+    if (which == 0) {
+      out->lambda1 = v;
+      out->exp = e - 32L * dm.nl;
+    } else if (which == 1) {
+      out->lambda1_km1 = v;
+      out->exp_km1 = e - 32L * dm.nl;
+    } else {
+      out->trunc = v;
+    }
+    if (dstm) HIPCHK(hipMemcpy(dstm, m.data() + (NWM - dm.nl), (size_t)dm.nl * 4, hipMemcpyHostToDevice));
+  }
+  int fl[16];
+  HIPCHK(hipMemcpy(fl, ews, sizeof fl, hipMemcpyDeviceToHost));
+  out->iterations = fl[1] + fl[9];
   return HL_OK;
 }

@@ -41,3 +41,13 @@ struct MfmaArgs {
 hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream);
 size_t eig_ws_bytes_impl(int nl, int k);
 }  // namespace hl
+
+namespace hl {
+hipError_t launch_trsm_row(const u32* ACC, const Dims& dm, int r, const i32* s, const i32* h, u32* X,
+                           DevStatus* st, hipStream_t stream);
+hipError_t launch_block(const u32* X, const Dims& dm, const u32* omega, int ostride, const i32* s,
+                        u32* part, int ns, int nchunks, int rows_per_chunk, u32* msum, int nm, u32* blk,
+                        i64* blk_exp, DevStatus* st, hipStream_t stream);
+hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
+void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
+}  // namespace hl

@@ -1,7 +1,705 @@
-// Eigen-step (filled in below).
+// Eigen-step: lambda_1 ~= 1 / lambda_max of the k x k block of H^-1 (Section 4.2),
+// and the same for the leading (k-1) x (k-1) block (truncation estimate,
+// Section 4.5).  The paper casts the block to double and calls a library
+// eigen-solver; here it stays in multiprecision and no FP64 arithmetic is used.
+//
+// Arithmetic: multiprecision floating point (sign, exponent, mantissa of up to
+// NWM 32-bit limbs normalised to [1/2, 1)), built on the exact multi-limb
+// primitives; a working precision of nw limbs uses only the top nw limbs.
+//
+// Iteration (one workgroup per block): shifted inverse iteration with Rayleigh
+// quotients inside a bracket lo <= lambda_max < hi.
+//   * every Rayleigh quotient y'By / y'y is a lower bound of lambda_max;
+//   * a shift sigma with sigma I - B positive definite (all LDL^T pivots > 0)
+//     is an upper bound; a trial shift that fails the test is a lower bound;
+//   * the upper bound starts at Gershgorin's bound; each step solves
+//     (hi I - B) z = y, normalises z by a power of two, takes its Rayleigh
+//     quotient, and tries hi' = lo + c (hi - lo)^2 / hi, the size the error of
+//     the Rayleigh quotient would have after one step of the iteration;
+//   * the working precision grows with the number of bits the bracket has
+//     resolved, so only the last steps run at full precision.
+// The iteration stops when the bracket is narrower than 2^-(P+32) relative.
 #include "hl_kernels.hpp"
 #include "hl_host.hpp"
 
 namespace hl {
-size_t eig_ws_bytes(const Dims& dm) { return (size_t)64 * 1024 + (size_t)dm.k * dm.k * (dm.nl + 8) * 4 * 8; }
+
+constexpr int EIG_WAVES = 4;
+constexpr int EIG_THREADS = EIG_WAVES * WAVE;
+constexpr int EIG_MAXIT = 400;
+constexpr int EIG_NSCAL = 24;
+
+// ---------------------------------------------------------------------------
+// multiprecision floats in global memory: header (sign, exp) + NWM limbs
+struct FpRef {
+  int* hdr;  // hdr[0] = sign (0/1), hdr[1] = exponent; zero when hdr[0] == 2
+  u32* m;    // NWM limbs, significant limbs at the top
+};
+
+struct FpCtx {
+  int NWM;   // limb capacity
+  int nw;    // working precision in limbs (<= NWM - 1)
+  u32* la;   // per-wave LDS scratch, 2 * (NWM + 4) words
+  u32* lb;
+};
+
+constexpr int FPZERO_TAG = 2;
+
+// make this wave's global and LDS writes visible to its other lanes
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ bool fp_is_zero(const FpRef& x) { return x.hdr[0] == FPZERO_TAG; }
+
+__device__ void fp_set_zero(const FpCtx& c, FpRef z) {
+  for (int j = lane_id(); j < c.NWM; j += WAVE) z.m[j] = 0;
+  if (lane_id() == 0) {
+    z.hdr[0] = FPZERO_TAG;
+    z.hdr[1] = 0;
+  }
+  wsync();
+}
+
+__device__ void fp_copy(const FpCtx& c, FpRef z, const FpRef& x) {
+  const int s0 = x.hdr[0], s1 = x.hdr[1];
+  for (int j = lane_id(); j < c.NWM; j += WAVE) z.m[j] = x.m[j];
+  if (lane_id() == 0) {
+    z.hdr[0] = s0;
+    z.hdr[1] = s1;
+  }
+  wsync();
+}
+
+// z = value of the signed integer (two's complement, n limbs) at src
+__device__ void fp_from_int(const FpCtx& c, FpRef z, const u32* src, int n) {
+  u32* t = c.la;
+  for (int j = lane_id(); j < n; j += WAVE) t[j] = src[j];
+  wsync();
+  const bool neg = (t[n - 1] >> 31) != 0;
+  if (neg) w_neg(t, n);
+  wsync();
+  const int bl = w_bitlen(t, n);
+  if (bl == 0) {
+    fp_set_zero(c, z);
+    return;
+  }
+  // mantissa = t << (32 NWM - bl): its top bit lands on bit 32 NWM - 1
+  const long sh = 32L * c.NWM - bl;
+  for (int j = lane_id(); j < c.NWM; j += WAVE) {
+    u32 v = sh >= 0 ? limb_shl(t, n, sh, j) : limb_shr(t, n, -sh, j);
+    if (j < c.NWM - c.nw) v = 0;
+    z.m[j] = v;
+  }
+  if (lane_id() == 0) {
+    z.hdr[0] = neg ? 1 : 0;
+    z.hdr[1] = bl;  // value = (M / 2^(32 NWM)) 2^bl
+  }
+  wsync();
+}
+
+// z = x * y at working precision (z may alias x or y)
+__device__ void fp_mul(const FpCtx& c, FpRef z, const FpRef& x, const FpRef& y) {
+  if (fp_is_zero(x) || fp_is_zero(y)) {
+    fp_set_zero(c, z);
+    return;
+  }
+  const int nw = c.nw, top = c.NWM - nw;
+  u32* A = c.la;
+  u32* B = c.lb;
+  for (int j = lane_id(); j < nw; j += WAVE) {
+    A[j] = x.m[top + j];
+    B[j] = y.m[top + j];
+  }
+  const int sx = x.hdr[0], sy = y.hdr[0], e = x.hdr[1] + y.hdr[1];
+  wsync();
+  // limbs nw-1 .. 2nw-1 of A*B land on z.m[top-1 .. NWM)
+  const int nch = (2 * nw + WAVE - 1) / WAVE;
+  u32* zm = z.m;
+  w_mul_stream(A, nw, B, nw, nch, [&](int ch, u32 limb) {
+    const int p = ch * WAVE + lane_id();
+    if (p >= nw - 1 && p < 2 * nw) zm[top - 1 + (p - (nw - 1))] = limb;
+  });
+  wsync();
+  const bool low = (zm[c.NWM - 1] >> 31) == 0;
+  if (low) {
+    // shift z.m[top-1 .. NWM) left by one bit through LDS
+    for (int j = top - 1 + lane_id(); j < c.NWM; j += WAVE) A[j - (top - 1)] = zm[j];
+    wsync();
+    for (int j = top + lane_id(); j < c.NWM; j += WAVE)
+      zm[j] = (A[j - (top - 1)] << 1) | (A[j - top] >> 31);
+  }
+  wsync();
+  for (int j = lane_id(); j < top; j += WAVE) zm[j] = 0;
+  if (lane_id() == 0) {
+    z.hdr[0] = sx ^ sy;
+    z.hdr[1] = e - (low ? 1 : 0);
+  }
+  wsync();
+}
+
+// z = x + (neg_y ? -y : y) at working precision (z may alias x or y)
+__device__ void fp_add(const FpCtx& c, FpRef z, const FpRef& x0, const FpRef& y0, bool neg_y) {
+  const int nw = c.nw, top = c.NWM - nw;
+  const bool xz = fp_is_zero(x0), yz = fp_is_zero(y0);
+  if (yz) {
+    if (z.m != x0.m) fp_copy(c, z, x0);
+    wsync();
+    return;
+  }
+  if (xz) {
+    if (z.m != y0.m) fp_copy(c, z, y0);
+    wsync();
+    if (neg_y && lane_id() == 0) z.hdr[0] ^= 1;
+    wsync();
+    return;
+  }
+  int sx = x0.hdr[0], sy = y0.hdr[0] ^ (neg_y ? 1 : 0);
+  int ex = x0.hdr[1], ey = y0.hdr[1];
+  const FpRef* X = &x0;
+  const FpRef* Y = &y0;
+  if (ey > ex) {
+    X = &y0;
+    Y = &x0;
+    int t = sx; sx = sy; sy = t;
+    t = ex; ex = ey; ey = t;
+  }
+  const long d = (long)ex - ey;
+  const int n = nw + 3;  // 2 guard limbs below, 1 carry limb above
+  u32* A = c.la;
+  u32* B = c.lb;
+  for (int j = lane_id(); j < n; j += WAVE) {
+    A[j] = (j >= 2 && j < nw + 2) ? X->m[top + j - 2] : 0u;
+  }
+  // B = (Y limbs placed like A) >> d
+  for (int j = lane_id(); j < n; j += WAVE) {
+    const long src = (long)j + (d >> 5) - 2;  // limb index into Y's nw significant limbs
+    const int r = (int)(d & 31);
+    u32 lo = (src >= 0 && src < nw) ? Y->m[top + src] : 0u;
+    u32 hi = (src + 1 >= 0 && src + 1 < nw) ? Y->m[top + src + 1] : 0u;
+    B[j] = (j == n - 1) ? 0u : (r ? ((lo >> r) | (hi << (32 - r))) : lo);
+    if (d > 32L * (nw + 4)) B[j] = 0;
+  }
+  wsync();
+  int sz = sx;
+  if (sx == sy) {
+    w_add(A, n, B, n, A, n);
+  } else {
+    const int cmp = w_cmp(A, B, n);
+    if (cmp == 0) {
+      fp_set_zero(c, z);
+      wsync();
+      return;
+    }
+    if (cmp > 0) {
+      w_sub(A, B, A, n);
+    } else {
+      w_sub(B, A, A, n);
+      sz = sy;
+    }
+  }
+  wsync();
+  // normalise: top bit of A (n limbs) to bit 32 (nw + 2) - 1, i.e. limb n-2's top
+  const int bl = w_bitlen(A, n);
+  const long want = 32L * (nw + 2);
+  const long sh = want - bl;  // > 0: shift left
+  int e = ex - (int)sh;
+  // write the top nw limbs of (A << sh) to z
+  for (int j = lane_id(); j < nw; j += WAVE) {
+    const int dst = j + 2;
+    u32 v = sh >= 0 ? limb_shl(A, n, sh, dst) : limb_shr(A, n, -sh, dst);
+    B[j] = v;
+  }
+  wsync();
+  for (int j = lane_id(); j < c.NWM; j += WAVE) z.m[j] = j >= top ? B[j - top] : 0u;
+  if (lane_id() == 0) {
+    z.hdr[0] = sz;
+    z.hdr[1] = e;
+  }
+  wsync();
+}
+
+// z = 2^k x
+__device__ void fp_ldexp(FpRef z, int k) {
+  if (lane_id() == 0 && z.hdr[0] != FPZERO_TAG) z.hdr[1] += k;
+  wsync();
+}
+
+// sign of x - y (magnitudes and signs), -1 / 0 / 1
+__device__ int fp_cmp(const FpCtx& c, const FpRef& x, const FpRef& y) {
+  const bool xz = fp_is_zero(x), yz = fp_is_zero(y);
+  const int sx = xz ? 0 : (x.hdr[0] ? -1 : 1), sy = yz ? 0 : (y.hdr[0] ? -1 : 1);
+  if (sx != sy) return sx > sy ? 1 : -1;
+  if (sx == 0) return 0;
+  int mag;
+  if (x.hdr[1] != y.hdr[1]) {
+    mag = x.hdr[1] > y.hdr[1] ? 1 : -1;
+  } else {
+    mag = w_cmp(x.m, y.m, c.NWM);
+  }
+  return sx > 0 ? mag : -mag;
+}
+
+// reciprocal by Newton's iteration y <- y + y (1 - x y) with doubling precision
+__device__ void fp_recip(const FpCtx& c0, FpRef z, const FpRef& x, FpRef t1, FpRef t2) {
+  FpCtx c = c0;
+  // 62-bit start from the top 64 bits of the mantissa
+  const u32 m1 = x.m[c.NWM - 1], m0 = x.m[c.NWM - 2];
+  const u64 top = ((u64)m1 << 32) | m0;  // in [2^63, 2^64)
+  const u64 top32 = top >> 32;           // [2^31, 2^32)
+  u64 q = (~0ull) / (top32 + 1);  // ~ 2^32 / f, f = top32 / 2^32 in [1/2, 1)
+  if (q < (1ull << 32)) q = 1ull << 32;
+  // 1/x = (1 / (2f)) 2^(1 - ex), and 1 / (2f) ~ q / 2^33 in [1/2, 1)
+  if (lane_id() == 0) z.hdr[0] = x.hdr[0];
+  for (int j = lane_id(); j < c.NWM; j += WAVE) {
+    u32 v = 0;
+    // q has 33 bits; place so that bit 32 of q is bit 32 NWM - 1
+    if (j == c.NWM - 1) v = (u32)(q >> 1);
+    if (j == c.NWM - 2) v = (u32)(q << 31);
+    z.m[j] = v;
+  }
+  if (lane_id() == 0) z.hdr[1] = 1 - x.hdr[1];
+  wsync();
+  // z ~ 1/x to ~30 bits; iterate
+  const int target = c0.nw;
+  int prec = 1;
+  for (int it = 0; it < 40; ++it) {
+    int np = 2 * prec;
+    if (np > target) np = target;
+    c.nw = np + 1 <= c0.NWM - 1 ? np + 1 : c0.NWM - 1;
+    if (c.nw > target) c.nw = target;
+    // t1 = x z ; t2 = 1 - t1 ; t1 = z t2 ; z = z + t1
+    fp_mul(c, t1, x, z);
+    // t2 = 1 - t1: build 1 in t2
+    for (int j = lane_id(); j < c.NWM; j += WAVE) t2.m[j] = (j == c.NWM - 1) ? 0x80000000u : 0u;
+    if (lane_id() == 0) {
+      t2.hdr[0] = 0;
+      t2.hdr[1] = 1;
+    }
+    wsync();
+    fp_add(c, t2, t2, t1, true);
+    fp_mul(c, t1, z, t2);
+    fp_add(c, z, z, t1, false);
+    prec = np;
+    if (np >= target) {
+      if (it > 0 && np == target) {
+        // one extra polish step at full precision
+        fp_mul(c, t1, x, z);
+        for (int j = lane_id(); j < c.NWM; j += WAVE) t2.m[j] = (j == c.NWM - 1) ? 0x80000000u : 0u;
+        if (lane_id() == 0) {
+          t2.hdr[0] = 0;
+          t2.hdr[1] = 1;
+        }
+        wsync();
+        fp_add(c, t2, t2, t1, true);
+        fp_mul(c, t1, z, t2);
+        fp_add(c, z, z, t1, false);
+      }
+      break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+struct EigMat {
+  int n;          // order of this block (k or k-1)
+  int NWM;
+  int* hdr;       // headers of all numbers, 2 ints each
+  u32* mant;      // mantissas, NWM each
+  int* flags;     // [0] status, [1] iterations
+};
+
+// number indices inside one EigMat region
+__host__ __device__ __forceinline__ int ix_B(int n, int a, int b) { return a * n + b; }
+__host__ __device__ __forceinline__ int ix_C(int n, int a, int b) { return n * n + a * n + b; }
+__host__ __device__ __forceinline__ int ix_L(int n, int a, int b) { return 2 * n * n + a * n + b; }
+__host__ __device__ __forceinline__ int ix_y(int n, int a) { return 3 * n * n + a; }
+__host__ __device__ __forceinline__ int ix_z(int n, int a) { return 3 * n * n + n + a; }
+__host__ __device__ __forceinline__ int ix_t(int n, int a) { return 3 * n * n + 2 * n + a; }
+__host__ __device__ __forceinline__ int ix_inv(int n, int a) { return 3 * n * n + 3 * n + a; }
+__host__ __device__ __forceinline__ int ix_s(int n, int j) { return 3 * n * n + 4 * n + j; }  // scalars
+// per-wave scratch numbers: after the scalars
+__host__ __device__ __forceinline__ int ix_w(int n, int w, int j) { return 3 * n * n + 4 * n + EIG_NSCAL + w * 4 + j; }
+__host__ __device__ __forceinline__ int eig_numbers(int n) { return 3 * n * n + 4 * n + EIG_NSCAL + EIG_WAVES * 4; }
+
+__device__ __forceinline__ FpRef num(const EigMat& M, int i) {
+  return FpRef{M.hdr + 2 * i, M.mant + (size_t)i * M.NWM};
+}
+
+enum { S_HI = 0, S_LO, S_RQ, S_TRY, S_W, S_NUM, S_DEN, S_ONE, S_T1, S_T2, S_T3, S_RES };
+
+// LDL^T of C = sigma I - B in place (C <- Schur complements, L, inv pivots);
+// returns true if every pivot is positive.  All waves call it.
+__device__ bool eig_factor(const EigMat& M, FpCtx c, const FpRef& sigma, int* flag_lds) {
+  const int n = M.n, w = wave_id();
+  // C = sigma I - B
+  for (int idx = w; idx < n * n; idx += EIG_WAVES) {
+    const int a = idx / n, b = idx % n;
+    FpRef C = num(M, ix_C(n, a, b));
+    FpRef B = num(M, ix_B(n, a, b));
+    if (a == b) fp_add(c, C, sigma, B, true);
+    else {
+      fp_copy(c, C, B);
+      wsync();
+      if (lane_id() == 0 && C.hdr[0] != FPZERO_TAG) C.hdr[0] ^= 1;
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {
+    if (w == 0) {
+      FpRef d = num(M, ix_C(n, i, i));
+      const bool pos = !fp_is_zero(d) && d.hdr[0] == 0;
+      if (lane_id() == 0) flag_lds[0] = pos ? 1 : 0;
+      if (pos) fp_recip(c, num(M, ix_inv(n, i)), d, num(M, ix_w(n, 0, 0)), num(M, ix_w(n, 0, 1)));
+    }
+    __syncthreads();
+    if (!flag_lds[0]) return false;
+    for (int r = i + 1 + w; r < n; r += EIG_WAVES)
+      fp_mul(c, num(M, ix_L(n, r, i)), num(M, ix_C(n, r, i)), num(M, ix_inv(n, i)));
+    __syncthreads();
+    const int m = n - i - 1;
+    for (int idx = w; idx < m * m; idx += EIG_WAVES) {
+      const int r = i + 1 + idx / m, cc = i + 1 + idx % m;
+      if (r < cc) continue;
+      FpRef T = num(M, ix_w(n, w, 0));
+      fp_mul(c, T, num(M, ix_L(n, r, i)), num(M, ix_C(n, cc, i)));
+      fp_add(c, num(M, ix_C(n, r, cc)), num(M, ix_C(n, r, cc)), T, true);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// z = C^-1 y with the factorisation above (C = L D L^T); y is preserved.
+__device__ void eig_solve(const EigMat& M, FpCtx c) {
+  const int n = M.n, w = wave_id();
+  for (int a = w; a < n; a += EIG_WAVES) fp_copy(c, num(M, ix_t(n, a)), num(M, ix_y(n, a)));
+  __syncthreads();
+  // forward: t_r -= L_rj t_j
+  for (int j = 0; j < n; ++j) {
+    for (int r = j + 1 + w; r < n; r += EIG_WAVES) {
+      FpRef T = num(M, ix_w(n, w, 0));
+      fp_mul(c, T, num(M, ix_L(n, r, j)), num(M, ix_t(n, j)));
+      fp_add(c, num(M, ix_t(n, r)), num(M, ix_t(n, r)), T, true);
+    }
+    __syncthreads();
+  }
+  for (int a = w; a < n; a += EIG_WAVES) fp_mul(c, num(M, ix_t(n, a)), num(M, ix_t(n, a)), num(M, ix_inv(n, a)));
+  __syncthreads();
+  // backward: t_r -= L_jr t_j for r < j
+  for (int j = n - 1; j >= 0; --j) {
+    for (int r = w; r < j; r += EIG_WAVES) {
+      FpRef T = num(M, ix_w(n, w, 0));
+      fp_mul(c, T, num(M, ix_L(n, j, r)), num(M, ix_t(n, j)));
+      fp_add(c, num(M, ix_t(n, r)), num(M, ix_t(n, r)), T, true);
+    }
+    __syncthreads();
+  }
+  for (int a = w; a < n; a += EIG_WAVES) fp_copy(c, num(M, ix_z(n, a)), num(M, ix_t(n, a)));
+  __syncthreads();
+}
+
+// S_RQ = y'By / y'y
+__device__ void eig_rayleigh(const EigMat& M, FpCtx c) {
+  const int n = M.n, w = wave_id();
+  // t_a = sum_b B_ab y_b
+  for (int a = w; a < n; a += EIG_WAVES) {
+    FpRef ta = num(M, ix_t(n, a));
+    fp_set_zero(c, ta);
+    wsync();
+    FpRef T = num(M, ix_w(n, w, 0));
+    for (int b = 0; b < n; ++b) {
+      fp_mul(c, T, num(M, ix_B(n, a, b)), num(M, ix_y(n, b)));
+      fp_add(c, ta, ta, T, false);
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    FpRef num_ = num(M, ix_s(n, S_NUM)), den = num(M, ix_s(n, S_DEN)), T = num(M, ix_w(n, 0, 0));
+    fp_set_zero(c, num_);
+    fp_set_zero(c, den);
+    wsync();
+    for (int a = 0; a < n; ++a) {
+      fp_mul(c, T, num(M, ix_y(n, a)), num(M, ix_t(n, a)));
+      fp_add(c, num_, num_, T, false);
+      fp_mul(c, T, num(M, ix_y(n, a)), num(M, ix_y(n, a)));
+      fp_add(c, den, den, T, false);
+    }
+    FpRef inv = num(M, ix_s(n, S_T1));
+    fp_recip(c, inv, den, num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
+    fp_mul(c, num(M, ix_s(n, S_RQ)), num_, inv);
+  }
+  __syncthreads();
+}
+
+// y = z * 2^-e, e = max exponent of z (exact)
+__device__ void eig_normalise(const EigMat& M, FpCtx c, int* lds_int) {
+  const int n = M.n, w = wave_id();
+  if (threadIdx.x == 0) {
+    int e = INT_MIN;
+    for (int a = 0; a < n; ++a) {
+      FpRef z = num(M, ix_z(n, a));
+      if (!fp_is_zero(z) && z.hdr[1] > e) e = z.hdr[1];
+    }
+    lds_int[0] = e == INT_MIN ? 0 : e;
+  }
+  __syncthreads();
+  const int e = lds_int[0];
+  for (int a = w; a < n; a += EIG_WAVES) {
+    FpRef y = num(M, ix_y(n, a));
+    fp_copy(c, y, num(M, ix_z(n, a)));
+    wsync();
+    fp_ldexp(y, -e);
+  }
+  __syncthreads();
+}
+
+// number of bits the bracket resolves: exp(hi) - exp(hi - lo), capped
+__device__ int eig_bits(const EigMat& M, FpCtx c) {
+  const int n = M.n;
+  FpRef W = num(M, ix_s(n, S_W));
+  fp_add(c, W, num(M, ix_s(n, S_HI)), num(M, ix_s(n, S_LO)), true);
+  if (fp_is_zero(W)) return 1 << 30;
+  if (W.hdr[0] == 1) return -1;  // lo above hi: inconsistent
+  return num(M, ix_s(n, S_HI)).hdr[1] - W.hdr[1];
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(const u32* __restrict__ blk, int k, int nl, int P,
+                                                     int NWM, int* hdr_base, u32* mant_base, size_t nums_per,
+                                                     int* flags_base, DevStatus* st) {
+  if (has_error(st)) return;
+  const int which = blockIdx.x;  // 0: k x k, 1: (k-1) x (k-1)
+  const int n = k - which;
+  if (n < 1) return;
+  EigMat M;
+  M.n = n;
+  M.NWM = NWM;
+  M.hdr = hdr_base + (size_t)which * nums_per * 2;
+  M.mant = mant_base + (size_t)which * nums_per * NWM;
+  M.flags = flags_base + which * 8;
+  extern __shared__ u32 lds[];
+  const int w = wave_id();
+  int* lds_int = (int*)lds;
+  FpCtx c;
+  c.NWM = NWM;
+  c.la = lds + 16 + w * 2 * (NWM + 8);
+  c.lb = c.la + NWM + 8;
+  const int NWF = NWM - 1;  // final working precision
+  c.nw = NWF;
+  // B from the integer block (full precision)
+  for (int idx = w; idx < n * n; idx += EIG_WAVES) {
+    const int a = idx / n, b = idx % n;
+    fp_from_int(c, num(M, ix_B(n, a, b)), blk + ((size_t)a * k + b) * nl, nl);
+  }
+  __syncthreads();
+  if (n == 1) {
+    if (w == 0) fp_copy(c, num(M, ix_s(n, S_RES)), num(M, ix_B(n, 0, 0)));
+    if (threadIdx.x == 0) M.flags[1] = 0;
+    __syncthreads();
+    goto finish;
+  }
+  {
+    c.nw = 4 < NWF ? 4 : NWF;
+    // hi = Gershgorin bound (1 + 2^-16), lo = max diagonal, y = 1
+    if (w == 0) {
+      FpRef hi = num(M, ix_s(n, S_HI)), lo = num(M, ix_s(n, S_LO));
+      FpRef T = num(M, ix_w(n, 0, 0)), R = num(M, ix_w(n, 0, 1));
+      FpCtx cf = c;
+      cf.nw = NWF;
+      fp_set_zero(cf, hi);
+      fp_copy(cf, lo, num(M, ix_B(n, 0, 0)));
+      wsync();
+      for (int a = 0; a < n; ++a) {
+        fp_set_zero(cf, R);
+        wsync();
+        for (int b = 0; b < n; ++b) {
+          fp_copy(cf, T, num(M, ix_B(n, a, b)));
+          wsync();
+          if (lane_id() == 0 && T.hdr[0] == 1) T.hdr[0] = 0;  // |B_ab|
+          wsync();
+          fp_add(cf, R, R, T, false);
+        }
+        if (fp_cmp(cf, R, hi) > 0) fp_copy(cf, hi, R);
+        wsync();
+        if (fp_cmp(cf, num(M, ix_B(n, a, a)), lo) > 0) fp_copy(cf, lo, num(M, ix_B(n, a, a)));
+        wsync();
+      }
+      // hi *= 1 + 2^-16
+      fp_copy(cf, T, hi);
+      wsync();
+      fp_ldexp(T, -16);
+      fp_add(cf, hi, hi, T, false);
+    }
+    for (int a = w; a < n; a += EIG_WAVES) {
+      FpRef y = num(M, ix_y(n, a));
+      for (int j = lane_id(); j < NWM; j += WAVE) y.m[j] = (j == NWM - 1) ? 0x80000000u : 0u;
+      if (lane_id() == 0) {
+        y.hdr[0] = 0;
+        y.hdr[1] = 1;
+      }
+    }
+    __syncthreads();
+    const long target_bits = (long)P + 32;
+    float cexp = 2.0f;  // log2 of the constant c in hi' = lo + c (hi - lo)^2 / hi
+    int it = 0;
+    bool have_factor = false;
+    for (; it < EIG_MAXIT; ++it) {
+      if (!have_factor) {
+        const bool pd = eig_factor(M, c, num(M, ix_s(n, S_HI)), lds_int + 4);
+        if (!pd) {
+          // hi was not above lambda_max at this precision: widen it
+          if (w == 0) {
+            FpRef hi = num(M, ix_s(n, S_HI)), lo = num(M, ix_s(n, S_LO)), T = num(M, ix_w(n, 0, 0));
+            fp_add(c, T, hi, lo, true);  // hi - lo
+            if (fp_is_zero(T) || T.hdr[0]) {
+              fp_copy(c, T, hi);
+              wsync();
+              fp_ldexp(T, -20);
+            }
+            fp_add(c, hi, hi, T, false);
+          }
+          __syncthreads();
+          continue;
+        }
+      }
+      eig_solve(M, c);
+      eig_normalise(M, c, lds_int + 8);
+      eig_rayleigh(M, c);
+      int bits;
+      if (w == 0) {
+        FpRef lo = num(M, ix_s(n, S_LO)), rq = num(M, ix_s(n, S_RQ));
+        if (fp_cmp(c, rq, lo) > 0) fp_copy(c, lo, rq);
+        wsync();
+        bits = eig_bits(M, c);
+        if (lane_id() == 0) lds_int[12] = bits;
+      }
+      __syncthreads();
+      bits = lds_int[12];
+      if (bits < 0) {
+        if (threadIdx.x == 0) set_status(st, HL_ENOCONV, which);
+        return;
+      }
+      if (bits >= target_bits && c.nw == NWF) break;
+      // precision for the next step
+      long need = 2L * bits + 160;
+      int nwn = (int)((need + 31) / 32);
+      if (nwn < 4) nwn = 4;
+      if (nwn > NWF) nwn = NWF;
+      if (nwn > c.nw) c.nw = nwn;
+      // trial upper bound: lo + c (hi - lo)^2 / hi, capped at lo + (hi - lo) / 2
+      if (w == 0) {
+        FpRef hi = num(M, ix_s(n, S_HI)), lo = num(M, ix_s(n, S_LO)), Wd = num(M, ix_s(n, S_W));
+        FpRef T = num(M, ix_s(n, S_T1)), U = num(M, ix_s(n, S_T2)), tr = num(M, ix_s(n, S_TRY));
+        fp_add(c, Wd, hi, lo, true);
+        fp_mul(c, T, Wd, Wd);
+        fp_recip(c, U, hi, num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
+        fp_mul(c, T, T, U);
+        const int ce = (int)cexp;
+        fp_ldexp(T, ce);
+        FpRef half = num(M, ix_s(n, S_T3));
+        fp_copy(c, half, Wd);
+        wsync();
+        fp_ldexp(half, -1);
+        if (fp_cmp(c, T, half) > 0) fp_copy(c, T, half);
+        wsync();
+        fp_add(c, tr, lo, T, false);
+      }
+      __syncthreads();
+      const bool pd = eig_factor(M, c, num(M, ix_s(n, S_TRY)), lds_int + 4);
+      if (w == 0) {
+        if (pd) {
+          fp_copy(c, num(M, ix_s(n, S_HI)), num(M, ix_s(n, S_TRY)));
+        } else {
+          fp_copy(c, num(M, ix_s(n, S_LO)), num(M, ix_s(n, S_TRY)));
+        }
+      }
+      __syncthreads();
+      if (pd) {
+        have_factor = true;
+        cexp = cexp > 2.0f ? cexp - 4.0f : 2.0f;
+      } else {
+        have_factor = false;
+        cexp += 8.0f;
+      }
+    }
+    if (threadIdx.x == 0) M.flags[1] = it;
+    if (it >= EIG_MAXIT) {
+      if (threadIdx.x == 0) set_status(st, HL_ENOCONV, which);
+      return;
+    }
+    if (w == 0) fp_copy(c, num(M, ix_s(n, S_RES)), num(M, ix_s(n, S_LO)));
+    __syncthreads();
+  }
+finish:
+  // lambda_1 (without the block exponent) = 1 / lambda_max
+  if (w == 0) {
+    c.nw = NWF;
+    FpRef res = num(M, ix_s(n, S_RES));
+    FpRef inv = num(M, ix_s(n, S_ONE));
+    fp_recip(c, inv, res, num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
+  }
+}
+
+// difference of the two results: trunc = lam(k) - lam(k-1) (scaled equally)
+__global__ __launch_bounds__(64) void k_eig_diff(int k, int NWM, int* hdr_base, u32* mant_base,
+                                                 size_t nums_per, DevStatus* st) {
+  if (has_error(st) || k < 2) return;
+  extern __shared__ u32 lds[];
+  FpCtx c;
+  c.NWM = NWM;
+  c.nw = NWM - 1;
+  c.la = lds;
+  c.lb = lds + NWM + 8;
+  EigMat A, B;
+  A.n = k;
+  A.NWM = NWM;
+  A.hdr = hdr_base;
+  A.mant = mant_base;
+  B.n = k - 1;
+  B.NWM = NWM;
+  B.hdr = hdr_base + nums_per * 2;
+  B.mant = mant_base + nums_per * NWM;
+  FpRef r = num(A, ix_s(k, S_T3));
+  fp_add(c, r, num(A, ix_s(k, S_ONE)), num(B, ix_s(k - 1, S_ONE)), true);
+}
+
+size_t eig_ws_bytes(const Dims& dm) {
+  const int NWM = dm.nl + 4;
+  const size_t per = (size_t)eig_numbers(dm.k);
+  return 2 * per * (2 * 4 + (size_t)NWM * 4) + 256;
+}
+
+// host: run the eigen-step on both blocks and read back the results
+hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream) {
+  const int NWM = dm.nl + 4;
+  const size_t per = (size_t)eig_numbers(dm.k);
+  int* flags = (int*)eig_ws;
+  int* hdr = flags + 64;
+  u32* mant = (u32*)(hdr + 2 * 2 * per);
+  const size_t lds = (size_t)(16 + EIG_WAVES * 2 * (NWM + 8)) * 4;
+  hipLaunchKernelGGL(k_eig, dim3(dm.k >= 2 ? 2 : 1), dim3(EIG_THREADS), lds, stream, blk, dm.k, dm.nl, dm.P, NWM,
+                     hdr, mant, per, flags, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (NWM + 8) * 4, stream, dm.k, NWM, hdr, mant,
+                     per, st);
+  return hipGetLastError();
+}
+
+// locations of the results (host side arithmetic on offsets only)
+void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out) {
+  const int NWM = dm.nl + 4;
+  const size_t per = (size_t)eig_numbers(dm.k);
+  int* flags = (int*)eig_ws;
+  int* hdr = flags + 64;
+  u32* mant = (u32*)(hdr + 2 * 2 * per);
+  // which: 0 -> 1/lambda_max(k), 1 -> 1/lambda_max(k-1), 2 -> difference, 3 -> iteration flags
+  const int n = which == 1 ? dm.k - 1 : dm.k;
+  const int blkidx = which == 1 ? 1 : 0;
+  const int idx = which == 2 ? ix_s(n, S_T3) : ix_s(n, S_ONE);
+  *hdr_out = hdr + (size_t)blkidx * per * 2 + 2 * idx;
+  *mant_out = mant + ((size_t)blkidx * per + idx) * NWM;
+}
+
 }  // namespace hl
