@@ -77,6 +77,9 @@ typedef struct {
   int32_t NT;             /* N rounded up to a multiple of 32                            */
   int32_t mu_limbs_min;   /* not used (moments may have any width w >= 1)                */
   int32_t reserved;
+  size_t diag_offset;     /* byte offset in the workspace of 64 int32 eigen-step
+                             diagnostics: [1], [9] iterations of the two blocks,
+                             [16..40), [40..64) per-iteration bracket bits*1000+limbs */
 } hl_sizes;
 
 /* Device views of the factorisation, all owned by the caller. */
@@ -173,6 +176,10 @@ hl_status hl_debug_mul(const uint32_t *a, int32_t na, const uint32_t *b, int32_t
                        int32_t nout, void *stream);
 hl_status hl_debug_recip(const uint32_t *d, int32_t nd, int32_t P, uint32_t *omega, int32_t *h,
                          void *stream);
+/* Output layout of v_mfma_i32_32x32x32_i8: out (device, 2048 int32) holds, per
+ * accumulator register v and lane l at out[v*64 + l], 32(m+1) for A rows m+1,
+ * B ones, then at out[1024 + v*64 + l] 32(n+1) for A ones, B columns n+1. */
+hl_status hl_debug_mfma_layout(int32_t *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,8 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_EINVAL", 2: "HL_ENOTPD", 3: "HL_EOVERFLOW", 4
                 5: "HL_EHIP", 6: "HL_ENOMEM"}
 
 EXPORTS = ["hl_create", "hl_destroy", "hl_last_error", "hl_get_sizes", "hl_factor", "hl_inv_block",
-           "hl_lambda_min", "hl_sync", "hl_set_timing", "hl_get_timing", "hl_debug_mul", "hl_debug_recip"]
+           "hl_lambda_min", "hl_sync", "hl_set_timing", "hl_get_timing", "hl_debug_mul", "hl_debug_recip",
+           "hl_debug_mfma_layout"]
 
 
 class hl_shape(ctypes.Structure):
@@ -25,7 +26,8 @@ class hl_sizes(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_size_t), ("d_words", ctypes.c_size_t),
                 ("l_words", ctypes.c_size_t), ("x_words", ctypes.c_size_t),
                 ("blk_words", ctypes.c_size_t), ("nl", ctypes.c_int32), ("NT", ctypes.c_int32),
-                ("mu_limbs_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mu_limbs_min", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("diag_offset", ctypes.c_size_t)]
 
 
 class hl_factor_t(ctypes.Structure):
@@ -73,6 +75,7 @@ def lib():
             "hl_get_timing": [P, ctypes.POINTER(hl_timing_t)],
             "hl_debug_mul": [P, I32, P, I32, P, I32, P],
             "hl_debug_recip": [P, I32, I32, P, P, P],
+            "hl_debug_mfma_layout": [P, P],
         }
         for name, args in sig.items():
             try:

@@ -191,6 +191,9 @@ class Context:
             raise L.HLError(code, L.lib().hl_last_error().decode())
         res = {"lambda1": out.lambda1, "lambda1_km1": out.lambda1_km1, "trunc": out.trunc,
                "exp": out.exp, "exp_km1": out.exp_km1, "iterations": out.iterations}
+        off = fac.sizes.diag_offset
+        fl = fac.ws[off:off + 256].view(torch.int32).cpu().tolist()
+        res["trace"] = [fl[16:40], fl[40:64]]
         if want_mant:
             res["mant"] = _ints(m1, nl, signed=False)[0]
             res["mant_km1"] = _ints(m2, nl, signed=False)[0]
@@ -217,6 +220,12 @@ class Context:
         L.check(L.lib().hl_debug_mul(_ptr(A), na, _ptr(B), nb, _ptr(O), nout, _stream()))
         torch.cuda.synchronize()
         return _ints(O, nout, signed=False)[0]
+
+    def debug_mfma_layout(self):
+        O = torch.zeros(2048, dtype=torch.int32, device=self.device)
+        L.check(L.lib().hl_debug_mfma_layout(_ptr(O), _stream()))
+        torch.cuda.synchronize()
+        return O.cpu().tolist()
 
     def debug_recip(self, d: int, P: int):
         nl = P // 32

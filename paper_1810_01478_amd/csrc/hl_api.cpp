@@ -122,6 +122,7 @@ extern "C" hl_status hl_get_sizes(const hl_shape* sh, hl_sizes* out) {
   out->blk_words = (size_t)dm.k * dm.k * dm.nl;
   out->nl = dm.nl;
   out->NT = dm.NT;
+  out->diag_offset = L.eig;
   return HL_OK;
 }
 
@@ -218,6 +219,11 @@ extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* 
   Stamp ld(ctx, st, 5);
   HIPCHK(launch_fill((u32*)dst, 64, 0u, st));
   HIPCHK(launch_fill(out->l, (size_t)dm.N * dm.NT * dm.nl, 0u, st));
+  if (sh->form == HL_FORM_MFMA8) {
+    // zero digit slices (the padding outside [0, S) must read as zero)
+    HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
+    HIPCHK(launch_fill((u32*)(base + L.udig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
+  }
   HIPCHK(launch_scales(mu, mu_exp, w, dm.N, dm.E, out->s, dst, st));
   HIPCHK(launch_load(mu, mu_exp, w, out->s, dm, A, dst, st));
   ld.end();
@@ -463,5 +469,11 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   int fl[16];
   HIPCHK(hipMemcpy(fl, ews, sizeof fl, hipMemcpyDeviceToHost));
   out->iterations = fl[1] + fl[9];
+  return HL_OK;
+}
+
+extern "C" hl_status hl_debug_mfma_layout(int32_t* out, void* stream) {
+  if (!out) return fail(HL_EINVAL, "null output");
+  HIPCHK(launch_mfma_probe(out, (hipStream_t)stream));
   return HL_OK;
 }

@@ -51,3 +51,7 @@ hipError_t launch_block(const u32* X, const Dims& dm, const u32* omega, int ostr
 hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
 }  // namespace hl
+
+namespace hl {
+hipError_t launch_mfma_probe(int* out, hipStream_t stream);
+}  // namespace hl

@@ -576,13 +576,19 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const u32* __restrict__ blk
       }
       __syncthreads();
       bits = lds_int[12];
+      if (threadIdx.x == 0 && it < 24) flags_base[16 + which * 24 + it] = bits * 1000 + c.nw;
       if (bits < 0) {
+        // the bounds crossed: at full precision that is rounding, the bracket
+        // has closed; below it the iteration has gone wrong
+        if (c.nw == NWF) break;
         if (threadIdx.x == 0) set_status(st, HL_ENOCONV, which);
         return;
       }
       if (bits >= target_bits && c.nw == NWF) break;
-      // precision for the next step
-      long need = 2L * bits + 160;
+      // precision for the trial factorisation, which the next solve reuses: its
+      // shift lies about 2^-2bits above lambda_max, so the system is that badly
+      // conditioned and the solution must still carry 2 bits of accuracy
+      long need = 4L * bits + 160;
       int nwn = (int)((need + 31) / 32);
       if (nwn < 4) nwn = 4;
       if (nwn > NWF) nwn = NWF;
@@ -603,6 +609,12 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const u32* __restrict__ blk
         fp_ldexp(half, -1);
         if (fp_cmp(c, T, half) > 0) fp_copy(c, T, half);
         wsync();
+        // not below what the working precision can add to lo
+        fp_copy(c, half, hi);
+        wsync();
+        fp_ldexp(half, -(32 * c.nw - 40));
+        if (fp_cmp(c, T, half) < 0) fp_copy(c, T, half);
+        wsync();
         fp_add(c, tr, lo, T, false);
       }
       __syncthreads();
@@ -617,7 +629,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eig(const u32* __restrict__ blk
       __syncthreads();
       if (pd) {
         have_factor = true;
-        cexp = cexp > 2.0f ? cexp - 4.0f : 2.0f;
+        cexp = cexp - 4.0f > 2.0f ? cexp - 4.0f : 2.0f;
       } else {
         have_factor = false;
         cexp += 8.0f;

@@ -94,3 +94,43 @@ def test_not_positive_definite_reports_pivot():
     with pytest.raises(HLError) as e:
         ctx().sync(fac)
     assert e.value.code == HL_ENOTPD and "index 1" in str(e.value)
+
+
+def test_mfma_output_layout():
+    # v_mfma_i32_32x32x32_i8: lane l, register v holds row 8(v/4) + 4(l/32) + v%4, column l%32
+    say("mfma layout")
+    out = ctx().debug_mfma_layout()
+    for v in range(16):
+        for l in range(64):
+            m = 8 * (v // 4) + 4 * (l // 32) + (v % 4)
+            n = l % 32
+            assert out[v * 64 + l] == 32 * (m + 1), (v, l, out[v * 64 + l])
+            assert out[1024 + v * 64 + l] == 32 * (n + 1), (v, l)
+
+
+@pytest.mark.parametrize("beta,N,P,E", [
+    (Fraction(1, 2), 64, 2048, 16),
+    (Fraction(1, 2), 80, 1024, 7),
+    (Fraction(1, 3), 45, 1536, 1),
+    (Fraction(1, 2), 100, 4096, 16),
+])
+def test_factor_mfma_bit_exact_vs_oracle(beta, N, P, E):
+    say("factor mfma", beta, N, P, E)
+    mu = moments(beta, 2 * N - 1)
+    f = C.factor(mu, N, P, E)
+    fac = ctx().factor(mu, N, 8, P, E, "mfma")
+    ctx().sync(fac)
+    _check_factor(fac, f, N)
+
+
+def test_mfma_equals_valu_bitwise_c2b_shape():
+    # beta = 1/2, N = 256 at 8192 bits: both forms of the update give the same bits
+    N, P = 256, 8192
+    say("mfma vs valu", N, P)
+    mu = moments(Fraction(1, 2), 2 * N - 1)
+    fa = ctx().factor(mu, N, 8, P, 16, "mfma")
+    ctx().sync(fa)
+    fb = ctx().factor(mu, N, 8, P, 16, "valu")
+    ctx().sync(fb)
+    import torch
+    assert torch.equal(fa.d, fb.d) and torch.equal(fa.l, fb.l) and torch.equal(fa.h, fb.h)
