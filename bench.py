@@ -1,0 +1,188 @@
+"""Benchmark of the hot path on one MI355X.
+
+A step is one pass of the whole path on one instance: moments resident in HBM
+-> hl_factor (extreme-precision LDL^T of H_N) -> hl_inv_block (first k columns of
+L^-1, k x k block of H^-1) -> hl_lambda_min (lambda_1 and truncation estimate),
+i.e. time-to-lambda_1.
+
+Default workload: beta = 1/2, N = 1024, k = 16, P = 49152 bits, E = 16, Schur
+update as exact int8 MFMA GEMMs.  Prints one JSON line:
+  value        algorithmic Schur limb-MACs of the step / step time (whole job)
+  ms_per_step  time-to-lambda_1
+  roofline     the int8 MFMA GEMM kernel against the int8 dense MFMA peak
+  cpu_baseline the CPU oracle on a bounded sample (leading block of the same
+               matrix at the same precision), also used as a parity check
+  valu_sample  the plain vector-ALU form on the first two panels of the same
+               matrix, checked bit-identical against the MFMA form
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from fractions import Fraction
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "limb-MAC/s in Schur update + time-to-λ₁ at N=1024 β=½ (MFMA-slice vs VALU)"
+
+WORKLOADS = {
+    # name: (beta, N, k, P, E)
+    "c4": (Fraction(1, 2), 1024, 16, 49152, 16),
+    "c2b": (Fraction(1, 2), 256, 8, 8192, 16),
+    "c1": (Fraction(1, 2), 64, 8, 2048, 16),
+    "n512": (Fraction(1, 2), 512, 8, 16384, 16),
+}
+
+MFMA_INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA, MI355X: 5.0 POP/s
+
+
+def schur_limb_macs(N, nl):
+    """Algorithmic limb multiply-adds of the whole Schur update: for every pivot
+    i and every r >= c > i one P x P-bit product, nl^2 limb products each."""
+    return (N - 1) * N * (N + 1) / 6 * nl * nl
+
+
+def cpu_sample(mu, N_s, P, E):
+    """The oracle on the leading N_s x N_s block (same moments, precision and
+    exponent blocks): its pivots and multipliers are exactly the first N_s of
+    the full factorisation."""
+    from oracle import contract as C
+    t = time.time()
+    f = C.factor(mu, N_s, P, E)
+    dt = time.time() - t
+    return f, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--form", default="mfma", choices=["mfma", "valu"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
+    ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
+    ap.add_argument("--cpu-rows", type=int, default=48)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus %d)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from hankel_inputs import moments
+    from paper_1810_01478_amd.api import Context
+
+    beta, N, k, P, E = WORKLOADS[a.workload]
+    nl = P // 32
+    log = lambda *x: print("[bench]", *x, file=sys.stderr, flush=True)
+    ctx = Context(0)
+    mu = moments(beta, 2 * N - 1)
+    packed = ctx.pack_moments(mu)
+    sh = ctx.shape(N, k, P, E, a.form)
+    fac = ctx.alloc(sh)
+    torch.cuda.synchronize()
+
+    # warm-up steps; the first one with per-stage timing
+    stages = None
+    res = None
+    for w in range(max(1, a.warmup)):
+        ctx.set_timing(w == 0)
+        log("warmup step", w)
+        ctx.factor(mu, N, k, P, E, a.form, fac=fac, packed=packed)
+        res = ctx.lambda_min(fac)
+        if w == 0:
+            stages = ctx.timing()
+        ctx.set_timing(False)
+    torch.cuda.synchronize()
+
+    # timed steps
+    log("timed steps", a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.factor(mu, N, k, P, E, a.form, fac=fac, packed=packed)
+        res = ctx.lambda_min(fac)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    macs = schur_limb_macs(N, nl)
+
+    ms = stages["ms"]
+    out = {
+        "metric": METRIC,
+        "value": macs / dt,
+        "unit": "limb-MAC/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8" if a.form == "mfma" else "u32",
+        "data": "synthetic: exact moments mu_j = Gamma((j+1)/beta)/beta generated on the host",
+        "config": {"workload": "beta=%s N=%d k=%d P=%d E=%d form=%s" % (beta, N, k, P, E, a.form),
+                   "beta": str(beta), "N": N, "k": k, "prec_bits": P, "exp_block": E, "form": a.form},
+        "time_to_lambda1_s": dt,
+        "lambda1": res["lambda1"],
+        "trunc": res["trunc"],
+        "stages_ms": {"schur": ms[0], "mfma_gemm": ms[6], "panel": ms[1], "load": ms[5], "trsm": ms[2],
+                      "block": ms[3], "eigen": ms[4], "factor_total": ms[7]},
+        "schur": {"limb_macs_algorithmic": macs, "limb_macs_in_updates": stages["schur_limb_macs"],
+                  "kernel_limb_mac_per_s": stages["schur_limb_macs"] / (ms[0] * 1e-3) if ms[0] else None},
+    }
+    if a.form == "mfma" and ms[6] > 0:
+        achieved = 32.0 * stages["schur_limb_macs"] / (ms[6] * 1e-3) / 1e12  # int8 ops: 16 MACs x 2
+        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_INT8_PEAK_TOPS,
+                           "unit": "TFLOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS, "traffic": None,
+                           "kernel": "k_upd_mfma (int8 ops)", "launches": stages["launches"][1],
+                           "avg_launch_ms": ms[6] / max(1, stages["launches"][1])}
+
+    # CPU oracle on a bounded sample, doubling as a parity check of the leading block
+    if not a.no_cpu:
+        Ns = min(a.cpu_rows, N)
+        if Ns < N:
+            Ns -= Ns % E   # whole exponent blocks: the leading block then has the same scales
+        log("cpu oracle sample", Ns)
+        fs, tcpu = cpu_sample(mu, Ns, P, E)
+        ctx.sync(fac)
+        piv = fac.pivots()[:Ns]
+        ok = piv == fs.d and fac.h_list()[:Ns] == fs.h
+        for i in range(Ns - 1):
+            ok = ok and fac.multipliers(i, range(i + 1, Ns)) == [fs.b[i][r] for r in range(i + 1, Ns)]
+        sample_macs = schur_limb_macs(Ns, nl)
+        out["cpu_baseline"] = {"value": sample_macs / tcpu, "unit": "limb-MAC/s", "cores": 1, "kind": "oracle",
+                               "sample": "oracle LDL^T of the leading %dx%d block of the same matrix at P=%d "
+                                         "(Python integers, one thread), %.1f s" % (Ns, Ns, P, tcpu),
+                               "parity_leading_block_bit_exact": bool(ok)}
+    # VALU sample: first two panels of the same matrix in both forms, bitwise
+    if not a.no_valu and N > 32:
+        cols = 32
+        log("valu sample", cols, "columns")
+        other = "valu" if a.form == "mfma" else "mfma"
+        fac2 = ctx.alloc(ctx.shape(N, k, P, E, other))
+        rates = {}
+        for form, f in ((a.form, fac), (other, fac2)):
+            ctx.set_timing(True)
+            ctx.factor_cols(mu, N, k, P, E, form, 0, cols, fac=f, packed=packed)
+            ctx.sync(f)
+            t = ctx.timing()
+            ctx.set_timing(False)
+            rates[form] = t["schur_limb_macs"] / (t["ms"][0] * 1e-3)
+        so, sb = fac.sizes.trail_offset, fac.sizes.trail_bytes
+        same = bool(torch.equal(fac.ws[so:so + sb], fac2.ws[so:so + sb])
+                    and torch.equal(fac.l, fac2.l) and torch.equal(fac.d[:cols * 2 * nl], fac2.d[:cols * 2 * nl]))
+        out["valu_sample"] = {"columns": cols, "mfma_limb_mac_per_s": rates["mfma"],
+                              "valu_limb_mac_per_s": rates["valu"], "mfma_over_valu": rates["mfma"] / rates["valu"],
+                              "bit_identical": same}
+        del fac2
+        torch.cuda.empty_cache()
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

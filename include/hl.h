@@ -77,6 +77,11 @@ typedef struct {
   int32_t NT;             /* N rounded up to a multiple of 32                            */
   int32_t mu_limbs_min;   /* not used (moments may have any width w >= 1)                */
   int32_t reserved;
+  size_t trail_offset;    /* byte offset and size in the workspace of the trailing
+                             matrix kept between hl_factor_cols calls (2P-bit
+                             entries in 32 x 32 tiles); copy it to checkpoint a
+                             factorisation in progress                           */
+  size_t trail_bytes;
   size_t diag_offset;     /* byte offset in the workspace of 64 int32 eigen-step
                              diagnostics: [1], [9] iterations of the two blocks,
                              [16..40), [40..64) per-iteration bracket bits*1000+limbs */
@@ -128,6 +133,17 @@ hl_status hl_factor(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, const i
                     int32_t w, void *ws, size_t ws_bytes, const hl_factor_t *out, void *stream);
 
 /*
+ * hl_factor_cols -- the same for pivots [col_begin, col_end) only: col_begin = 0
+ * also loads H; later calls continue from the trailing matrix kept in ws.  Both
+ * ends must be multiples of 16 (col_end may be N).  hl_factor(...) is
+ * hl_factor_cols(..., 0, N, ...).  Used to time or check part of a
+ * factorisation and to run one in pieces.
+ */
+hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, const int64_t *mu_exp,
+                         int32_t w, void *ws, size_t ws_bytes, const hl_factor_t *out,
+                         int32_t col_begin, int32_t col_end, void *stream);
+
+/*
  * hl_inv_block -- first k columns of L^-1 (Algorithm 4, Section 4.4) and the
  * top-left k x k block of H^-1 (eq. equ:index, Section 4.5).
  *   x        device, NT x k x nl limbs: x_rm at x + (r*k + m)*nl, the scaled
@@ -158,9 +174,11 @@ hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
 
 /* Per-stage device time of the last hl_factor / hl_inv_block / hl_lambda_min on
  * this context, measured with HIP events on the caller's stream when timing is
- * enabled (hl_set_timing(ctx, 1)).  ms[0] Schur update, ms[1] panel (pivots,
- * factor columns, in-panel updates), ms[2] triangular solve, ms[3] block,
- * ms[4] eigen-step, ms[5] load; launches[0] = Schur-update launches. */
+ * enabled (hl_set_timing(ctx, 1); timing synchronises after each stage).
+ * ms[0] Schur update (all its kernels), ms[1] panel (pivots, factor columns,
+ * in-panel updates), ms[2] triangular solve, ms[3] block, ms[4] eigen-step,
+ * ms[5] load, ms[6] the int8 MFMA GEMM kernel alone, ms[7] whole hl_factor;
+ * launches[0] Schur updates, launches[1] MFMA GEMM launches. */
 typedef struct {
   double ms[8];
   int64_t launches[4];

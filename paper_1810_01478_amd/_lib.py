@@ -12,7 +12,7 @@ HL_FORM_MFMA8, HL_FORM_VALU = 0, 1
 STATUS_NAMES = {0: "HL_OK", 1: "HL_EINVAL", 2: "HL_ENOTPD", 3: "HL_EOVERFLOW", 4: "HL_ENOCONV",
                 5: "HL_EHIP", 6: "HL_ENOMEM"}
 
-EXPORTS = ["hl_create", "hl_destroy", "hl_last_error", "hl_get_sizes", "hl_factor", "hl_inv_block",
+EXPORTS = ["hl_create", "hl_destroy", "hl_last_error", "hl_get_sizes", "hl_factor", "hl_factor_cols", "hl_inv_block",
            "hl_lambda_min", "hl_sync", "hl_set_timing", "hl_get_timing", "hl_debug_mul", "hl_debug_recip",
            "hl_debug_mfma_layout"]
 
@@ -27,6 +27,7 @@ class hl_sizes(ctypes.Structure):
                 ("l_words", ctypes.c_size_t), ("x_words", ctypes.c_size_t),
                 ("blk_words", ctypes.c_size_t), ("nl", ctypes.c_int32), ("NT", ctypes.c_int32),
                 ("mu_limbs_min", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("trail_offset", ctypes.c_size_t), ("trail_bytes", ctypes.c_size_t),
                 ("diag_offset", ctypes.c_size_t)]
 
 
@@ -68,6 +69,8 @@ def lib():
             "hl_destroy": [P],
             "hl_get_sizes": [ctypes.POINTER(hl_shape), ctypes.POINTER(hl_sizes)],
             "hl_factor": [P, ctypes.POINTER(hl_shape), P, P, I32, P, SZ, ctypes.POINTER(hl_factor_t), P],
+            "hl_factor_cols": [P, ctypes.POINTER(hl_shape), P, P, I32, P, SZ, ctypes.POINTER(hl_factor_t),
+                               I32, I32, P],
             "hl_inv_block": [P, ctypes.POINTER(hl_shape), ctypes.POINTER(hl_factor_t), P, SZ, P, P, P, P],
             "hl_lambda_min": [P, ctypes.POINTER(hl_shape), P, P, P, SZ, P, P, ctypes.POINTER(hl_lambda_t), P],
             "hl_sync": [P, P, P, ctypes.POINTER(I32)],

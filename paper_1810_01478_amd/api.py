@@ -159,10 +159,24 @@ class Context:
         sh = self.shape(N, k, P, E, form)
         if fac is None:
             fac = self.alloc(sh)
+        fac.shape = sh
         limbs, exps, w = packed if packed is not None else self.pack_moments(mu[:2 * N - 1])
         fac._mu = (limbs, exps, w)
         L.check(L.lib().hl_factor(self.h, ctypes.byref(sh), _ptr(limbs), _ptr(exps), w, _ptr(fac.ws),
                                   fac.ws.numel(), ctypes.byref(fac.views), _stream(stream)))
+        return fac
+
+    def factor_cols(self, mu, N, k, P, E, form, col_begin, col_end, fac: Optional[Factorization] = None,
+                    packed=None, stream=None) -> Factorization:
+        sh = self.shape(N, k, P, E, form)
+        if fac is None:
+            fac = self.alloc(sh)
+        fac.shape = sh
+        limbs, exps, w = packed if packed is not None else self.pack_moments(mu[:2 * N - 1])
+        fac._mu = (limbs, exps, w)
+        L.check(L.lib().hl_factor_cols(self.h, ctypes.byref(sh), _ptr(limbs), _ptr(exps), w, _ptr(fac.ws),
+                                       fac.ws.numel(), ctypes.byref(fac.views), col_begin, col_end,
+                                       _stream(stream)))
         return fac
 
     def sync(self, fac: Factorization, stream=None):

@@ -122,6 +122,8 @@ extern "C" hl_status hl_get_sizes(const hl_shape* sh, hl_sizes* out) {
   out->blk_words = (size_t)dm.k * dm.k * dm.nl;
   out->nl = dm.nl;
   out->NT = dm.NT;
+  out->trail_offset = L.tiles;
+  out->trail_bytes = (size_t)dm.nt * (dm.nt + 1) / 2 * tile_words(dm.nw) * 4;
   out->diag_offset = L.eig;
   return HL_OK;
 }
@@ -199,6 +201,12 @@ static hl_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
 // ---------------------------------------------------------------------------
 extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* mu, const int64_t* mu_exp,
                                int32_t w, void* ws, size_t ws_bytes, const hl_factor_t* out, void* stream) {
+  return hl_factor_cols(ctx, sh, mu, mu_exp, w, ws, ws_bytes, out, 0, sh ? sh->N : 0, stream);
+}
+
+extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint32_t* mu, const int64_t* mu_exp,
+                                    int32_t w, void* ws, size_t ws_bytes, const hl_factor_t* out,
+                                    int32_t col_begin, int32_t col_end, void* stream) {
   if (!ctx) return fail(HL_EINVAL, "null ctx");
   Dims dm;
   hl_status s = make_dims(sh, &dm);
@@ -207,6 +215,8 @@ extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* 
   if (!out || !out->d || !out->h || !out->s || !out->l) return fail(HL_EINVAL, "null factor output");
   Layout L = make_layout(dm);
   if ((s = check_ws(L, ws, ws_bytes)) != HL_OK) return s;
+  if (col_begin < 0 || col_end > dm.N || col_begin > col_end || col_begin % 16 || (col_end % 16 && col_end != dm.N))
+    return fail(HL_EINVAL, "column range [%d, %d) must be panel aligned", col_begin, col_end);
   hipStream_t st = (hipStream_t)stream;
   char* base = (char*)ws;
   DevStatus* dst = (DevStatus*)(base + L.status);
@@ -216,6 +226,7 @@ extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* 
   ctx->t = hl_timing_t{};
 
   Stamp total(ctx, st, 7);
+  if (col_begin == 0) {
   Stamp ld(ctx, st, 5);
   HIPCHK(launch_fill((u32*)dst, 64, 0u, st));
   HIPCHK(launch_fill(out->l, (size_t)dm.N * dm.NT * dm.nl, 0u, st));
@@ -227,9 +238,10 @@ extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* 
   HIPCHK(launch_scales(mu, mu_exp, w, dm.N, dm.E, out->s, dst, st));
   HIPCHK(launch_load(mu, mu_exp, w, out->s, dm, A, dst, st));
   ld.end();
+  }
 
   const size_t ldb = (size_t)dm.NT * dm.nl;
-  for (int i0 = 0; i0 < dm.N; i0 += 16) {
+  for (int i0 = col_begin; i0 < col_end; i0 += 16) {
     const int npan = dm.N - i0 < 16 ? dm.N - i0 : 16;
     Stamp pn(ctx, st, 1);
     for (int il = 0; il < npan; ++il) {
@@ -286,6 +298,7 @@ extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* 
         m.NT = dm.NT;
         m.carry = (long long*)(base + L.carry);
         m.max_ranges = kMaxRanges;
+        m.timing = ctx->timing ? &ctx->t : nullptr;
         e = launch_upd_mfma(m, st);
       } else {
         e = launch_upd_valu(g, st);

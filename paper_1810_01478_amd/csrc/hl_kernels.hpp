@@ -37,6 +37,7 @@ struct MfmaArgs {
   int slices, pad, S, NT;
   long long* carry;   // per (tile, range, entry) carries between limb ranges
   int max_ranges;
+  hl_timing_t* timing;  // host: when set, the GEMM kernel alone is timed into ms[6]
 };
 hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream);
 size_t eig_ws_bytes_impl(int nl, int k);

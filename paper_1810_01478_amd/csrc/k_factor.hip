@@ -390,8 +390,16 @@ hipError_t launch_load(const u32* mu, const i64* mu_exp, int w, const i32* s, co
   return hipGetLastError();
 }
 
+// kernels that may need more than 64 KiB of dynamic LDS (up to the 160 KiB of a CU)
+static hipError_t allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
                         DevStatus* st, hipStream_t stream) {
+  hipError_t e = allow_lds((const void*)k_pivot, pivot_lds_bytes(dm.nl));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pivot, dim3(1), dim3(64), pivot_lds_bytes(dm.nl), stream, A, dm, i, d_out, h_out,
                      omega, ostride, st);
   return hipGetLastError();
@@ -423,6 +431,8 @@ hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out
 hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_omega, i32* h,
                               hipStream_t stream) {
   const int nl = P / 32;
+  hipError_t e = allow_lds((const void*)k_debug_recip, pivot_lds_bytes(nl));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_debug_recip, dim3(1), dim3(64), pivot_lds_bytes(nl), stream, d, nd, P, nl, omega,
                      n_omega, h);
   return hipGetLastError();

@@ -96,8 +96,13 @@ __global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_
   const int8_t* Ub = m.udig + (size_t)(pad - h) * sstride + (size_t)(C * 32 + mm) * 16;
   u32* At = g.A + tri_tile_index(R, C) * tile_words(g.nw);
   i64 carry[16];
+  bool live[16];  // entries of the trailing matrix proper (r >= c, inside the target)
 #pragma unroll
-  for (int v = 0; v < 16; ++v) carry[v] = 0;
+  for (int v = 0; v < 16; ++v) {
+    carry[v] = 0;
+    const int r = R * 32 + mf_row(l, v), c = C * 32 + mf_col(l);
+    live[v] = r >= c && r >= g.r_lo && r < g.r_hi && c >= g.c_lo && c < g.c_hi;
+  }
   const int tb0 = rt.tb[rg], tb1 = rt.tb[rg + 1];
   for (int tb = tb0; tb < tb1; ++tb) {
     const int t0 = MF_T * tb;
@@ -147,6 +152,7 @@ __global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int r = mf_row(l, v), c = mf_col(l);
+      if (!live[v]) continue;
       u32* p = At + in_tile(r, c, 2 * tb);
       const u64 a64 = ((u64)p[1] << 32) | p[0];
       i64 vlo = 0, vhi = 0;
@@ -174,6 +180,10 @@ __global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) {
   if (has_error(m.g.st)) return;
   const int e = threadIdx.x;  // 0..1023
   const int r = e >> 5, c = e & 31;
+  {
+    const int rg = R * 32 + r, cg = C * 32 + c;
+    if (!(rg >= cg && rg >= m.g.r_lo && rg < m.g.r_hi && cg >= m.g.c_lo && cg < m.g.c_hi)) return;
+  }
   u32* At = m.g.A + tri_tile_index(R, C) * tile_words(m.g.nw);
   const long long* cb = m.carry + tri_tile_index(R, C) * (size_t)m.max_ranges * 1024;
   const int nw = m.g.nw;
@@ -292,8 +302,24 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   const int ntiles = ncol * (ncol + 1) / 2;
   RangeTab rt = make_ranges(g.nl, m.S, ntiles);
   if (rt.n > m.max_ranges) return hipErrorInvalidValue;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (m.timing) {
+    (void)hipEventCreate(&ev0);
+    (void)hipEventCreate(&ev1);
+    (void)hipEventRecord(ev0, stream);
+  }
   hipLaunchKernelGGL(k_upd_mfma, dim3(ncol, ncol, rt.n), dim3(64), 0, stream, m, rt, C_lo);
   e = hipGetLastError();
+  if (m.timing) {
+    (void)hipEventRecord(ev1, stream);
+    (void)hipEventSynchronize(ev1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    m.timing->ms[6] += ms;
+    m.timing->launches[1] += 1;
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+  }
   if (e != hipSuccess) return e;
   if (rt.n > 1) {
     hipLaunchKernelGGL(k_carry_fix, dim3(ncol, ncol), dim3(1024), 0, stream, m, rt, C_lo);
