@@ -299,6 +299,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         m.carry = (long long*)(base + L.carry);
         m.max_ranges = kMaxRanges;
         m.timing = ctx->timing ? &ctx->t : nullptr;
+        m.u_rows = dm.NT;
         e = launch_upd_mfma(m, st);
       } else {
         e = launch_upd_valu(g, st);
@@ -362,6 +363,11 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
 
   Stamp ts(ctx, st, 2);
   HIPCHK(launch_fill(ACC, (size_t)dm.nt * tile_words(dm.nw), 0u, st));
+  if (sh->form == HL_FORM_MFMA8) {
+    // digit slices outside [0, S) must read as zero whatever ran before
+    HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
+    HIPCHK(launch_fill((u32*)(base + L.udig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
+  }
   for (int R0 = 0; R0 < dm.N; R0 += 16) {
     const int nb = dm.N - R0 < 16 ? dm.N - R0 : 16;
     for (int j = 0; j < nb; ++j) {
@@ -404,7 +410,23 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
       g.c_lo = 0;
       g.c_hi = dm.k;
       g.st = dst;
-      HIPCHK(launch_upd_valu(g, st));
+      if (sh->form == HL_FORM_MFMA8) {
+        MfmaArgs m{};
+        m.g = g;
+        m.bdig = (int8_t*)(base + L.bdig);
+        m.udig = (int8_t*)(base + L.udig);
+        m.slices = L.digit_slices;
+        m.pad = kDigitPad;
+        m.S = dm.S;
+        m.NT = dm.NT;
+        m.carry = (long long*)(base + L.carry);
+        m.max_ranges = kMaxRanges;
+        m.timing = nullptr;
+        m.u_rows = dm.k;
+        HIPCHK(launch_upd_mfma(m, st));
+      } else {
+        HIPCHK(launch_upd_valu(g, st));
+      }
     }
   }
   ts.end();

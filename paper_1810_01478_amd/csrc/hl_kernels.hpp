@@ -38,6 +38,7 @@ struct MfmaArgs {
   long long* carry;   // per (tile, range, entry) carries between limb ranges
   int max_ranges;
   hl_timing_t* timing;  // host: when set, the GEMM kernel alone is timed into ms[6]
+  int u_rows;           // rows of the u operand (NT for the Schur update, k for X)
 };
 hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream);
 size_t eig_ws_bytes_impl(int nl, int k);

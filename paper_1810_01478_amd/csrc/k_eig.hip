@@ -24,7 +24,7 @@
 
 namespace hl {
 
-constexpr int EIG_WAVES = 4;
+constexpr int EIG_WAVES = 8;
 constexpr int EIG_THREADS = EIG_WAVES * WAVE;
 constexpr int EIG_MAXIT = 400;
 constexpr int EIG_NSCAL = 24;
@@ -690,6 +690,10 @@ hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* s
   int* hdr = flags + 64;
   u32* mant = (u32*)(hdr + 2 * 2 * per);
   const size_t lds = (size_t)(16 + EIG_WAVES * 2 * (NWM + 8)) * 4;
+  if (lds > 65536) {
+    hipError_t e0 = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e0 != hipSuccess) return e0;
+  }
   hipLaunchKernelGGL(k_eig, dim3(dm.k >= 2 ? 2 : 1), dim3(EIG_THREADS), lds, stream, blk, dm.k, dm.nl, dm.P, NWM,
                      hdr, mant, per, flags, st);
   hipError_t e = hipGetLastError();

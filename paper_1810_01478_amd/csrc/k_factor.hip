@@ -124,6 +124,9 @@ __device__ void add_i32(u32* x, int n, int d) {
 
 __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_omega, u32* lds,
                                 int nl) {
+  // every thread of the block calls this: the products use all waves, the
+  // other steps run on wave 0 between barriers
+  const bool w0 = wave_id() == 0;
   PivotOut res{0, 1};
   const int NB = nl + 8;
   u32* D = lds;            // d~
@@ -133,22 +136,23 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   u32* Z = dq + NB;
   u32* T = Z + NB;         // 2 NB
   u32* T2 = T + 2 * NB;    // 2 NB
+  u32* colbuf = T2 + 2 * NB;  // 6 NB: column sums of g_mul
   const int Ld = w_bitlen(d, nw);
   const int h = Ld / 2;
   res.h = h;
   const long m = Ld - (long)P - 64 > 0 ? Ld - (long)P - 64 : 0;
   const int nd = nl + 2;
-  w_shift_right(d, nw, m, D, nd);
+  if (w0) w_shift_right(d, nw, m, D, nd);
   __syncthreads();
   const int LD = w_bitlen(D, nd);
   const long e = 2L * h + P - m;
   const long pf = e - LD + 40;   // final precision of y
   // initial 30-bit estimate from the top 32 bits of D
-  {
+  if (w0) {
     const u32 dtop = LD >= 32 ? limb_shr(D, nd, LD - 32, 0) : limb_shl(D, nd, 32 - LD, 0);
     const u64 y0 = ((u64)1 << 62) / (u64)dtop;
     if (lane_id() == 0) Y[0] = (u32)y0;
-    for (int p = 1 + lane_id(); p < NB; p += WAVE) Y[p] = 0;
+    for (int p2 = 1 + lane_id(); p2 < NB; p2 += WAVE) Y[p2] = 0;
   }
   __syncthreads();
   long p = 30;
@@ -159,18 +163,18 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
     const long q = pn + 8;
     const int nq = (int)(q / 32) + 2;
     // dq = floor(D * 2^(q - LD))
-    w_shift_right(D, nd, LD - q, dq, nq);
+    if (w0) w_shift_right(D, nd, LD - q, dq, nq);
     __syncthreads();
     // T = dq * Y
     const int nT = nq + ny;
-    w_mul(dq, nq, Y, ny, T, nT);
-    __syncthreads();
+    g_mul(dq, nq, Y, ny, T, nT, colbuf);
     // E = 2^(p+q) - T  (two's complement over nT + 1 limbs)
     const int nE = nT + 1;
-    sub_from_pow2(p + q, T, nT, T, nE);
+    if (w0) sub_from_pow2(p + q, T, nT, T, nE);
     __syncthreads();
     const bool neg = (T[nE - 1] >> 31) != 0;
-    if (neg) w_neg(T, nE);
+    __syncthreads();
+    if (w0 && neg) w_neg(T, nE);
     __syncthreads();
     // T2 = Y * |E|, then shifted
     int ne = (w_bitlen(T, nE) + 31) / 32;
@@ -180,91 +184,98 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
       break;
     }
     const int nT2 = ny + ne;
-    w_mul(Y, ny, T, ne, T2, nT2);
-    __syncthreads();
+    g_mul(Y, ny, T, ne, T2, nT2, colbuf);
     const int nyn = (int)((pn + 2) / 32) + 2;
     // Yn = Y << (pn - p);   Z = T2 >> (2p + q - pn)
-    w_shift_right(Y, ny, -(pn - p), Yn, nyn);
-    w_shift_right(T2, nT2, 2 * p + q - pn, Z, nyn);
-    __syncthreads();
-    if (neg) {
-      w_sub(Yn, Z, Y, nyn);
-    } else {
-      w_add(Yn, nyn, Z, nyn, Y, nyn);
+    if (w0) {
+      w_shift_right(Y, ny, -(pn - p), Yn, nyn);
+      w_shift_right(T2, nT2, 2 * p + q - pn, Z, nyn);
     }
     __syncthreads();
-    for (int j = nyn + lane_id(); j < NB; j += WAVE) Y[j] = 0;
+    if (w0) {
+      if (neg) {
+        w_sub(Yn, Z, Y, nyn);
+      } else {
+        w_add(Yn, nyn, Z, nyn, Y, nyn);
+      }
+      for (int j = nyn + lane_id(); j < NB; j += WAVE) Y[j] = 0;
+    }
+    __syncthreads();
     ny = nyn;
     p = pn;
-    __syncthreads();
   }
   // Z = Y >> (pf - (e - LD))  ~ 2^e / D
   const int nz = nl + 3;
-  w_shift_right(Y, ny, pf - (e - LD), Z, nz);
+  if (w0) w_shift_right(Y, ny, pf - (e - LD), Z, nz);
   __syncthreads();
   // R = 2^e - Z D, exact, over nR limbs
   const int nR = (int)(e / 32) + 3;
-  w_mul(Z, nz, D, nd, T, nR);
-  __syncthreads();
-  sub_from_pow2(e, T, nR, T, nR);
-  __syncthreads();
-  // T2 = D zero-extended to nR
-  for (int j = lane_id(); j < nR; j += WAVE) T2[j] = j < nd ? D[j] : 0u;
+  g_mul(Z, nz, D, nd, T, nR, colbuf);
+  if (w0) {
+    sub_from_pow2(e, T, nR, T, nR);
+    // T2 = D zero-extended to nR (and zero up to NB for the comparison below)
+    for (int j = lane_id(); j < (nR > NB ? nR : NB); j += WAVE) T2[j] = j < nd ? D[j] : 0u;
+  }
   __syncthreads();
   int guard = 0;
   while (true) {
     const bool rneg = (T[nR - 1] >> 31) != 0;
+    const int cmp = rneg ? 0 : w_cmp(T, T2, nR);
+    __syncthreads();
     if (rneg) {
-      add_i32(Z, nz, -1);
-      __syncthreads();
-      w_add(T, nR, T2, nR, T, nR);
-      __syncthreads();
-    } else if (w_cmp(T, T2, nR) >= 0) {
-      add_i32(Z, nz, 1);
-      __syncthreads();
-      w_sub(T, T2, T, nR);
-      __syncthreads();
+      if (w0) {
+        add_i32(Z, nz, -1);
+        w_add(T, nR, T2, nR, T, nR);
+      }
+    } else if (cmp >= 0) {
+      if (w0) {
+        add_i32(Z, nz, 1);
+        w_sub(T, T2, T, nR);
+      }
     } else {
       break;
     }
+    __syncthreads();
     if (++guard > 16) {
       res.ok = 0;
       break;
     }
   }
   // omega = Z + [2R >= D]
-  w_shift_right(T, nR, -1, Yn, nR > NB ? NB : nR);  // 2R fits: R < D < 2^(P+64)
-  __syncthreads();
-  for (int j = nd + lane_id(); j < NB; j += WAVE) T2[j] = 0;
+  if (w0) w_shift_right(T, nR, -1, Yn, nR > NB ? NB : nR);  // 2R fits: R < D < 2^(P+64)
   __syncthreads();
   const bool up = w_cmp(Yn, T2, nd + 1) >= 0;
-  if (up) add_i32(Z, nz, 1);
   __syncthreads();
-  for (int j = lane_id(); j < n_omega; j += WAVE) omega[j] = j < nz ? Z[j] : 0u;
+  if (w0) {
+    if (up) add_i32(Z, nz, 1);
+    for (int j = lane_id(); j < n_omega; j += WAVE) omega[j] = j < nz ? Z[j] : 0u;
+  }
   __syncthreads();
   return res;
 }
 
 // One wave: pivot i of the trailing matrix.
-__global__ __launch_bounds__(64) void k_pivot(u32* __restrict__ A, Dims dm, int i,
-                                              u32* __restrict__ d_out, i32* __restrict__ h_out,
-                                              u32* __restrict__ omega_tab, int omega_stride,
-                                              DevStatus* st) {
+constexpr int PIVOT_THREADS = 1024;
+
+__global__ __launch_bounds__(PIVOT_THREADS) void k_pivot(u32* __restrict__ A, Dims dm, int i,
+                                                         u32* __restrict__ d_out, i32* __restrict__ h_out,
+                                                         u32* __restrict__ omega_tab, int omega_stride,
+                                                         DevStatus* st) {
   if (has_error(st)) return;
   extern __shared__ u32 lds[];
   const int nw = dm.nw, nl = dm.nl;
-  u32* dl = lds + 9 * (nl + 8);
+  u32* dl = lds + 15 * (nl + 8);
   const u32* src = A + tri_tile_index(i >> 5, i >> 5) * tile_words(nw);
-  for (int l = lane_id(); l < nw; l += WAVE) dl[l] = src[in_tile(i, i, l)];
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) dl[l] = src[in_tile(i, i, l)];
   __syncthreads();
   const bool neg = (dl[nw - 1] >> 31) != 0;
   if (neg || w_is_zero(dl, nw)) {
-    if (lane_id() == 0) set_status(st, HL_ENOTPD, i);
+    if (threadIdx.x == 0) set_status(st, HL_ENOTPD, i);
     return;
   }
-  for (int l = lane_id(); l < nw; l += WAVE) d_out[(size_t)i * nw + l] = dl[l];
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) d_out[(size_t)i * nw + l] = dl[l];
   PivotOut po = pivot_recip(dl, nw, dm.P, omega_tab + (size_t)i * omega_stride, omega_stride, lds, nl);
-  if (lane_id() == 0) {
+  if (threadIdx.x == 0) {
     h_out[i] = po.h;
     if (!po.ok) set_status(st, HL_ENOCONV, i);
   }
@@ -361,19 +372,19 @@ __global__ __launch_bounds__(64) void k_debug_mul(const u32* a, int na, const u3
   w_mul(a, na, b, nb, out, nout);
 }
 
-__global__ __launch_bounds__(64) void k_debug_recip(const u32* d, int nd, int P, int nl, u32* omega,
-                                                    int n_omega, i32* h) {
+__global__ __launch_bounds__(PIVOT_THREADS) void k_debug_recip(const u32* d, int nd, int P, int nl, u32* omega,
+                                                               int n_omega, i32* h) {
   extern __shared__ u32 lds[];
-  u32* dl = lds + 9 * (nl + 8);
-  for (int l = lane_id(); l < 2 * nl; l += WAVE) dl[l] = l < nd ? d[l] : 0u;
+  u32* dl = lds + 15 * (nl + 8);
+  for (int l = threadIdx.x; l < 2 * nl; l += blockDim.x) dl[l] = l < nd ? d[l] : 0u;
   __syncthreads();
   PivotOut po = pivot_recip(dl, 2 * nl, P, omega, n_omega, lds, nl);
-  if (lane_id() == 0) h[0] = po.ok ? po.h : -1;
+  if (threadIdx.x == 0) h[0] = po.ok ? po.h : -1;
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
-size_t pivot_lds_bytes(int nl) { return (size_t)(9 * (nl + 8) + 2 * nl + 8) * 4; }
+size_t pivot_lds_bytes(int nl) { return (size_t)(15 * (nl + 8) + 2 * nl + 8) * 4; }
 size_t col_lds_bytes(int nl) { return (size_t)(2 * nl + 4 + 3 * (nl + 4)) * 4; }
 
 hipError_t launch_scales(const u32* mu, const i64* mu_exp, int w, int N, int E, i32* s, DevStatus* st,
@@ -400,7 +411,7 @@ hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u
                         DevStatus* st, hipStream_t stream) {
   hipError_t e = allow_lds((const void*)k_pivot, pivot_lds_bytes(dm.nl));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(64), pivot_lds_bytes(dm.nl), stream, A, dm, i, d_out, h_out,
+  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(PIVOT_THREADS), pivot_lds_bytes(dm.nl), stream, A, dm, i, d_out, h_out,
                      omega, ostride, st);
   return hipGetLastError();
 }
@@ -433,7 +444,7 @@ hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_ome
   const int nl = P / 32;
   hipError_t e = allow_lds((const void*)k_debug_recip, pivot_lds_bytes(nl));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_debug_recip, dim3(1), dim3(64), pivot_lds_bytes(nl), stream, d, nd, P, nl, omega,
+  hipLaunchKernelGGL(k_debug_recip, dim3(1), dim3(PIVOT_THREADS), pivot_lds_bytes(nl), stream, d, nd, P, nl, omega,
                      n_omega, h);
   return hipGetLastError();
 }

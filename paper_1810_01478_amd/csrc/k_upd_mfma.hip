@@ -46,7 +46,7 @@ __device__ __forceinline__ int mf_col(int l) { return l & 31; }
 // ---------------------------------------------------------------------------
 // Recode the panel factors (two's complement, nl limbs) into balanced digits.
 // src: [16][NT][nl] limbs; dst: [slices][NT][16] bytes, slice = digit + pad.
-__global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int NT, int nl, int pad,
+__global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows, int nl, int pad,
                          int8_t* __restrict__ dst) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int il = gid & 15, row = gid >> 4;
@@ -54,7 +54,7 @@ __global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int 
   const int S = 4 * nl;
   const size_t rstride = (size_t)NT * 16;
   int8_t* d = dst + (size_t)pad * rstride + (size_t)row * 16 + il;
-  if (il >= npan) {
+  if (il >= npan || row >= nrows) {
     for (int j = 0; j < S; ++j) d[(size_t)j * rstride] = 0;
     return;
   }
@@ -83,25 +83,29 @@ __global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int 
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo) {
   const UpdArgs& g = m.g;
-  const int R = C_lo + blockIdx.x, C = C_lo + blockIdx.y, rg = blockIdx.z;
-  if (R < C || R * 32 >= m.NT) return;
+  // triangular target: tiles (R, C), C_lo <= C <= R; rectangular: rows from
+  // C_lo (here the first tile row), all g.ntc tile columns
+  const int R = C_lo + blockIdx.x, C = g.tri ? C_lo + blockIdx.y : blockIdx.y, rg = blockIdx.z;
+  if ((g.tri && R < C) || R * 32 >= m.NT) return;
+  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   if (has_error(g.st)) return;
+  __shared__ i64 carry_s[16 * WAVE];  // carry of each of the lane's 16 entries
   const int l = lane_id(), h = l >> 5, mm = l & 31;
   const int S = m.S, NT = m.NT, pad = m.pad;
-  const size_t sstride = (size_t)NT * 16;  // bytes per digit slice
+  const long sstride = (long)NT * 16;  // bytes per digit slice
   // A operand (b digits of tile rows), B operand (u digits of tile columns)
-  const int8_t* Ab = m.bdig + (size_t)(pad + h) * sstride + (size_t)(R * 32 + mm) * 16;
-  const int8_t* Ub = m.udig + (size_t)(pad - h) * sstride + (size_t)(C * 32 + mm) * 16;
-  u32* At = g.A + tri_tile_index(R, C) * tile_words(g.nw);
-  i64 carry[16];
-  bool live[16];  // entries of the trailing matrix proper (r >= c, inside the target)
+  const int8_t* Ab = m.bdig + (long)(pad + h) * sstride + (long)(R * 32 + mm) * 16;
+  const int8_t* Ub = m.udig + (long)(pad - h) * sstride + (long)(C * 32 + mm) * 16;
+  u32* At = g.A + tix * tile_words(g.nw);
+  unsigned live = 0;  // entries of the trailing matrix proper (r >= c, inside the target)
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    carry[v] = 0;
+    carry_s[v * WAVE + l] = 0;
     const int r = R * 32 + mf_row(l, v), c = C * 32 + mf_col(l);
-    live[v] = r >= c && r >= g.r_lo && r < g.r_hi && c >= g.c_lo && c < g.c_hi;
+    if ((!g.tri || r >= c) && r >= g.r_lo && r < g.r_hi && c >= g.c_lo && c < g.c_hi) live |= 1u << v;
   }
   const int tb0 = rt.tb[rg], tb1 = rt.tb[rg + 1];
   for (int tb = tb0; tb < tb1; ++tb) {
@@ -114,17 +118,23 @@ __global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_
     jlo &= ~1;
     int jhi = t0 + MF_T - 1;
     if (jhi > S - 1) jhi = S - 1;
+    // steps of two digits, padded to whole rotations of the register window;
+    // the extra steps pair A digits with zero B padding (or the reverse) and
+    // add nothing
     const int nsteps = (jhi - jlo) / 2 + 1;
-    // window: slice x = t0 + q - j0 - h sits at Ub + x * sstride
-    const int8_t* ub0 = Ub + (long)(t0 - jlo) * (long)sstride;
+    const int nrot = (nsteps + 4) / 5;
+    // window: slice x = t0 + q - j0 - h sits at Ub + (t0 + q - j0) * sstride
+    const int8_t* ub0 = Ub + (long)(t0 - jlo) * sstride;
     v4i w0 = ld16(ub0 + 0 * sstride), w1 = ld16(ub0 + 1 * sstride), w2 = ld16(ub0 + 2 * sstride),
         w3 = ld16(ub0 + 3 * sstride), w4 = ld16(ub0 + 4 * sstride), w5 = ld16(ub0 + 5 * sstride),
         w6 = ld16(ub0 + 6 * sstride), w7 = ld16(ub0 + 7 * sstride), w8, w9;
-    const int8_t* ap = Ab + (size_t)jlo * sstride;
-    const int8_t* un = ub0 - 2 * (long)sstride;  // next window's slices 0, 1
+    const int8_t* ap = Ab + (long)jlo * sstride;
+    const int8_t* un = ub0 - 2 * sstride;  // next window's slices 0, 1
+    v4i an = ld16(ap);                    // A of the current step, loaded one step ahead
 #define MF_STEP(P0, P1, P2, P3, P4, P5, P6, P7, N0, N1)                                   \
   {                                                                                       \
-    const v4i a = ld16(ap);                                                               \
+    const v4i a = an;                                                                     \
+    an = ld16(ap + 2 * sstride);                                                          \
     N0 = ld16(un);                                                                        \
     N1 = ld16(un + sstride);                                                              \
     acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P0, acc[0], 0, 0, 0);               \
@@ -136,11 +146,11 @@ __global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_
     acc[6] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P6, acc[6], 0, 0, 0);               \
     acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P7, acc[7], 0, 0, 0);               \
     ap += 2 * sstride;                                                                    \
-    un -= 2 * (long)sstride;                                                              \
-    if (++s >= nsteps) break;                                                             \
+    un -= 2 * sstride;                                                                    \
+    __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);                                    \
+    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);                                    \
   }
-    int s = 0;
-    while (true) {
+    for (int rot = 0; rot < nrot; ++rot) {
       MF_STEP(w0, w1, w2, w3, w4, w5, w6, w7, w8, w9)
       MF_STEP(w8, w9, w0, w1, w2, w3, w4, w5, w6, w7)
       MF_STEP(w6, w7, w8, w9, w0, w1, w2, w3, w4, w5)
@@ -151,8 +161,8 @@ __global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_
     // fold the 8 digit sums of each entry into limbs 2 tb, 2 tb + 1
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
+      if (!((live >> v) & 1u)) continue;
       const int r = mf_row(l, v), c = mf_col(l);
-      if (!live[v]) continue;
       u32* p = At + in_tile(r, c, 2 * tb);
       const u64 a64 = ((u64)p[1] << 32) | p[0];
       i64 vlo = 0, vhi = 0;
@@ -160,32 +170,34 @@ __global__ __launch_bounds__(64) void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_
       for (int q = 0; q < 4; ++q) vlo += (i64)acc[q][v] << (8 * q);
 #pragma unroll
       for (int q = 4; q < 8; ++q) vhi += (i64)acc[q][v] << (8 * (q - 4));
-      __int128 X = (__int128)a64 - (__int128)vlo - ((__int128)vhi << 32) + (__int128)carry[v];
+      __int128 X = (__int128)a64 - (__int128)vlo - ((__int128)vhi << 32) + (__int128)carry_s[v * WAVE + l];
       const u64 nl64 = (u64)X;
       p[0] = (u32)nl64;
       p[1] = (u32)(nl64 >> 32);
-      carry[v] = (i64)(X >> 64);
+      carry_s[v * WAVE + l] = (i64)(X >> 64);
     }
   }
   // carries out of this range
-  long long* cb = m.carry + (tri_tile_index(R, C) * (size_t)m.max_ranges + rg) * 1024;
+  long long* cb = m.carry + (tix * (size_t)m.max_ranges + rg) * 1024;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry[v];
+  for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry_s[v * WAVE + l];
 }
 
 // Add the carries of range w at limb 2 tb[w+1] of every entry, w = 0..n-2.
 __global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) {
-  const int R = C_lo + blockIdx.x, C = C_lo + blockIdx.y;
-  if (R < C || R * 32 >= m.NT) return;
-  if (has_error(m.g.st)) return;
+  const UpdArgs& g = m.g;
+  const int R = C_lo + blockIdx.x, C = g.tri ? C_lo + blockIdx.y : blockIdx.y;
+  if ((g.tri && R < C) || R * 32 >= m.NT) return;
+  if (has_error(g.st)) return;
+  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   const int e = threadIdx.x;  // 0..1023
   const int r = e >> 5, c = e & 31;
   {
     const int rg = R * 32 + r, cg = C * 32 + c;
-    if (!(rg >= cg && rg >= m.g.r_lo && rg < m.g.r_hi && cg >= m.g.c_lo && cg < m.g.c_hi)) return;
+    if (!((!g.tri || rg >= cg) && rg >= g.r_lo && rg < g.r_hi && cg >= g.c_lo && cg < g.c_hi)) return;
   }
-  u32* At = m.g.A + tri_tile_index(R, C) * tile_words(m.g.nw);
-  const long long* cb = m.carry + tri_tile_index(R, C) * (size_t)m.max_ranges * 1024;
+  u32* At = g.A + tix * tile_words(g.nw);
+  const long long* cb = m.carry + tix * (size_t)m.max_ranges * 1024;
   const int nw = m.g.nw;
   for (int w = 0; w + 1 < rt.n; ++w) {
     const i64 cv = cb[(size_t)w * 1024 + e];
@@ -280,11 +292,11 @@ static RangeTab make_ranges(int nl, int S, int ntiles) {
   return rt;
 }
 
-hipError_t launch_recode(const u32* src, size_t lds, int npan, int NT, int nl, int pad, int8_t* dst,
+hipError_t launch_recode(const u32* src, size_t lds, int npan, int NT, int nrows, int nl, int pad, int8_t* dst,
                          hipStream_t stream) {
   const int threads = NT * 16;
-  hipLaunchKernelGGL(k_recode, dim3((threads + 255) / 256), dim3(256), 0, stream, src, lds, npan, NT, nl, pad,
-                     dst);
+  hipLaunchKernelGGL(k_recode, dim3((threads + 255) / 256), dim3(256), 0, stream, src, lds, npan, NT, nrows, nl,
+                     pad, dst);
   return hipGetLastError();
 }
 
@@ -292,14 +304,22 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   const UpdArgs& g = m.g;
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
   // digits of the panel: b from the multiplier array, u from the panel buffer
-  hipError_t e = launch_recode(g.Bop, g.ldb, g.npan, m.NT, g.nl, m.pad, m.bdig, stream);
+  hipError_t e = launch_recode(g.Bop, g.ldb, g.npan, m.NT, m.NT, g.nl, m.pad, m.bdig, stream);
   if (e != hipSuccess) return e;
-  e = launch_recode(g.Uop, g.ldu, g.npan, m.NT, g.nl, m.pad, m.udig, stream);
+  e = launch_recode(g.Uop, g.ldu, g.npan, m.NT, m.u_rows, g.nl, m.pad, m.udig, stream);
   if (e != hipSuccess) return e;
-  const int C_lo = g.c_lo / 32;
   const int nt = m.NT / 32;
-  const int ncol = nt - C_lo;
-  const int ntiles = ncol * (ncol + 1) / 2;
+  int C_lo, nrow, ncol, ntiles;
+  if (g.tri) {
+    C_lo = g.c_lo / 32;
+    nrow = ncol = nt - C_lo;
+    ntiles = ncol * (ncol + 1) / 2;
+  } else {
+    C_lo = g.r_lo / 32;  // first tile row of the rectangular target
+    nrow = nt - C_lo;
+    ncol = g.ntc;
+    ntiles = nrow * ncol;
+  }
   RangeTab rt = make_ranges(g.nl, m.S, ntiles);
   if (rt.n > m.max_ranges) return hipErrorInvalidValue;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -308,7 +328,7 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
     (void)hipEventCreate(&ev1);
     (void)hipEventRecord(ev0, stream);
   }
-  hipLaunchKernelGGL(k_upd_mfma, dim3(ncol, ncol, rt.n), dim3(64), 0, stream, m, rt, C_lo);
+  hipLaunchKernelGGL(k_upd_mfma, dim3(nrow, ncol, rt.n), dim3(64), 0, stream, m, rt, C_lo);
   e = hipGetLastError();
   if (m.timing) {
     (void)hipEventRecord(ev1, stream);
@@ -322,7 +342,7 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   }
   if (e != hipSuccess) return e;
   if (rt.n > 1) {
-    hipLaunchKernelGGL(k_carry_fix, dim3(ncol, ncol), dim3(1024), 0, stream, m, rt, C_lo);
+    hipLaunchKernelGGL(k_carry_fix, dim3(nrow, ncol), dim3(1024), 0, stream, m, rt, C_lo);
     e = hipGetLastError();
   }
   return e;

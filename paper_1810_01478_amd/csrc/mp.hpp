@@ -282,4 +282,47 @@ __device__ __forceinline__ u32 get_bit(const u32* x, int n, long s) {
   return (x[q] >> (s & 31)) & 1u;
 }
 
+// ---------------------------------------------------------------------------
+// Workgroup-level product: the waves of the block form the column sums of
+// interleaved 64-column chunks into LDS (3 words per column), then wave 0
+// turns them into limbs.  All threads of the block must call it.
+// colbuf: 3 * nout words of LDS.  out may not alias a or b.
+__device__ __forceinline__ void g_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout,
+                                      u32* colbuf) {
+  const int w = wave_id(), nwv = blockDim.x / WAVE, l = lane_id();
+  const int nch = (nout + WAVE - 1) / WAVE;
+  for (int ch = w; ch < nch; ch += nwv) {
+    const int t = ch * WAVE + l;
+    u64 lo = 0;
+    u32 hi = 0;
+    if (t < na + nb - 1) {
+      int x0 = t - (nb - 1);
+      if (x0 < 0) x0 = 0;
+      const int x1 = t < na - 1 ? t : na - 1;
+      col_sum(a, b, t, x0, x1, lo, hi);
+    }
+    if (t < nout) {
+      colbuf[3 * t] = (u32)lo;
+      colbuf[3 * t + 1] = (u32)(lo >> 32);
+      colbuf[3 * t + 2] = hi;
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    u32 carry = 0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int p = ch * WAVE + l;
+      u64 v = 0;
+      if (p < nout) {
+        v = colbuf[3 * p];
+        if (p >= 1) v += colbuf[3 * (p - 1) + 1];
+        if (p >= 2) v += colbuf[3 * (p - 2) + 2];
+      }
+      const u32 limb = w_resolve(v, carry);
+      if (p < nout) out[p] = limb;
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace hl
