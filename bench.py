@@ -45,6 +45,22 @@ def schur_limb_macs(N, nl):
     return (N - 1) * N * (N + 1) / 6 * nl * nl
 
 
+def measured_traffic(workload):
+    """HBM traffic per trailing-update launch from the rocprofv3 counter runs
+    recorded under profiles/, if they were taken on this workload and on the
+    kernel source as it is now; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_upd_mfma_c4_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def cpu_sample(mu, N_s, P, E):
     """The oracle on the leading N_s x N_s block (same moments, precision and
     exponent blocks): its pivots and multipliers are exactly the first N_s of
@@ -66,6 +82,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
     ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--progress", action="store_true",
+                    help="factor in pieces of 128 columns, printing a line after each (profiler runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device three times (calibrates HBM byte counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus %d)" % a.gpus,
@@ -73,6 +93,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if a.copy_probe:
+        n = 1 << 30
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}), flush=True)
+        return
     from hankel_inputs import moments
     from paper_1810_01478_amd.api import Context
 
@@ -86,16 +116,44 @@ def main():
     fac = ctx.alloc(sh)
     torch.cuda.synchronize()
 
+    def step(timed_stages):
+        """One pass of the path.  With --progress the factorisation runs in
+        pieces of 128 columns with a line after each (for profiler runs, which
+        serialise every launch); the per-stage times are then summed."""
+        if not a.progress:
+            ctx.factor(mu, N, k, P, E, a.form, fac=fac, packed=packed)
+            r = ctx.lambda_min(fac)
+            return r, (ctx.timing() if timed_stages else None)
+        acc = None
+        for c0 in range(0, N, 128):
+            c1 = min(N, c0 + 128)
+            ctx.factor_cols(mu, N, k, P, E, a.form, c0, c1, fac=fac, packed=packed)
+            if timed_stages:
+                t = ctx.timing()
+                if acc is None:
+                    acc = t
+                else:
+                    acc["ms"] = [x + y for x, y in zip(acc["ms"], t["ms"])]
+                    acc["launches"] = [x + y for x, y in zip(acc["launches"], t["launches"])]
+                    acc["schur_limb_macs"] += t["schur_limb_macs"]
+            log("columns", c0, c1)
+        r = ctx.lambda_min(fac)
+        if timed_stages:
+            t = ctx.timing()
+            for i in (2, 3, 4):
+                acc["ms"][i] = t["ms"][i]
+        log("lambda_min done")
+        return r, acc
+
     # warm-up steps; the first one with per-stage timing
     stages = None
     res = None
     for w in range(max(1, a.warmup)):
         ctx.set_timing(w == 0)
         log("warmup step", w)
-        ctx.factor(mu, N, k, P, E, a.form, fac=fac, packed=packed)
-        res = ctx.lambda_min(fac)
+        res, t = step(w == 0)
         if w == 0:
-            stages = ctx.timing()
+            stages = t
         ctx.set_timing(False)
     torch.cuda.synchronize()
 
@@ -104,13 +162,13 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        ctx.factor(mu, N, k, P, E, a.form, fac=fac, packed=packed)
-        res = ctx.lambda_min(fac)
+        res, _t = step(False)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
     macs = schur_limb_macs(N, nl)
 
     ms = stages["ms"]
+    workload = "beta=%s N=%d k=%d P=%d E=%d form=%s" % (beta, N, k, P, E, a.form)
     out = {
         "metric": METRIC,
         "value": macs / dt,
@@ -124,7 +182,7 @@ def main():
         "vs_baseline": None,
         "dtype": "i8" if a.form == "mfma" else "u32",
         "data": "synthetic: exact moments mu_j = Gamma((j+1)/beta)/beta generated on the host",
-        "config": {"workload": "beta=%s N=%d k=%d P=%d E=%d form=%s" % (beta, N, k, P, E, a.form),
+        "config": {"workload": workload,
                    "beta": str(beta), "N": N, "k": k, "prec_bits": P, "exp_block": E, "form": a.form},
         "time_to_lambda1_s": dt,
         "lambda1": res["lambda1"],
@@ -137,7 +195,8 @@ def main():
     if a.form == "mfma" and ms[6] > 0:
         achieved = 32.0 * stages["schur_limb_macs"] / (ms[6] * 1e-3) / 1e12  # int8 ops: 16 MACs x 2
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_INT8_PEAK_TOPS,
-                           "unit": "TFLOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS, "traffic": None,
+                           "unit": "TFLOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
+                           "traffic": measured_traffic(workload),
                            "kernel": "k_upd_mfma (int8 ops)", "launches": stages["launches"][1],
                            "avg_launch_ms": ms[6] / max(1, stages["launches"][1])}
 

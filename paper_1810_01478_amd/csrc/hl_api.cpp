@@ -91,7 +91,16 @@ Layout make_layout(const Dims& dm) {
   L.udig = off;
   off += al((size_t)L.digit_slices * dm.NT * 16);
   L.carry = off;
-  off += al((size_t)kMaxRanges * dm.nt * (dm.nt + 1) / 2 * 1024 * 8);
+  {
+    // one carry slot of 1024 entries per work item (tile x limb range) of an
+    // MFMA launch; the range count is chosen within this capacity
+    const size_t tri = (size_t)dm.nt * (dm.nt + 1) / 2;
+    const size_t rect = (size_t)dm.nt * ((dm.k + 31) / 32);
+    const size_t tiles = tri > rect ? tri : rect;
+    const size_t useful = tiles * (size_t)(kMaxRanges < dm.nl / 2 ? kMaxRanges : dm.nl / 2);
+    L.carry_tiles = 16384 + tiles < useful ? 16384 + tiles : useful;
+    off += al(L.carry_tiles * 1024 * 8);
+  }
   // block: per pair and row chunk partial sums of 3nl + 8 limbs
   const int npairs = dm.k * (dm.k + 1) / 2;
   L.blk_stride = 3 * dm.nl + 16;
@@ -298,6 +307,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         m.NT = dm.NT;
         m.carry = (long long*)(base + L.carry);
         m.max_ranges = kMaxRanges;
+        m.carry_tiles = L.carry_tiles;
         m.timing = ctx->timing ? &ctx->t : nullptr;
         m.u_rows = dm.NT;
         e = launch_upd_mfma(m, st);
@@ -421,6 +431,7 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
         m.NT = dm.NT;
         m.carry = (long long*)(base + L.carry);
         m.max_ranges = kMaxRanges;
+        m.carry_tiles = L.carry_tiles;
         m.timing = nullptr;
         m.u_rows = dm.k;
         HIPCHK(launch_upd_mfma(m, st));

@@ -6,12 +6,13 @@
 namespace hl {
 
 constexpr int kMaxPrec = 57344;   // pivot kernel keeps ~9 (P/32 + 8) words in LDS
-constexpr int kDigitPad = 32;     // zero digit slices below 0 and above S-1
-constexpr int kMaxRanges = 16;    // output-limb ranges per tile in the MFMA update
+constexpr int kDigitPad = 48;     // zero digit slices below 0 and above S-1
+constexpr int kMaxRanges = 64;    // output-limb ranges per tile in the MFMA updates
 constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
+  size_t carry_tiles;  // carry slots of 1024 entries
   int omega_stride;
   int digit_slices;
   int blk_stride;

@@ -37,6 +37,7 @@ struct MfmaArgs {
   int slices, pad, S, NT;
   long long* carry;   // per (tile, range, entry) carries between limb ranges
   int max_ranges;
+  size_t carry_tiles; // capacity of carry in units of 1024 entries
   hl_timing_t* timing;  // host: when set, the GEMM kernel alone is timed into ms[6]
   int u_rows;           // rows of the u operand (NT for the Schur update, k for X)
 };

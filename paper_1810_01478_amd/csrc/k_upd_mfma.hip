@@ -14,17 +14,21 @@
 // output limbs.  v_mfma_i32_32x32x32_i8 takes K = 32 = 2 digits x 16 panel
 // columns: lane half h of the A operand holds the 16 panel columns of digit
 // j0 + h for row m; of the B operand, digit t - j0 - h for column n.  Output
-// digits are taken 8 at a time (8 accumulators of 16 registers); for the 8
-// accumulators of one step the B operands are 8 consecutive digit slices, and
-// the next step (j0 + 2) needs the same slices shifted by two, so a window of
-// 10 slices rotates through registers and each step loads one A slice and two
-// new B slices for eight MFMAs.  Digit slices outside [0, S) are zero padding.
+// digits are taken 16 at a time (16 accumulators of 16 registers, one 4-limb
+// slab of each entry); for the 16 accumulators of one step the B operands are
+// 16 consecutive digit slices, and the next step (j0 + 2) needs the same slices
+// shifted by two, so a window of 20 slices rotates through registers: each step
+// loads one A slice and two B slices for the step after next and issues 16
+// MFMAs, 3 KiB of operands per 2^19 int8 multiply-adds.  Digit slices outside
+// [0, S) are zero padding.  One wave per SIMD (the accumulators fill the
+// accumulation registers); the work items are grouped per XCD so that the waves
+// resident on one XCD stream the same slices through its L2.
 //
-// Recombination.  After the j loop of 8 output digits (2 limbs), each lane folds
+// Recombination.  After the j loop of 16 output digits (4 limbs), each lane folds
 // its 16 entries: X = A[2 limbs] - sum_q out_(t0+q) 256^q + carry, an exact
-// 128-bit value; the low 64 bits are the new limbs and X >> 64 the carry into
-// the next pair of limbs.  The carry out of each wave's limb range is stored
-// and added by k_carry_fix, so ranges of one tile run in parallel.
+// 128-bit value, twice; the low 64 bits are the new limbs and X >> 64 the carry
+// into the next pair of limbs.  The carry out of each wave's limb range is
+// stored and added by k_carry_fix, so ranges of one tile run in parallel.
 #include "hl_kernels.hpp"
 
 namespace hl {
@@ -32,11 +36,16 @@ namespace hl {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int MF_T = 8;  // output digits per accumulation block (2 limbs)
+constexpr int MF_T = 16;             // output digits per accumulation block
+constexpr int MF_LPB = MF_T / 4;     // limbs per block (one 16-byte slab of an entry)
+constexpr int MF_WIN = MF_T + 4;     // B window: MF_T slices in use, two steps in flight
+constexpr int MF_ROT = MF_WIN / 2;   // steps per rotation of the window
+
+constexpr int MF_MAX_RANGES = 64;
 
 struct RangeTab {
-  int n;        // ranges
-  int tb[17];   // t-block boundaries, tb[0] = 0, tb[n] = nl
+  int n;                        // ranges
+  int tb[MF_MAX_RANGES + 1];    // t-block boundaries, tb[0] = 0, tb[n] = nl
 };
 
 // entry (m, n) of the 32 x 32 MFMA result held by lane l, register v
@@ -82,14 +91,41 @@ __global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int 
 
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
 
+// index of tile (R, C) among the tiles of one launch, for its carry slots
+__device__ __forceinline__ size_t launch_tile_index(const UpdArgs& g, int R, int C, int C_lo) {
+  if (g.tri) {
+    const size_t r = R - C_lo;
+    return r * (r + 1) / 2 + (C - C_lo);
+  }
+  return (size_t)(R - C_lo) * g.ntc + C;
+}
+
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   const UpdArgs& g = m.g;
-  // triangular target: tiles (R, C), C_lo <= C <= R; rectangular: rows from
-  // C_lo (here the first tile row), all g.ntc tile columns
-  const int R = C_lo + blockIdx.x, C = g.tri ? C_lo + blockIdx.y : blockIdx.y, rg = blockIdx.z;
-  if ((g.tri && R < C) || R * 32 >= m.NT) return;
+  // Work items (range rg, tile lt) in range-major order; the workgroups of a
+  // launch are dealt to the 8 XCDs in turn, so block b takes item
+  // (b % 8) * per_xcd + b / 8: the waves resident on one XCD share a limb range
+  // and hold neighbouring tiles, and read the same digit slices from its L2.
+  const int b = blockIdx.x;
+  const int item = (b & 7) * per_xcd + (b >> 3);
+  if (item >= ntiles * rt.n) return;
+  const int rg = item / ntiles, lt = item - rg * ntiles;
+  // triangular target: tiles (R, C), C_lo <= C <= R, row by row; rectangular:
+  // tile rows from C_lo (here the first tile row), all g.ntc tile columns
+  int R, C;
+  if (g.tri) {
+    int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
+    while (r > 0 && r * (r + 1) / 2 > lt) --r;
+    while ((r + 1) * (r + 2) / 2 <= lt) ++r;
+    R = C_lo + r;
+    C = C_lo + (lt - r * (r + 1) / 2);
+  } else {
+    R = C_lo + lt / g.ntc;
+    C = lt % g.ntc;
+  }
+  if (R * 32 >= m.NT) return;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   if (has_error(g.st)) return;
   __shared__ i64 carry_s[16 * WAVE];  // carry of each of the lane's 16 entries
@@ -122,68 +158,65 @@ void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo) {
     // the extra steps pair A digits with zero B padding (or the reverse) and
     // add nothing
     const int nsteps = (jhi - jlo) / 2 + 1;
-    const int nrot = (nsteps + 4) / 5;
-    // window: slice x = t0 + q - j0 - h sits at Ub + (t0 + q - j0) * sstride
-    const int8_t* ub0 = Ub + (long)(t0 - jlo) * sstride;
-    v4i w0 = ld16(ub0 + 0 * sstride), w1 = ld16(ub0 + 1 * sstride), w2 = ld16(ub0 + 2 * sstride),
-        w3 = ld16(ub0 + 3 * sstride), w4 = ld16(ub0 + 4 * sstride), w5 = ld16(ub0 + 5 * sstride),
-        w6 = ld16(ub0 + 6 * sstride), w7 = ld16(ub0 + 7 * sstride), w8, w9;
+    const int nrot = (nsteps + MF_ROT - 1) / MF_ROT;
+    // Window slot (y mod MF_WIN) holds the slice at offset t0 - jlo + y; step s
+    // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -4 - 2s, -3 - 2s
+    // for step s + 2.  A digits are likewise loaded two steps ahead.
+    const int8_t* ub = Ub + (long)(t0 - jlo) * sstride;
+    v4i w[MF_WIN];
+#pragma unroll
+    for (int y = 0; y < MF_T; ++y) w[y] = ld16(ub + y * sstride);
+    w[MF_WIN - 2] = ld16(ub - 2 * sstride);
+    w[MF_WIN - 1] = ld16(ub - 1 * sstride);
     const int8_t* ap = Ab + (long)jlo * sstride;
-    const int8_t* un = ub0 - 2 * sstride;  // next window's slices 0, 1
-    v4i an = ld16(ap);                    // A of the current step, loaded one step ahead
-#define MF_STEP(P0, P1, P2, P3, P4, P5, P6, P7, N0, N1)                                   \
-  {                                                                                       \
-    const v4i a = an;                                                                     \
-    an = ld16(ap + 2 * sstride);                                                          \
-    N0 = ld16(un);                                                                        \
-    N1 = ld16(un + sstride);                                                              \
-    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P0, acc[0], 0, 0, 0);               \
-    acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P1, acc[1], 0, 0, 0);               \
-    acc[2] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P2, acc[2], 0, 0, 0);               \
-    acc[3] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P3, acc[3], 0, 0, 0);               \
-    acc[4] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P4, acc[4], 0, 0, 0);               \
-    acc[5] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P5, acc[5], 0, 0, 0);               \
-    acc[6] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P6, acc[6], 0, 0, 0);               \
-    acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, P7, acc[7], 0, 0, 0);               \
-    ap += 2 * sstride;                                                                    \
-    un -= 2 * sstride;                                                                    \
-    __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);                                    \
-    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);                                    \
-  }
+    v4i an[2];
+    an[0] = ld16(ap);
+    an[1] = ld16(ap + 2 * sstride);
+    ap += 4 * sstride;
+    const int8_t* un = ub - 4 * sstride;
     for (int rot = 0; rot < nrot; ++rot) {
-      MF_STEP(w0, w1, w2, w3, w4, w5, w6, w7, w8, w9)
-      MF_STEP(w8, w9, w0, w1, w2, w3, w4, w5, w6, w7)
-      MF_STEP(w6, w7, w8, w9, w0, w1, w2, w3, w4, w5)
-      MF_STEP(w4, w5, w6, w7, w8, w9, w0, w1, w2, w3)
-      MF_STEP(w2, w3, w4, w5, w6, w7, w8, w9, w0, w1)
+#pragma unroll
+      for (int st = 0; st < MF_ROT; ++st) {
+        const v4i a = an[st & 1];
+        an[st & 1] = ld16(ap);
+        const int k0 = (MF_WIN * 4 - 4 - 2 * st) % MF_WIN;  // slot of y = -4 - 2 st (even)
+        w[k0] = ld16(un);
+        w[k0 + 1] = ld16(un + sstride);
+#pragma unroll
+        for (int q = 0; q < MF_T; ++q)
+          acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, w[(q - 2 * st + MF_WIN * 4) % MF_WIN], acc[q], 0, 0, 0);
+        ap += 2 * sstride;
+        un -= 2 * sstride;
+        __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MF_T, 0);
+      }
     }
-#undef MF_STEP
-    // fold the 8 digit sums of each entry into limbs 2 tb, 2 tb + 1
+    // fold the 16 digit sums of each entry into limbs 4 tb .. 4 tb + 3 (one slab)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       if (!((live >> v) & 1u)) continue;
       const int r = mf_row(l, v), c = mf_col(l);
-      u32* p = At + in_tile(r, c, 2 * tb);
-      const u64 a64 = ((u64)p[1] << 32) | p[0];
-      i64 vlo = 0, vhi = 0;
+      uint4* p = (uint4*)(At + in_tile(r, c, MF_LPB * tb));
+      const uint4 x = *p;
+      i64 d[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) vlo += (i64)acc[q][v] << (8 * q);
-#pragma unroll
-      for (int q = 4; q < 8; ++q) vhi += (i64)acc[q][v] << (8 * (q - 4));
-      __int128 X = (__int128)a64 - (__int128)vlo - ((__int128)vhi << 32) + (__int128)carry_s[v * WAVE + l];
-      const u64 nl64 = (u64)X;
-      p[0] = (u32)nl64;
-      p[1] = (u32)(nl64 >> 32);
-      carry_s[v * WAVE + l] = (i64)(X >> 64);
+      for (int q = 0; q < MF_T; ++q) d[q >> 2] += (i64)acc[q][v] << (8 * (q & 3));
+      const __int128 X = (__int128)(((u64)x.y << 32) | x.x) - (__int128)d[0] - ((__int128)d[1] << 32) +
+                         (__int128)carry_s[v * WAVE + l];
+      const __int128 Y = (__int128)(((u64)x.w << 32) | x.z) - (__int128)d[2] - ((__int128)d[3] << 32) +
+                         (__int128)(i64)(X >> 64);
+      const u64 lo = (u64)X, hi = (u64)Y;
+      *p = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
+      carry_s[v * WAVE + l] = (i64)(Y >> 64);
     }
   }
   // carries out of this range
-  long long* cb = m.carry + (tix * (size_t)m.max_ranges + rg) * 1024;
+  long long* cb = m.carry + ((size_t)lt * rt.n + rg) * 1024;
 #pragma unroll
   for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry_s[v * WAVE + l];
 }
 
-// Add the carries of range w at limb 2 tb[w+1] of every entry, w = 0..n-2.
+// Add the carries of range w at limb MF_LPB tb[w+1] of every entry, w = 0..n-2.
 __global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) {
   const UpdArgs& g = m.g;
   const int R = C_lo + blockIdx.x, C = g.tri ? C_lo + blockIdx.y : blockIdx.y;
@@ -197,12 +230,12 @@ __global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) {
     if (!((!g.tri || rg >= cg) && rg >= g.r_lo && rg < g.r_hi && cg >= g.c_lo && cg < g.c_hi)) return;
   }
   u32* At = g.A + tix * tile_words(g.nw);
-  const long long* cb = m.carry + tix * (size_t)m.max_ranges * 1024;
+  const long long* cb = m.carry + launch_tile_index(g, R, C, C_lo) * rt.n * 1024;
   const int nw = m.g.nw;
   for (int w = 0; w + 1 < rt.n; ++w) {
     const i64 cv = cb[(size_t)w * 1024 + e];
     if (cv == 0) continue;
-    int li = 2 * rt.tb[w + 1];
+    int li = MF_LPB * rt.tb[w + 1];
     if (li >= nw) continue;
     // add the sign-extended 64-bit value cv at limb li
     u32* p0 = At + in_tile(r, c, li);
@@ -252,38 +285,53 @@ __global__ __launch_bounds__(64) void k_mfma_probe(int* out) {
 }
 
 // ---------------------------------------------------------------------------
-static RangeTab make_ranges(int nl, int S, int ntiles) {
-  // t-blocks tb = 0..nl-1 cover digits 8 tb .. 8 tb + 7; work ~ number of (t, j) pairs
+// Digit-pair work of output block tb (the (t, j) pairs it multiplies).
+static double block_work(int tb, int S) {
+  double w = 0;
+  for (int q = 0; q < MF_T; ++q) {
+    const int t = MF_T * tb + q;
+    int cnt = t + 1;
+    if (cnt > S) cnt = S;
+    if (2 * S - 1 - t < cnt) cnt = 2 * S - 1 - t;
+    if (cnt > 0) w += cnt;
+  }
+  return w;
+}
+
+// Split the output blocks of every tile into ranges of about equal work.  The
+// number of ranges minimises the launch's time in units of one tile's work,
+// rounds x (1/n + per-item cost), where one round is one wave on each of the
+// 1024 SIMDs (8 XCDs x 128).
+static RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items) {
+  const int ntb = 8 * nl / MF_T;
   RangeTab rt{};
-  int want = (4096 + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
-  if (want < 1) want = 1;
-  if (want > 16) want = 16;
-  if (want > nl) want = nl;
-  double total = 0;
-  for (int tb = 0; tb < nl; ++tb)
-    for (int q = 0; q < MF_T; ++q) {
-      const int t = MF_T * tb + q;
-      int cnt = t + 1;
-      if (cnt > S) cnt = S;
-      if (2 * S - 1 - t < cnt) cnt = 2 * S - 1 - t;
-      if (cnt > 0) total += cnt;
+  int cap = max_ranges < MF_MAX_RANGES ? max_ranges : MF_MAX_RANGES;
+  if (cap > ntb) cap = ntb;
+  if (cap < 1) cap = 1;
+  int want = 1;
+  double best = 1e300;
+  for (int n = 1; n <= cap; ++n) {
+    const long total = (long)ntiles * n;
+    if (n > 1 && (size_t)total > max_items) break;
+    const long per = (total + 7) / 8;
+    const long rounds = (per + 127) / 128;
+    const double cost = (double)rounds * (1.0 / n + 0.01);
+    if (cost < best * 0.999) {
+      best = cost;
+      want = n;
     }
-  rt.n = want;
+  }
+  double total = 0;
+  for (int tb = 0; tb < ntb; ++tb) total += block_work(tb, S);
   rt.tb[0] = 0;
   double acc = 0;
   int k = 1;
-  for (int tb = 0; tb < nl && k < want; ++tb) {
-    for (int q = 0; q < MF_T; ++q) {
-      const int t = MF_T * tb + q;
-      int cnt = t + 1;
-      if (cnt > S) cnt = S;
-      if (2 * S - 1 - t < cnt) cnt = 2 * S - 1 - t;
-      if (cnt > 0) acc += cnt;
-    }
+  for (int tb = 0; tb < ntb && k < want; ++tb) {
+    acc += block_work(tb, S);
     if (acc >= total * k / want) rt.tb[k++] = tb + 1;
   }
-  while (k < want) rt.tb[k++] = nl;
-  rt.tb[want] = nl;
+  while (k < want) rt.tb[k++] = ntb;
+  rt.tb[want] = ntb;
   // drop empty ranges
   int w = 1;
   for (int j = 1; j <= want; ++j)
@@ -320,15 +368,18 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
     ncol = g.ntc;
     ntiles = nrow * ncol;
   }
-  RangeTab rt = make_ranges(g.nl, m.S, ntiles);
-  if (rt.n > m.max_ranges) return hipErrorInvalidValue;
+  RangeTab rt = make_ranges(g.nl, m.S, ntiles, m.max_ranges, m.carry_tiles);
+  // one carry slot of 1024 entries per work item
+  if (rt.n > m.max_ranges || (size_t)ntiles * rt.n > m.carry_tiles) return hipErrorInvalidValue;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (m.timing) {
     (void)hipEventCreate(&ev0);
     (void)hipEventCreate(&ev1);
     (void)hipEventRecord(ev0, stream);
   }
-  hipLaunchKernelGGL(k_upd_mfma, dim3(nrow, ncol, rt.n), dim3(64), 0, stream, m, rt, C_lo);
+  const long items = (long)ntiles * rt.n;
+  const int per_xcd = (int)((items + 7) / 8);
+  hipLaunchKernelGGL(k_upd_mfma, dim3(8 * per_xcd), dim3(64), 0, stream, m, rt, C_lo, ntiles, per_xcd);
   e = hipGetLastError();
   if (m.timing) {
     (void)hipEventRecord(ev1, stream);
