@@ -87,6 +87,55 @@ def _round_mpf(x, mant_bits: int) -> Dyadic:
     return Dyadic(-man if sign else man, int(exp))
 
 
+def _gamma_rational(a: int, b: int, cache: dict):
+    """Gamma(a / b) for integers a, b >= 1 at the current mpmath precision:
+    Gamma(n + r/b) = Gamma(r/b) (r/b)(r/b + 1)...(r/b + n - 1), with
+    Gamma(r/b) from the reflection formula when r/b > 1/2 and its partner is
+    known."""
+    import mpmath
+
+    n, r = divmod(a, b)
+    if r == 0:
+        return mpmath.mpf(math.factorial(n - 1))
+    g = cache.get(r)
+    if g is None:
+        partner = cache.get(b - r)
+        if partner is not None:
+            g = mpmath.pi / (mpmath.sin(mpmath.pi * r / b) * partner)
+        else:
+            g = mpmath.gamma(mpmath.mpf(r) / b)
+        cache[r] = g
+    x = mpmath.mpf(r) / b
+    for j in range(n):
+        g = g * (x + j)
+    return g
+
+
+def _digamma_rational(a: int, b: int):
+    """psi(a / b) for integers a, b >= 1 at the current mpmath precision.  For
+    b <= 64, Gauss's digamma theorem at the fractional part r/b (0 < r < b),
+      psi(r/b) = -gamma - ln(2b) - (pi/2) cot(pi r/b)
+                 + 2 sum_{n=1}^{ceil(b/2)-1} cos(2 pi n r/b) ln sin(pi n/b),
+    psi(1) = -gamma, then psi(x + 1) = psi(x) + 1/x; larger b directly."""
+    import mpmath
+
+    if b > 64:
+        return mpmath.digamma(mpmath.mpf(a) / b)
+    n, r = divmod(a, b)
+    if r == 0:
+        n, r = n - 1, b
+    if r == b:
+        s = -mpmath.euler
+    else:
+        s = -mpmath.euler - mpmath.log(2 * b) - mpmath.pi / 2 * mpmath.cot(mpmath.pi * r / b)
+        for j in range(1, (b + 1) // 2):
+            s += 2 * mpmath.cos(2 * mpmath.pi * j * r / b) * mpmath.log(mpmath.sin(mpmath.pi * j / b))
+    x = mpmath.mpf(r) / b
+    for j in range(n):
+        s += 1 / (x + j)
+    return s
+
+
 def exact_moment_fraction(beta, k: int) -> Fraction:
     """mu_k as an exact rational, for beta = 1/q or beta = 2/q at integer Gamma."""
     b = _as_fraction(beta)
@@ -144,7 +193,8 @@ def moments(beta, count: int, mant_bits: int = 0) -> List[Dyadic]:
                     out.append(_round_mpf(val, mant_bits))
             return out
         # general rational beta = p/q: x_k = q (k+1) / p, x_{k+p} = x_k + q
-        base = [mpmath.gamma(mpmath.mpf(q * (k + 1)) / p) for k in range(min(p, count))]
+        cache: dict = {}
+        base = [_gamma_rational(q * (k + 1), p, cache) for k in range(min(p, count))]
         vals = list(base)
         for k in range(p, count):
             x = mpmath.mpf(q * (k + 1 - p)) / p
@@ -170,8 +220,9 @@ def dmoments_dbeta(beta, count: int, mant_bits: int) -> List[Dyadic]:
     try:
         mpmath.mp.prec = mant_bits + 64
         xs = [mpmath.mpf(q * (k + 1)) / p for k in range(count)]
-        gam = [mpmath.gamma(xs[k]) for k in range(min(p, count))]
-        psi = [mpmath.digamma(xs[k]) for k in range(min(p, count))]
+        cache: dict = {}
+        gam = [_gamma_rational(q * (k + 1), p, cache) for k in range(min(p, count))]
+        psi = [_digamma_rational(q * (k + 1), p) for k in range(min(p, count))]
         for k in range(p, count):
             x = xs[k - p]
             g, s = gam[k - p], psi[k - p]

@@ -15,8 +15,9 @@ contract  the fixed-point contract step by step, in Python integers:
           the largest eigenvalue of the block by a dense library eigen-solver.
 exact     exact rational arithmetic for tiny N: LDL^T, L^-1, H^-1 block, and the
           characteristic polynomial of H_N for a brute-force smallest eigenvalue.
-gmp       optional libgmp backend (ctypes) for the one primitive that dominates
-          large runs, the exact multiply-subtract; pinned against Python ints.
+adjoint   the derivative of lambda_1 with respect to the moments (the adjoint
+          vector mubar) and its contraction with d mu / d beta, from the
+          definition, in mpmath.
 
 Every function names the passage of the paper it follows.  Parity status of each
 function is stated in its module header.
