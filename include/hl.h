@@ -168,6 +168,50 @@ hl_status hl_lambda_min(hl_ctx *ctx, const hl_shape *sh, const uint32_t *blk, co
                         void *ws, size_t ws_bytes, uint32_t *lam_mant, uint32_t *lam_mant_km1,
                         hl_lambda_t *out, void *stream);
 
+/*
+ * hl_lambda_grad -- the derivative of lambda_1 along a moment direction dmu
+ * (dmu = d mu / d beta gives d lambda_1 / d beta).  The paper computes lambda_1
+ * (Sections 4.2 and 4.5) but does not differentiate it; this is the first-order
+ * perturbation of the block's largest eigenvalue:
+ *   d lambda_1 = v^T dH v,  v = lambda_1 H^-1 E y  (y the unit eigenvector of
+ *   the block for lambda_max, E the first k columns of I, dH_ij = dmu_{i+j}),
+ * i.e. sum_m mubar_m dmu_m with the moment adjoint mubar_m = sum_{i+j=m} v_i v_j.
+ * It runs on the scaled factor: one transposed triangular solve with B^T
+ * (B_ri = b_ri, B_ii = 2^h_i) and an exact contraction with the scaled matrix
+ * dmu_{i+j} 2^(W' - s_i - s_j); nothing but the final number is floating point.
+ * Needs hl_factor, hl_inv_block and hl_lambda_min on the same workspace first.
+ * Synchronises the stream.
+ *   x        device, the first k columns of L^-1 written by hl_inv_block
+ *   blk_exp  device, the block exponent written by hl_inv_block
+ *   dmu      device, (2N-1) x w uint32 limbs: |dmu_m| (unsigned mantissa)
+ *   dmu_exp  device, 2N-1 int64: |dmu_m| = mantissa * 2^dmu_exp[m]
+ *   dmu_neg  device, 2N-1 int32: nonzero where dmu_m < 0
+ *   z        optional device output, N x nl limbs (two's complement): the
+ *            adjoint vector in the scaled basis, v_i = lambda_1 2^(W - s_i - F)
+ *            z_i / ynorm with F = out->z_shift (NULL: not written)
+ *   out      host; besides the double result it locates the exact integers
+ *            the result is made of, in the workspace until its next use:
+ *            dlambda1 = lambda_1^2 * num * 2^num_shift / den, num two's
+ *            complement (num_limbs limbs at byte offset num_offset), den > 0
+ *            (den_limbs limbs at den_offset)
+ * Device errors: HL_EOVERFLOW (index = row of z) when z leaves its P bits.
+ */
+typedef struct {
+  double dlambda1;     /* sum_m (d lambda_1 / d mu_m) dmu_m                          */
+  double lambda1;      /* lambda_1 of the same factorisation                         */
+  double ynorm;        /* |y| of the eigenvector used (its largest entry in [1/2, 1)) */
+  int64_t z_shift;     /* F, the binary point of z                                   */
+  int64_t num_shift;
+  uint64_t num_offset;
+  uint64_t den_offset;
+  int32_t num_limbs;
+  int32_t den_limbs;
+} hl_grad_t;
+hl_status hl_lambda_grad(hl_ctx *ctx, const hl_shape *sh, const hl_factor_t *f, const uint32_t *x,
+                         const int64_t *blk_exp, const uint32_t *dmu, const int64_t *dmu_exp,
+                         const int32_t *dmu_neg, int32_t w, void *ws, size_t ws_bytes, uint32_t *z,
+                         hl_grad_t *out, void *stream);
+
 /* Wait for the stream and return the status word of the workspace (index of
  * the failing pivot or column in *index if not NULL). */
 hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
@@ -177,10 +221,11 @@ hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
  * enabled (hl_set_timing(ctx, 1); timing synchronises after each stage).
  * ms[0] Schur update (all its kernels), ms[1] panel (pivots, factor columns,
  * in-panel updates), ms[2] triangular solve, ms[3] block, ms[4] eigen-step,
- * ms[5] load, ms[6] the int8 MFMA GEMM kernel alone, ms[7] whole hl_factor;
- * launches[0] Schur updates, launches[1] MFMA GEMM launches. */
+ * ms[5] load, ms[6] the int8 MFMA GEMM kernel alone, ms[7] whole hl_factor,
+ * ms[8] hl_lambda_grad; launches[0] Schur updates, launches[1] MFMA GEMM
+ * launches. */
 typedef struct {
-  double ms[8];
+  double ms[12];
   int64_t launches[4];
   double schur_limb_macs; /* algorithmic limb multiply-adds of the Schur updates */
 } hl_timing_t;

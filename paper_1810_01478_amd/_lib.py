@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_EINVAL", 2: "HL_ENOTPD", 3: "HL_EOVERFLOW", 4
 
 EXPORTS = ["hl_create", "hl_destroy", "hl_last_error", "hl_get_sizes", "hl_factor", "hl_factor_cols", "hl_inv_block",
            "hl_lambda_min", "hl_sync", "hl_set_timing", "hl_get_timing", "hl_debug_mul", "hl_debug_recip",
-           "hl_debug_mfma_layout"]
+           "hl_debug_mfma_layout", "hl_lambda_grad"]
 
 
 class hl_shape(ctypes.Structure):
@@ -43,8 +43,14 @@ class hl_lambda_t(ctypes.Structure):
 
 
 class hl_timing_t(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 4),
+    _fields_ = [("ms", ctypes.c_double * 12), ("launches", ctypes.c_int64 * 4),
                 ("schur_limb_macs", ctypes.c_double)]
+
+
+class hl_grad_t(ctypes.Structure):
+    _fields_ = [("dlambda1", ctypes.c_double), ("lambda1", ctypes.c_double), ("ynorm", ctypes.c_double),
+                ("z_shift", ctypes.c_int64), ("num_shift", ctypes.c_int64), ("num_offset", ctypes.c_uint64),
+                ("den_offset", ctypes.c_uint64), ("num_limbs", ctypes.c_int32), ("den_limbs", ctypes.c_int32)]
 
 
 class HLError(RuntimeError):
@@ -79,6 +85,8 @@ def lib():
             "hl_debug_mul": [P, I32, P, I32, P, I32, P],
             "hl_debug_recip": [P, I32, I32, P, P, P],
             "hl_debug_mfma_layout": [P, P],
+            "hl_lambda_grad": [P, ctypes.POINTER(hl_shape), ctypes.POINTER(hl_factor_t), P, P, P, P, P, I32, P, SZ,
+                               P, ctypes.POINTER(hl_grad_t), P],
         }
         for name, args in sig.items():
             try:

@@ -217,6 +217,37 @@ class Context:
         self.inv_block(fac, stream)
         return self.eigen(fac, stream=stream)
 
+    def pack_signed(self, vals):
+        """Signed dyadics (M, e) as magnitude limbs, exponents and sign flags."""
+        mags = [abs(v.M) for v in vals]
+        w = max(1, max((m.bit_length() + 31) // 32 for m in mags))
+        limbs = _u32_tensor(pack_limbs(mags, w), self.device)
+        exps = torch.tensor([v.e for v in vals], dtype=torch.int64, device=self.device)
+        neg = torch.tensor([1 if v.M < 0 else 0 for v in vals], dtype=torch.int32, device=self.device)
+        return limbs, exps, neg, w
+
+    def lambda_grad(self, fac: Factorization, dmu, want_z: bool = False, stream=None):
+        """sum_m (d lambda_1 / d mu_m) dmu_m on the GPU (hl_lambda_grad); with
+        dmu = d mu / d beta this is d lambda_1 / d beta.  Needs lambda_min(fac)
+        first."""
+        N, nl = fac.N, fac.nl
+        limbs, exps, neg, w = self.pack_signed(dmu[:2 * N - 1])
+        z = torch.zeros(N * nl, dtype=torch.int32, device=self.device) if want_z else None
+        out = L.hl_grad_t()
+        L.check(L.lib().hl_lambda_grad(self.h, ctypes.byref(fac.shape), ctypes.byref(fac.views), _ptr(fac.x),
+                                       _ptr(fac.blk_exp), _ptr(limbs), _ptr(exps), _ptr(neg), w, _ptr(fac.ws),
+                                       fac.ws.numel(), _ptr(z) if z is not None else None, ctypes.byref(out),
+                                       _stream(stream)))
+        res = {"dlambda1": out.dlambda1, "lambda1": out.lambda1, "ynorm": out.ynorm, "z_shift": out.z_shift,
+               "num_shift": out.num_shift}
+        if out.num_limbs:
+            a, b = out.num_offset, out.den_offset
+            res["num"] = _ints(fac.ws[a:a + 4 * out.num_limbs].view(torch.int32), out.num_limbs, signed=True)[0]
+            res["den"] = _ints(fac.ws[b:b + 4 * out.den_limbs].view(torch.int32), out.den_limbs, signed=False)[0]
+        if want_z:
+            res["z"] = _ints(z, nl, signed=True)
+        return res
+
     # timing ------------------------------------------------------------------
     def set_timing(self, on: bool):
         L.check(L.lib().hl_set_timing(self.h, 1 if on else 0))
@@ -259,3 +290,37 @@ def lambda_min(beta, N: int, k: int, P: int, E: int = 16, form: str = "mfma", ma
     mu = _moments(beta, 2 * N - 1, mant_bits=mant_bits or 2 * P)
     fac = ctx.factor(mu, N, k, P, E, form)
     return ctx.lambda_min(fac)
+
+
+class LambdaMin(torch.autograd.Function):
+    """lambda_1(beta) of H_N for the weight exp(-x^beta) as a differentiable
+    function of beta.  Forward: moments on the host, then factor -> block ->
+    eigen-step on the GPU.  Backward: d mu / d beta on the host (digamma chain),
+    then the adjoint kernels (hl_lambda_grad) give d lambda_1 / d beta.
+
+    beta is a 0-dim float64 tensor; its value is read as the decimal it prints as
+    (0.45 -> 9/20), so the moments are those of that rational."""
+
+    @staticmethod
+    def forward(ctx_, beta, N, k, P, E, form, context):
+        from hankel_inputs.moments import _as_fraction
+        b = _as_fraction(float(beta.detach().cpu().item()))
+        mu = _moments(b, 2 * N - 1, mant_bits=P + 64)
+        fac = context.factor(mu, N, k, P, E, form)
+        res = context.lambda_min(fac)
+        ctx_.state = (context, fac, b, N, P)
+        return torch.tensor(res["lambda1"], dtype=torch.float64, device=beta.device)
+
+    @staticmethod
+    def backward(ctx_, grad):
+        from hankel_inputs import dmoments_dbeta
+        context, fac, b, N, P = ctx_.state
+        dmu = dmoments_dbeta(b, 2 * N - 1, P + 64)
+        g = context.lambda_grad(fac, dmu)["dlambda1"]
+        return grad * g, None, None, None, None, None, None
+
+
+def lambda1(beta: torch.Tensor, N: int, k: int, P: int, E: int = 16, form: str = "mfma",
+            context: Optional[Context] = None) -> torch.Tensor:
+    """Differentiable lambda_1(beta) (see LambdaMin)."""
+    return LambdaMin.apply(beta, N, k, P, E, form, context or Context())

@@ -111,6 +111,25 @@ Layout make_layout(const Dims& dm) {
   off += al((size_t)npairs * (L.blk_stride + 64) * 4);
   L.eig = off;
   off += al(eig_ws_bytes(dm));
+  {
+    const size_t ns = 4 * (size_t)dm.nl + 4;
+    L.adj_y = off;
+    off += al((size_t)dm.k * dm.nl * 4);
+    L.adj_yc = off;
+    off += al((size_t)dm.k * dm.nl * 4);
+    L.adj_ysq = off;
+    off += al(((size_t)2 * dm.nl + 2) * 4);
+    L.adj_z = off;
+    off += al((size_t)dm.NT * dm.nl * 4);
+    L.adj_wp = off;
+    off += 256;
+    L.adj_part = off;
+    off += al((size_t)dm.N * ns * 4);
+    L.adj_col = off;
+    off += al(ns * 8);
+    L.adj_tot = off;
+    off += al(ns * 4);
+  }
   L.total = off;
   return L;
 }
@@ -515,6 +534,190 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   int fl[16];
   HIPCHK(hipMemcpy(fl, ews, sizeof fl, hipMemcpyDeviceToHost));
   out->iterations = fl[1] + fl[9];
+  return HL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a nonnegative little-endian limb array as m 2^e, m in [1/2, 1) (m = 0 for 0)
+static double limbs_to_double(const std::vector<uint32_t>& x, long* e) {
+  int top = (int)x.size() - 1;
+  while (top >= 0 && x[top] == 0) --top;
+  if (top < 0) {
+    *e = 0;
+    return 0.0;
+  }
+  uint64_t hi = ((uint64_t)x[top] << 32) | (top >= 1 ? x[top - 1] : 0u);
+  const uint32_t lo = top >= 2 ? x[top - 2] : 0u;
+  int lz = 0;
+  while (!(hi >> 63)) {
+    hi = (hi << 1) | ((lo >> (31 - lz)) & 1u);
+    ++lz;
+  }
+  // value = hi 2^(32 (top - 1) - lz) up to the bits below
+  *e = 32L * (top - 1) - lz + 64;
+  return std::ldexp((double)(hi >> 11), -53);
+}
+
+static void limbs_negate(std::vector<uint32_t>& x) {
+  uint64_t c = 1;
+  for (auto& v : x) {
+    const uint64_t t = (uint64_t)(uint32_t)~v + c;
+    v = (uint32_t)t;
+    c = t >> 32;
+  }
+}
+
+extern "C" hl_status hl_lambda_grad(hl_ctx* ctx, const hl_shape* sh, const hl_factor_t* f, const uint32_t* x,
+                                    const int64_t* blk_exp, const uint32_t* dmu, const int64_t* dmu_exp,
+                                    const int32_t* dmu_neg, int32_t w, void* ws, size_t ws_bytes, uint32_t* z,
+                                    hl_grad_t* out, void* stream) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  Dims dm;
+  hl_status s = make_dims(sh, &dm);
+  if (s != HL_OK) return s;
+  if (!f || !f->d || !f->h || !f->s || !f->l || !x || !blk_exp || !dmu || !dmu_exp || !dmu_neg || !out)
+    return fail(HL_EINVAL, "null argument");
+  if (w < 1) return fail(HL_EINVAL, "w must be >= 1");
+  Layout L = make_layout(dm);
+  if ((s = check_ws(L, ws, ws_bytes)) != HL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  DevStatus* dst = (DevStatus*)(base + L.status);
+  int32_t idx = 0;
+  if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;
+
+  // lambda_1 = (1 / lambda_max(blk)) 2^-blk_exp from the eigen-step
+  const int NWM = dm.nl + 4;
+  int* rh = nullptr;
+  u32* rm = nullptr;
+  eig_result_refs(dm, base + L.eig, 0, &rh, &rm);
+  int h2[2];
+  std::vector<uint32_t> lm(NWM);
+  int64_t bexp = 0;
+  HIPCHK(hipMemcpy(h2, rh, 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(lm.data(), rm, (size_t)NWM * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&bexp, blk_exp, 8, hipMemcpyDeviceToHost));
+  if (h2[0] != 0) return fail(HL_EINVAL, "no positive lambda_1 in the workspace: run hl_lambda_min first");
+  long le = 0;
+  const double lmant = limbs_to_double(lm, &le);   // 1/lambda_max = lmant 2^(le - 32 NWM + h2[1])
+  le += (long)h2[1] - 32L * NWM - bexp;             // lambda_1 = lmant 2^le
+  const double lam1 = std::ldexp(lmant, (int)le);
+
+  // scales: s0 = min_{m<k} s_m, Q = W - (max_{m<k} s_m + 64), s_max over all rows
+  std::vector<int32_t> sv(dm.N);
+  HIPCHK(hipMemcpy(sv.data(), f->s, (size_t)dm.N * 4, hipMemcpyDeviceToHost));
+  int s0 = sv[0], sk = sv[0], smax = sv[0];
+  for (int m = 0; m < dm.k; ++m) {
+    s0 = sv[m] < s0 ? sv[m] : s0;
+    sk = sv[m] > sk ? sv[m] : sk;
+  }
+  for (int i = 0; i < dm.N; ++i) smax = sv[i] > smax ? sv[i] : smax;
+  const long Q = (long)dm.W - (sk + 64);
+  // |v_i| <= |y| lambda_1 / lambda_min(H) ~ |y|, so |z_i| <~ sqrt(k) 2^(s_i - W) / lambda_1;
+  // F keeps the largest below 2^(P - 8 - 16)
+  const long lg = (long)std::ceil(0.5 * std::log2((double)dm.k) - (std::log2(lmant) + (double)le));
+  const long F = (long)dm.P - 8 - ((long)smax - dm.W) - (lg > 0 ? lg : 0) - 16;
+  const long eG = F - Q - s0 - 2L * dm.P + 3;
+
+  u32* ACC = (u32*)(base + L.tiles);
+  u32* Y = (u32*)(base + L.adj_y);
+  u32* Yc = (u32*)(base + L.adj_yc);
+  u32* ysq = (u32*)(base + L.adj_ysq);
+  u32* Z = (u32*)(base + L.adj_z);
+  i64* wp = (i64*)(base + L.adj_wp);
+  u32* part = (u32*)(base + L.adj_part);
+  unsigned long long* col = (unsigned long long*)(base + L.adj_col);
+  u32* tot = (u32*)(base + L.adj_tot);
+  const size_t nlz = (size_t)dm.nl;
+
+  Stamp ta(ctx, st, 8);
+  HIPCHK(launch_fill(ACC, (size_t)dm.nt * tile_words(dm.nw), 0u, st));
+  int* yh = nullptr;
+  u32* ym = nullptr;
+  eig_vector_refs(dm, base + L.eig, &yh, &ym);
+  HIPCHK(launch_adj_y(yh, ym, NWM, dm, f->s, Y, Yc, ysq, dst, st));
+  HIPCHK(launch_adj_g(x, Yc, (const u32*)(base + L.omega), L.omega_stride, dm, eG, ACC, dst, st));
+  // B^T z = G from the last row up, in blocks of 16 rows
+  for (int i0 = (dm.N - 1) / 16 * 16; i0 >= 0; i0 -= 16) {
+    const int nb = dm.N - i0 < 16 ? dm.N - i0 : 16;
+    for (int i = i0 + nb - 1; i >= i0; --i) {
+      HIPCHK(launch_adj_row(ACC, dm, i, f->h, Z, dst, st));
+      if (i > i0) {
+        // rows [i0, i) of the block: acc_r -= b_ir z_i
+        UpdArgs g{};
+        g.A = ACC;
+        g.tri = 0;
+        g.ntc = 1;
+        g.nw = dm.nw;
+        g.nl = dm.nl;
+        g.Bop = f->l + (size_t)i * nlz;
+        g.ldb = nlz;
+        g.rsb = (size_t)dm.NT * nlz;
+        g.Uop = Z + (size_t)i * nlz;
+        g.ldu = nlz;
+        g.npan = 1;
+        g.r_lo = i0;
+        g.r_hi = i;
+        g.c_lo = 0;
+        g.c_hi = 1;
+        g.st = dst;
+        HIPCHK(launch_upd_valu(g, st));
+      }
+    }
+    if (i0 > 0) {
+      // rows above the block: acc_r -= sum_{i in block} b_ir z_i
+      UpdArgs g{};
+      g.A = ACC;
+      g.tri = 0;
+      g.ntc = 1;
+      g.nw = dm.nw;
+      g.nl = dm.nl;
+      g.Bop = f->l + (size_t)i0 * nlz;
+      g.ldb = nlz;
+      g.rsb = (size_t)dm.NT * nlz;
+      g.Uop = Z + (size_t)i0 * nlz;
+      g.ldu = nlz;
+      g.npan = nb;
+      g.r_lo = 0;
+      g.r_hi = i0;
+      g.c_lo = 0;
+      g.c_hi = 1;
+      g.st = dst;
+      HIPCHK(launch_upd_valu(g, st));
+    }
+  }
+  HIPCHK(launch_adj_contract(dmu, dmu_exp, (const int*)dmu_neg, w, dm, f->s, wp, Z, part, col, tot, dst, st));
+  if (z) HIPCHK(hipMemcpyAsync(z, Z, (size_t)dm.N * nlz * 4, hipMemcpyDeviceToDevice, st));
+  ta.end();
+  if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;
+
+  const size_t ns = 4 * nlz + 4;
+  std::vector<uint32_t> T(ns), q(2 * nlz + 2);
+  int64_t Wp = 0;
+  HIPCHK(hipMemcpy(T.data(), tot, ns * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(q.data(), ysq, q.size() * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&Wp, wp, 8, hipMemcpyDeviceToHost));
+  memset(out, 0, sizeof *out);
+  out->lambda1 = lam1;
+  out->z_shift = F;
+  out->num_offset = L.adj_tot;
+  out->num_limbs = (int32_t)ns;
+  out->den_offset = L.adj_ysq;
+  out->den_limbs = (int32_t)(2 * nlz + 2);
+  long qe = 0;
+  const double qm = limbs_to_double(q, &qe);
+  if (qm == 0.0) return fail(HL_EINVAL, "eigenvector is zero");
+  out->ynorm = std::sqrt(qm) * std::ldexp(1.0, (int)(qe / 2 - (dm.P - 3))) * ((qe & 1) ? std::sqrt(2.0) : 1.0);
+  if (Wp == LLONG_MAX) return HL_OK;  // dmu = 0
+  out->num_shift = 2L * dm.W - Wp - 2 * F + 2L * dm.P - 6;
+  const bool neg = (T[ns - 1] >> 31) != 0;
+  if (neg) limbs_negate(T);
+  long te = 0;
+  const double tm = limbs_to_double(T, &te);
+  // d lambda_1 = lambda_1^2 2^(2W - W' - 2F + 2P - 6) Tot / sum Y^2
+  const long ex = 2 * le + te - qe + 2L * dm.W - Wp - 2 * F + 2L * dm.P - 6;
+  const double v = lmant * lmant * tm / qm;
+  out->dlambda1 = std::ldexp(neg ? -v : v, (int)(ex < -100000 ? -100000 : (ex > 100000 ? 100000 : ex)));
   return HL_OK;
 }
 

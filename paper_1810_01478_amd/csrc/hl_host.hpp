@@ -13,6 +13,9 @@ constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
   size_t carry_tiles;  // carry slots of 1024 entries
+  // adjoint: Y and Yc (k x nl each), sum Y^2 (2 nl + 2), z (NT x nl), W' (int64),
+  // per-row parts (N x (4 nl + 4)), their column sums (u64) and total (4 nl + 4)
+  size_t adj_y, adj_yc, adj_ysq, adj_z, adj_wp, adj_part, adj_col, adj_tot;
   int omega_stride;
   int digit_slices;
   int blk_stride;

@@ -55,8 +55,9 @@ struct UpdArgs {
   int ntc;               // tile columns (rectangular packing)
   int nw;                // limbs per entry (2 nl)
   int nl;                // limbs per factor
-  const uint32_t* Bop;   // b_ri at Bop + il*ldb + r*nl   (two's complement, nl limbs)
+  const uint32_t* Bop;   // b_ri at Bop + il*ldb + r*rsb  (two's complement, nl limbs)
   size_t ldb;
+  size_t rsb;            // row stride of Bop in limbs (0: nl); the MFMA form needs nl
   const uint32_t* Uop;   // u_ci at Uop + il*ldu + c*nl
   size_t ldu;
   int npan;              // number of factor columns i (<= 16)

@@ -53,6 +53,20 @@ hipError_t launch_block(const u32* X, const Dims& dm, const u32* omega, int ostr
                         i64* blk_exp, DevStatus* st, hipStream_t stream);
 hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
+void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out);
+}  // namespace hl
+
+namespace hl {
+// adjoint of lambda_1 (first-order perturbation of the block's largest eigenvalue)
+hipError_t launch_adj_y(const int* yhdr, const u32* ymant, int NWM, const Dims& dm, const i32* s, u32* Y, u32* Yc,
+                        u32* ysq, DevStatus* st, hipStream_t stream);
+hipError_t launch_adj_g(const u32* X, const u32* Yc, const u32* omega, int ostride, const Dims& dm, long eG, u32* ACC,
+                        DevStatus* st, hipStream_t stream);
+hipError_t launch_adj_row(const u32* ACC, const Dims& dm, int i, const i32* h, u32* Z, DevStatus* st,
+                          hipStream_t stream);
+hipError_t launch_adj_contract(const u32* dmu, const i64* dexp, const int* dneg, int w, const Dims& dm, const i32* s,
+                               i64* wprime, const u32* Z, u32* part, unsigned long long* col, u32* tot,
+                               DevStatus* st, hipStream_t stream);
 }  // namespace hl
 
 namespace hl {

@@ -45,12 +45,6 @@ struct FpCtx {
 
 constexpr int FPZERO_TAG = 2;
 
-// make this wave's global and LDS writes visible to its other lanes
-__device__ __forceinline__ void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-}
-
 __device__ __forceinline__ bool fp_is_zero(const FpRef& x) { return x.hdr[0] == FPZERO_TAG; }
 
 __device__ void fp_set_zero(const FpCtx& c, FpRef z) {
@@ -701,6 +695,18 @@ hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* s
   hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (NWM + 8) * 4, stream, dm.k, NWM, hdr, mant,
                      per, st);
   return hipGetLastError();
+}
+
+// location of the k x k block's eigenvector (k numbers, consecutive headers and
+// mantissas), left by the last iteration
+void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out) {
+  const int NWM = dm.nl + 4;
+  const size_t per = (size_t)eig_numbers(dm.k);
+  int* flags = (int*)eig_ws;
+  int* hdr = flags + 64;
+  u32* mant = (u32*)(hdr + 2 * 2 * per);
+  *hdr_out = hdr + 2 * ix_y(dm.k, 0);
+  *mant_out = mant + (size_t)ix_y(dm.k, 0) * NWM;
 }
 
 // locations of the results (host side arithmetic on offsets only)

@@ -351,6 +351,7 @@ hipError_t launch_recode(const u32* src, size_t lds, int npan, int NT, int nrows
 hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   const UpdArgs& g = m.g;
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  if (g.rsb != 0 && g.rsb != (size_t)g.nl) return hipErrorInvalidValue;  // digit recode reads rows nl apart
   // digits of the panel: b from the multiplier array, u from the panel buffer
   hipError_t e = launch_recode(g.Bop, g.ldb, g.npan, m.NT, m.NT, g.nl, m.pad, m.bdig, stream);
   if (e != hipSuccess) return e;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64) void k_upd_valu(UpdArgs g) {
     hi[q] = 0;
   }
   for (int il = 0; il < g.npan; ++il) {
-    const u32* bp = g.Bop + (size_t)il * g.ldb + (size_t)r * nl;
+    const u32* bp = g.Bop + (size_t)il * g.ldb + (size_t)r * (g.rsb ? g.rsb : (size_t)nl);
     const u32* up = g.Uop + (size_t)il * g.ldu + (size_t)c * nl;
     __syncthreads();
     for (int p = l; p < nl; p += WAVE) {

@@ -32,6 +32,12 @@ __device__ __forceinline__ int wave_id() { return threadIdx.x / WAVE; }
 
 __device__ __forceinline__ u64 ballot64(bool p) { return __ballot(p); }
 
+// make this wave's global and LDS writes visible to its other lanes
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // 96-bit accumulate: (lo, hi) += a * b.  v_mad_u64_u32 writes its carry out to
 // VCC, which v_addc_co_u32 folds into the carry count.
 __device__ __forceinline__ void mac96(u64& lo, u32& hi, u32 a, u32 b) {
