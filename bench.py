@@ -14,6 +14,8 @@ update as exact int8 MFMA GEMMs.  Prints one JSON line:
                matrix at the same precision), also used as a parity check
   valu_sample  the plain vector-ALU form on the first two panels of the same
                matrix, checked bit-identical against the MFMA form
+  adjoint      d lambda_1 / d beta on the same factorisation (hl_lambda_grad)
+               and its time
 """
 import argparse
 import json
@@ -81,6 +83,7 @@ def main():
     ap.add_argument("--form", default="mfma", choices=["mfma", "valu"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
+    ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (d lambda_1 / d beta)")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--progress", action="store_true",
                     help="factor in pieces of 128 columns, printing a line after each (profiler runs)")
@@ -199,6 +202,23 @@ def main():
                            "traffic": measured_traffic(workload),
                            "kernel": "k_upd_mfma (int8 ops)", "launches": stages["launches"][1],
                            "avg_launch_ms": ms[6] / max(1, stages["launches"][1])}
+
+    # adjoint on the same factorisation: d lambda_1 / d beta (after the timed steps)
+    if not a.no_grad:
+        from hankel_inputs import dmoments_dbeta
+        dmu = dmoments_dbeta(beta, 2 * N - 1, P + 64)
+        log("adjoint")
+        ctx.set_timing(True)
+        g = ctx.lambda_grad(fac, dmu)
+        tg = ctx.timing()["ms"][8]
+        ctx.set_timing(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = ctx.lambda_grad(fac, dmu)
+        torch.cuda.synchronize()
+        tg2 = (time.perf_counter() - t0) * 1e3
+        out["adjoint"] = {"dlambda1_dbeta": g["dlambda1"], "ms": tg2, "device_ms": tg,
+                          "time_to_dlambda1_dbeta_s": dt + tg2 * 1e-3}
 
     # CPU oracle on a bounded sample, doubling as a parity check of the leading block
     if not a.no_cpu:
