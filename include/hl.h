@@ -212,6 +212,64 @@ hl_status hl_lambda_grad(hl_ctx *ctx, const hl_shape *sh, const hl_factor_t *f, 
                          const int32_t *dmu_neg, int32_t w, void *ws, size_t ws_bytes, uint32_t *z,
                          hl_grad_t *out, void *stream);
 
+/*
+ * Batches (many instances of uneven N and precision in one launch sequence).
+ * The paper factors one matrix at a time on a cluster and hands the largest
+ * work out first (Section 4.3.3); here a batch advances all its instances in
+ * lock step over a global pivot counter, every launch covering every instance
+ * that still has work (so the sequential chain of Algorithm 1 is paid once per
+ * batch), the trailing updates of a step go to one persistent int8 MFMA launch
+ * fed from per-XCD queues of work items, largest first, and the whole sequence
+ * (load, panels, the first k columns of L^-1, the blocks, the eigen-steps) is
+ * captured once in a hipGraph and replayed.  Results are bit-identical to
+ * hl_factor + hl_inv_block + hl_lambda_min on each instance.
+ */
+typedef struct {
+  hl_shape shape;          /* as for hl_factor (form may be overridden by the tuning) */
+  const uint32_t *mu;      /* device moments, (2N-1) x w limbs                        */
+  const int64_t *mu_exp;   /* device, 2N-1                                            */
+  int32_t w;
+  void *ws;                /* device workspace of hl_get_sizes(shape) bytes           */
+  size_t ws_bytes;
+  hl_factor_t f;           /* device outputs as for hl_factor                         */
+  uint32_t *x;             /* device outputs as for hl_inv_block                      */
+  uint32_t *blk;
+  int64_t *blk_exp;
+} hl_instance;
+
+/* Launch shape of a batch (never changes the results). */
+typedef struct {
+  int32_t items_per_simd;  /* MFMA work items per SIMD and step (granularity)        */
+  int32_t range_cap;       /* most output-limb ranges per tile                        */
+  int32_t valu_below_bits; /* instances with P below this use the VALU update form   */
+  int32_t reserved;
+} hl_tune_t;
+
+typedef struct hl_batch hl_batch;
+
+/* Bytes of device memory the batch's launch plan needs (argument tables and
+ * work queues); tune may be NULL (defaults). */
+hl_status hl_batch_plan_bytes(int32_t count, const hl_instance *inst, const hl_tune_t *tune, size_t *bytes);
+
+/* Build the plan into the caller's device buffer `plan` (which must stay
+ * allocated and untouched while the batch exists) and capture the whole launch
+ * sequence in a hipGraph.  Instances must not share workspaces or outputs. */
+hl_status hl_batch_create(hl_ctx *ctx, int32_t count, const hl_instance *inst, const hl_tune_t *tune,
+                          void *plan, size_t plan_bytes, hl_batch **out);
+/* Replay the graph on `stream` (asynchronous). */
+hl_status hl_batch_launch(hl_batch *b, void *stream);
+/* Wait for `stream`; per-instance lambda_1 results (host arrays of count) and
+ * device status (HL_OK or the instance's first device error). */
+hl_status hl_batch_results(hl_batch *b, void *stream, hl_lambda_t *out, hl_status *status);
+hl_status hl_batch_destroy(hl_batch *b);
+
+/* Autotuner: builds and times the batch's first `panels` panel steps under each
+ * candidate launch shape (items per SIMD 1, 2, 4, 8; range cap 16, 64; VALU
+ * below 0, 2048, 4096 bits) and returns the fastest in *best (its time per
+ * replay in *best_ms).  Uses the instances' workspaces and `plan` as scratch. */
+hl_status hl_autotune(hl_ctx *ctx, int32_t count, const hl_instance *inst, void *plan, size_t plan_bytes,
+                      int32_t panels, hl_tune_t *best, double *best_ms);
+
 /* Wait for the stream and return the status word of the workspace (index of
  * the failing pivot or column in *index if not NULL). */
 hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);

@@ -14,7 +14,8 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_EINVAL", 2: "HL_ENOTPD", 3: "HL_EOVERFLOW", 4
 
 EXPORTS = ["hl_create", "hl_destroy", "hl_last_error", "hl_get_sizes", "hl_factor", "hl_factor_cols", "hl_inv_block",
            "hl_lambda_min", "hl_sync", "hl_set_timing", "hl_get_timing", "hl_debug_mul", "hl_debug_recip",
-           "hl_debug_mfma_layout", "hl_lambda_grad"]
+           "hl_debug_mfma_layout", "hl_lambda_grad", "hl_batch_plan_bytes", "hl_batch_create", "hl_batch_launch",
+           "hl_batch_results", "hl_batch_destroy", "hl_autotune"]
 
 
 class hl_shape(ctypes.Structure):
@@ -53,6 +54,17 @@ class hl_grad_t(ctypes.Structure):
                 ("den_offset", ctypes.c_uint64), ("num_limbs", ctypes.c_int32), ("den_limbs", ctypes.c_int32)]
 
 
+class hl_instance(ctypes.Structure):
+    _fields_ = [("shape", hl_shape), ("mu", ctypes.c_void_p), ("mu_exp", ctypes.c_void_p), ("w", ctypes.c_int32),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("f", hl_factor_t), ("x", ctypes.c_void_p),
+                ("blk", ctypes.c_void_p), ("blk_exp", ctypes.c_void_p)]
+
+
+class hl_tune_t(ctypes.Structure):
+    _fields_ = [("items_per_simd", ctypes.c_int32), ("range_cap", ctypes.c_int32),
+                ("valu_below_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class HLError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(code, code), msg))
@@ -87,6 +99,15 @@ def lib():
             "hl_debug_mfma_layout": [P, P],
             "hl_lambda_grad": [P, ctypes.POINTER(hl_shape), ctypes.POINTER(hl_factor_t), P, P, P, P, P, I32, P, SZ,
                                P, ctypes.POINTER(hl_grad_t), P],
+            "hl_batch_plan_bytes": [I32, ctypes.POINTER(hl_instance), ctypes.POINTER(hl_tune_t),
+                                    ctypes.POINTER(ctypes.c_size_t)],
+            "hl_batch_create": [P, I32, ctypes.POINTER(hl_instance), ctypes.POINTER(hl_tune_t), P, SZ,
+                                ctypes.POINTER(ctypes.c_void_p)],
+            "hl_batch_launch": [P, P],
+            "hl_batch_results": [P, P, ctypes.POINTER(hl_lambda_t), ctypes.POINTER(ctypes.c_int)],
+            "hl_batch_destroy": [P],
+            "hl_autotune": [P, I32, ctypes.POINTER(hl_instance), P, SZ, I32, ctypes.POINTER(hl_tune_t),
+                            ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             try:

@@ -283,6 +283,82 @@ class Context:
         return _ints(O, nl + 4, signed=False)[0], int(H.cpu().item())
 
 
+class Batch:
+    """Many instances in one captured launch sequence (hl_batch_*).
+
+    specs: list of (mu, N, k, P, E, form) with mu the moment dyadics.  The
+    device buffers of every instance and the plan are held here; launch() replays
+    the graph, results() waits and returns one dict per instance."""
+
+    def __init__(self, ctx: "Context", specs, tune: Optional[dict] = None):
+        self.ctx = ctx
+        self.facs, self.packed = [], []
+        n = len(specs)
+        self.inst = (L.hl_instance * n)()
+        for j, (mu, N, k, P, E, form) in enumerate(specs):
+            sh = ctx.shape(N, k, P, E, form)
+            fac = ctx.alloc(sh)
+            limbs, exps, w = ctx.pack_moments(mu[:2 * N - 1])
+            fac._mu = (limbs, exps, w)
+            self.facs.append(fac)
+            self.inst[j] = L.hl_instance(shape=sh, mu=limbs.data_ptr(), mu_exp=exps.data_ptr(), w=w,
+                                         ws=fac.ws.data_ptr(), ws_bytes=fac.ws.numel(), f=fac.views,
+                                         x=fac.x.data_ptr(), blk=fac.blk.data_ptr(), blk_exp=fac.blk_exp.data_ptr())
+        self.tune = L.hl_tune_t(**tune) if tune else None
+        nb = ctypes.c_size_t(0)
+        tp = ctypes.byref(self.tune) if self.tune is not None else None
+        L.check(L.lib().hl_batch_plan_bytes(n, self.inst, tp, ctypes.byref(nb)))
+        self.plan = torch.empty(max(256, nb.value), dtype=torch.uint8, device=ctx.device)
+        h = ctypes.c_void_p()
+        L.check(L.lib().hl_batch_create(ctx.h, n, self.inst, tp, _ptr(self.plan), self.plan.numel(),
+                                        ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        L.check(L.lib().hl_batch_launch(self.h, _stream(stream)))
+
+    def results(self, stream=None):
+        n = len(self.facs)
+        out = (L.hl_lambda_t * n)()
+        st = (ctypes.c_int * n)()
+        code = L.lib().hl_batch_results(self.h, _stream(stream), out, st)
+        res = []
+        for j in range(n):
+            o = out[j]
+            res.append({"status": st[j], "lambda1": o.lambda1, "lambda1_km1": o.lambda1_km1, "trunc": o.trunc,
+                        "exp": o.exp, "iterations": o.iterations})
+        if code != L.HL_OK:
+            raise L.HLError(code, L.lib().hl_last_error().decode())
+        return res
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().hl_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(batch: Batch, panels: int = 2):
+    """Time candidate launch shapes on the batch's first panel steps (hl_autotune);
+    returns (tuning dict, ms per replay).  The instances' workspaces serve as
+    scratch (a later launch of the batch recomputes everything from the load);
+    the plans go to a scratch buffer, not the batch's own."""
+    best = L.hl_tune_t()
+    ms = ctypes.c_double(0)
+    scratch = torch.empty(2 * batch.plan.numel(), dtype=torch.uint8, device=batch.ctx.device)
+    L.check(L.lib().hl_autotune(batch.ctx.h, len(batch.facs), batch.inst, _ptr(scratch), scratch.numel(),
+                                panels, ctypes.byref(best), ctypes.byref(ms)))
+    torch.cuda.synchronize()
+    del scratch
+    return ({"items_per_simd": best.items_per_simd, "range_cap": best.range_cap,
+             "valu_below_bits": best.valu_below_bits}, ms.value)
+
+
 def lambda_min(beta, N: int, k: int, P: int, E: int = 16, form: str = "mfma", mant_bits: int = 0,
                ctx: Optional[Context] = None):
     """lambda_1 of H_N for the weight exp(-x^beta), end to end on the GPU."""

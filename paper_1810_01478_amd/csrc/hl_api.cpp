@@ -392,6 +392,7 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
 
   Stamp ts(ctx, st, 2);
   HIPCHK(launch_fill(ACC, (size_t)dm.nt * tile_words(dm.nw), 0u, st));
+  HIPCHK(launch_fill(x, (size_t)dm.NT * dm.k * dm.nl, 0u, st));  // rows N .. NT-1 stay zero
   if (sh->form == HL_FORM_MFMA8) {
     // digit slices outside [0, S) must read as zero whatever ran before
     HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
@@ -497,6 +498,13 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;
   int64_t bexp = 0;
   HIPCHK(hipMemcpy(&bexp, blk_exp, 8, hipMemcpyDeviceToHost));
+  return read_lambda(dm, ews, bexp, lam_mant, lam_mant_km1, out);
+}
+
+namespace hl {
+// host readback of the eigen-step's results (after the stream has finished)
+hl_status read_lambda(const Dims& dm, void* ews, int64_t bexp, uint32_t* lam_mant, uint32_t* lam_mant_km1,
+                      hl_lambda_t* out) {
   const int NWM = dm.nl + 4;
   memset(out, 0, sizeof *out);
   for (int which = 0; which < 3; ++which) {
@@ -536,6 +544,7 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   out->iterations = fl[1] + fl[9];
   return HL_OK;
 }
+}  // namespace hl
 
 // ---------------------------------------------------------------------------
 // a nonnegative little-endian limb array as m 2^e, m in [1/2, 1) (m = 0 for 0)

@@ -26,5 +26,7 @@ hl_status fail(hl_status s, const char* fmt, ...);
 hl_status make_dims(const hl_shape* sh, Dims* dm);
 Layout make_layout(const Dims& dm);
 size_t eig_ws_bytes(const Dims& dm);
+hl_status read_lambda(const Dims& dm, void* eig_ws, int64_t bexp, uint32_t* lam_mant, uint32_t* lam_mant_km1,
+                      hl_lambda_t* out);
 
 }  // namespace hl

@@ -18,13 +18,43 @@ hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u
 hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
                       int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
 hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream);
+
+// Argument records of the per-pivot kernels; a batch launch takes a device array
+// of them, one per instance.
+struct PivotArgs {
+  u32* A;
+  Dims dm;
+  int i;
+  u32* d_out;
+  i32* h_out;
+  u32* omega;
+  int ostride;
+  DevStatus* st;
+};
+struct ColArgs {
+  const u32* A;
+  Dims dm;
+  int i, r0;
+  const i32* h;
+  const u32* omega;
+  int ostride;
+  u32* u_out;
+  u32* l_col;
+  DevStatus* st;
+};
+hipError_t launch_pivot_batch(const PivotArgs* tab, int count, int nl_max, hipStream_t stream);
+hipError_t launch_col_batch(const ColArgs* tab, int count, int rows_max, int nl_max, hipStream_t stream);
 hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout,
                             hipStream_t stream);
 hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_omega, i32* h,
                               hipStream_t stream);
 
-// exact update A[r][c] -= sum_i b_ri u_ci on the vector ALU
+// exact update A[r][c] -= sum_i b_ri u_ci on the vector ALU; the batch form
+// takes a device array of records (grid nr_max x nc_max x count, each record
+// bounded by its own row and column ranges; npan <= 0 skips a record)
 hipError_t launch_upd_valu(const UpdArgs& g, hipStream_t stream);
+hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int nc_max, int nw_max, int nl_max,
+                                 hipStream_t stream);
 
 }  // namespace hl
 
@@ -42,16 +72,69 @@ struct MfmaArgs {
   int u_rows;           // rows of the u operand (NT for the Schur update, k for X)
 };
 hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream);
+
+// Output-limb ranges of one MFMA launch: output block boundaries tb[0..n]
+// (a block is 16 digits = 4 limbs).
+constexpr int MF_MAX_RANGES = 64;
+struct RangeTab {
+  int n;                        // ranges
+  int tb[MF_MAX_RANGES + 1];    // block boundaries, tb[0] = 0, tb[n] = nw / 4
+};
+RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items);
+RangeTab split_ranges(int nl, int S, int n);
+double block_work(int tb, int S);  // digit pairs multiplied for output block tb
+constexpr int MF_BLOCK_DIGITS = 16;
+
+// Batched form: one entry per instance and step, work items (entry, tile index
+// of the entry's launch, range) in 8 per-XCD queues of per_xcd items (x < 0:
+// none); heads: 8 counters of device memory.
+struct MfmaEntry {
+  MfmaArgs m;
+  RangeTab rt;
+  int C_lo;
+  int ntiles;
+};
+struct RecodeArgs {
+  const u32* src;
+  size_t lds;
+  int npan, NT, nrows, nl, pad;
+  int8_t* dst;
+};
+hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int NT_max, hipStream_t stream);
+hipError_t launch_upd_mfma_batch(const MfmaEntry* tab, const int4* items, int per_xcd, unsigned* heads,
+                                 hipStream_t stream);
+hipError_t launch_carry_fix_batch(const MfmaEntry* tab, int count, int nrow_max, int ncol_max, hipStream_t stream);
 size_t eig_ws_bytes_impl(int nl, int k);
 }  // namespace hl
 
 namespace hl {
 hipError_t launch_trsm_row(const u32* ACC, const Dims& dm, int r, const i32* s, const i32* h, u32* X,
                            DevStatus* st, hipStream_t stream);
+struct TrsmRowArgs {
+  const u32* ACC;
+  Dims dm;
+  int r;
+  const i32* s;
+  const i32* h;
+  u32* X;
+  DevStatus* st;
+};
+hipError_t launch_trsm_row_batch(const TrsmRowArgs* tab, int count, int k_max, int nl_max, hipStream_t stream);
 hipError_t launch_block(const u32* X, const Dims& dm, const u32* omega, int ostride, const i32* s,
                         u32* part, int ns, int nchunks, int rows_per_chunk, u32* msum, int nm, u32* blk,
                         i64* blk_exp, DevStatus* st, hipStream_t stream);
 hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
+struct EigArgs {
+  const u32* blk;
+  int k, nl, P, NWM;
+  int* hdr;
+  u32* mant;
+  size_t nums_per;
+  int* flags;
+  DevStatus* st;
+};
+EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st);
+hipError_t launch_eig_batch(const EigArgs* tab, int count, int nl_max, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
 void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out);
 }  // namespace hl

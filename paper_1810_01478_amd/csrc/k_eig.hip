@@ -459,11 +459,16 @@ __device__ int eig_bits(const EigMat& M, FpCtx c) {
   return num(M, ix_s(n, S_HI)).hdr[1] - W.hdr[1];
 }
 
-__global__ __launch_bounds__(EIG_THREADS) void k_eig(const u32* __restrict__ blk, int k, int nl, int P,
-                                                     int NWM, int* hdr_base, u32* mant_base, size_t nums_per,
-                                                     int* flags_base, DevStatus* st) {
+__device__ void eig_body(const EigArgs& ea, int which) {
+  const u32* __restrict__ blk = ea.blk;
+  const int k = ea.k, nl = ea.nl, P = ea.P, NWM = ea.NWM;
+  int* hdr_base = ea.hdr;
+  u32* mant_base = ea.mant;
+  const size_t nums_per = ea.nums_per;
+  int* flags_base = ea.flags;
+  DevStatus* st = ea.st;
   if (has_error(st)) return;
-  const int which = blockIdx.x;  // 0: k x k, 1: (k-1) x (k-1)
+  // which = 0: k x k, 1: (k-1) x (k-1)
   const int n = k - which;
   if (n < 1) return;
   EigMat M;
@@ -647,9 +652,20 @@ finish:
   }
 }
 
+__global__ __launch_bounds__(EIG_THREADS) void k_eig(EigArgs a) { eig_body(a, blockIdx.x); }
+
+// batch: blockIdx.y is the instance
+__global__ __launch_bounds__(EIG_THREADS) void k_eig_b(const EigArgs* __restrict__ tab) {
+  eig_body(tab[blockIdx.y], blockIdx.x);
+}
+
 // difference of the two results: trunc = lam(k) - lam(k-1) (scaled equally)
-__global__ __launch_bounds__(64) void k_eig_diff(int k, int NWM, int* hdr_base, u32* mant_base,
-                                                 size_t nums_per, DevStatus* st) {
+__device__ void eig_diff_body(const EigArgs& ea) {
+  const int k = ea.k, NWM = ea.NWM;
+  int* hdr_base = ea.hdr;
+  u32* mant_base = ea.mant;
+  const size_t nums_per = ea.nums_per;
+  DevStatus* st = ea.st;
   if (has_error(st) || k < 2) return;
   extern __shared__ u32 lds[];
   FpCtx c;
@@ -670,6 +686,9 @@ __global__ __launch_bounds__(64) void k_eig_diff(int k, int NWM, int* hdr_base, 
   fp_add(c, r, num(A, ix_s(k, S_ONE)), num(B, ix_s(k - 1, S_ONE)), true);
 }
 
+__global__ __launch_bounds__(64) void k_eig_diff(EigArgs a) { eig_diff_body(a); }
+__global__ __launch_bounds__(64) void k_eig_diff_b(const EigArgs* __restrict__ tab) { eig_diff_body(tab[blockIdx.x]); }
+
 size_t eig_ws_bytes(const Dims& dm) {
   const int NWM = dm.nl + 4;
   const size_t per = (size_t)eig_numbers(dm.k);
@@ -677,23 +696,48 @@ size_t eig_ws_bytes(const Dims& dm) {
 }
 
 // host: run the eigen-step on both blocks and read back the results
+EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st) {
+  EigArgs a{};
+  a.blk = blk;
+  a.k = dm.k;
+  a.nl = dm.nl;
+  a.P = dm.P;
+  a.NWM = dm.nl + 4;
+  a.nums_per = (size_t)eig_numbers(dm.k);
+  a.flags = (int*)eig_ws;
+  a.hdr = a.flags + 64;
+  a.mant = (u32*)(a.hdr + 2 * 2 * a.nums_per);
+  a.st = st;
+  return a;
+}
+
+static size_t eig_lds(int NWM) { return (size_t)(16 + EIG_WAVES * 2 * (NWM + 8)) * 4; }
+
 hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream) {
-  const int NWM = dm.nl + 4;
-  const size_t per = (size_t)eig_numbers(dm.k);
-  int* flags = (int*)eig_ws;
-  int* hdr = flags + 64;
-  u32* mant = (u32*)(hdr + 2 * 2 * per);
-  const size_t lds = (size_t)(16 + EIG_WAVES * 2 * (NWM + 8)) * 4;
+  const EigArgs a = eig_args(blk, dm, eig_ws, st);
+  const size_t lds = eig_lds(a.NWM);
   if (lds > 65536) {
     hipError_t e0 = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e0 != hipSuccess) return e0;
   }
-  hipLaunchKernelGGL(k_eig, dim3(dm.k >= 2 ? 2 : 1), dim3(EIG_THREADS), lds, stream, blk, dm.k, dm.nl, dm.P, NWM,
-                     hdr, mant, per, flags, st);
+  hipLaunchKernelGGL(k_eig, dim3(dm.k >= 2 ? 2 : 1), dim3(EIG_THREADS), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (NWM + 8) * 4, stream, dm.k, NWM, hdr, mant,
-                     per, st);
+  hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (a.NWM + 8) * 4, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_batch(const EigArgs* tab, int count, int nl_max, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = eig_lds(nl_max + 4);
+  if (lds > 65536) {
+    hipError_t e0 = hipFuncSetAttribute((const void*)k_eig_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e0 != hipSuccess) return e0;
+  }
+  hipLaunchKernelGGL(k_eig_b, dim3(2, count), dim3(EIG_THREADS), lds, stream, tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eig_diff_b, dim3(count), dim3(64), (size_t)2 * (nl_max + 4 + 8) * 4, stream, tab);
   return hipGetLastError();
 }
 

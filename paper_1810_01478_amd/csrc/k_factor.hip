@@ -257,10 +257,15 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
 // One wave: pivot i of the trailing matrix.
 constexpr int PIVOT_THREADS = 1024;
 
-__global__ __launch_bounds__(PIVOT_THREADS) void k_pivot(u32* __restrict__ A, Dims dm, int i,
-                                                         u32* __restrict__ d_out, i32* __restrict__ h_out,
-                                                         u32* __restrict__ omega_tab, int omega_stride,
-                                                         DevStatus* st) {
+__device__ void pivot_body(const PivotArgs& a) {
+  u32* __restrict__ A = a.A;
+  const Dims dm = a.dm;
+  const int i = a.i;
+  u32* __restrict__ d_out = a.d_out;
+  i32* __restrict__ h_out = a.h_out;
+  u32* __restrict__ omega_tab = a.omega;
+  const int omega_stride = a.ostride;
+  DevStatus* st = a.st;
   if (has_error(st)) return;
   extern __shared__ u32 lds[];
   const int nw = dm.nw, nl = dm.nl;
@@ -281,18 +286,31 @@ __global__ __launch_bounds__(PIVOT_THREADS) void k_pivot(u32* __restrict__ A, Di
   }
 }
 
+__global__ __launch_bounds__(PIVOT_THREADS) void k_pivot(PivotArgs a) { pivot_body(a); }
+
+// one workgroup per instance of a batch
+__global__ __launch_bounds__(PIVOT_THREADS) void k_pivot_b(const PivotArgs* __restrict__ tab) {
+  pivot_body(tab[blockIdx.x]);
+}
+
 // ---------------------------------------------------------------------------
 // Factor columns of pivot i for rows r in [r0, NT):
 //   u_r = rnd(a_ri / 2^h_i),  b_r = rnd(u_r w_i / 2^P),
 // both two's complement over nl limbs; rows r <= i and r >= N give zeros.
 // u goes to the panel buffer, b to the multiplier array L (column i).
-__global__ __launch_bounds__(64) void k_col(const u32* __restrict__ A, Dims dm, int i, int r0,
-                                            const i32* __restrict__ h_tab,
-                                            const u32* __restrict__ omega_tab, int omega_stride,
-                                            u32* __restrict__ u_out, u32* __restrict__ l_col,
-                                            DevStatus* st) {
+__device__ void col_body(const ColArgs& a, int bx) {
+  const u32* __restrict__ A = a.A;
+  const Dims dm = a.dm;
+  const int i = a.i;
+  const i32* __restrict__ h_tab = a.h;
+  const u32* __restrict__ omega_tab = a.omega;
+  const int omega_stride = a.ostride;
+  DevStatus* st = a.st;
   if (has_error(st)) return;
-  const int r = r0 + blockIdx.x;
+  const int r = a.r0 + bx;
+  if (r >= dm.NT) return;
+  u32* __restrict__ u_out = a.u_out;
+  u32* __restrict__ l_col = a.l_col;
   const int nl = dm.nl, nw = dm.nw;
   u32* uo = u_out + (size_t)r * nl;
   u32* bo = l_col + (size_t)r * nl;
@@ -358,6 +376,11 @@ __global__ __launch_bounds__(64) void k_col(const u32* __restrict__ A, Dims dm, 
   }
 }
 
+__global__ __launch_bounds__(64) void k_col(ColArgs a) { col_body(a, blockIdx.x); }
+
+// batch: blockIdx.y is the instance, blockIdx.x the row offset
+__global__ __launch_bounds__(64) void k_col_b(const ColArgs* __restrict__ tab) { col_body(tab[blockIdx.y], blockIdx.x); }
+
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u32(u32* __restrict__ p, size_t n, u32 v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -411,8 +434,8 @@ hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u
                         DevStatus* st, hipStream_t stream) {
   hipError_t e = allow_lds((const void*)k_pivot, pivot_lds_bytes(dm.nl));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(PIVOT_THREADS), pivot_lds_bytes(dm.nl), stream, A, dm, i, d_out, h_out,
-                     omega, ostride, st);
+  const PivotArgs a{A, dm, i, d_out, h_out, omega, ostride, st};
+  hipLaunchKernelGGL(k_pivot, dim3(1), dim3(PIVOT_THREADS), pivot_lds_bytes(dm.nl), stream, a);
   return hipGetLastError();
 }
 
@@ -420,8 +443,22 @@ hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h,
                       int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream) {
   const int nrows = dm.NT - r0;
   if (nrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_col, dim3(nrows), dim3(64), col_lds_bytes(dm.nl), stream, A, dm, i, r0, h, omega,
-                     ostride, u_out, l_col, st);
+  const ColArgs a{A, dm, i, r0, h, omega, ostride, u_out, l_col, st};
+  hipLaunchKernelGGL(k_col, dim3(nrows), dim3(64), col_lds_bytes(dm.nl), stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot_batch(const PivotArgs* tab, int count, int nl_max, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipError_t e = allow_lds((const void*)k_pivot_b, pivot_lds_bytes(nl_max));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pivot_b, dim3(count), dim3(PIVOT_THREADS), pivot_lds_bytes(nl_max), stream, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_batch(const ColArgs* tab, int count, int rows_max, int nl_max, hipStream_t stream) {
+  if (count <= 0 || rows_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_b, dim3(rows_max, count), dim3(64), col_lds_bytes(nl_max), stream, tab);
   return hipGetLastError();
 }
 

@@ -23,11 +23,15 @@ __device__ __forceinline__ int q_of(const i32* s, int k, int W) {
 }
 
 // Finish row r of X: one wave per column m.
-__global__ __launch_bounds__(64) void k_trsm_row(const u32* __restrict__ ACC, Dims dm, int r,
-                                                 const i32* __restrict__ s, const i32* __restrict__ h,
-                                                 u32* __restrict__ X, DevStatus* st) {
-  if (has_error(st)) return;
-  const int m = blockIdx.x;
+__device__ void trsm_row_body(const TrsmRowArgs& a, int m) {
+  const u32* __restrict__ ACC = a.ACC;
+  const Dims dm = a.dm;
+  const int r = a.r;
+  const i32* __restrict__ s = a.s;
+  const i32* __restrict__ h = a.h;
+  u32* __restrict__ X = a.X;
+  DevStatus* st = a.st;
+  if (has_error(st) || m >= dm.k) return;
   const int nl = dm.nl, nw = dm.nw;
   u32* xo = X + ((size_t)r * dm.k + m) * nl;
   if (r < m) {
@@ -65,6 +69,13 @@ __global__ __launch_bounds__(64) void k_trsm_row(const u32* __restrict__ ACC, Di
   if (neg) w_neg(Xs, nl);
   __syncthreads();
   for (int l = lane_id(); l < nl; l += WAVE) xo[l] = Xs[l];
+}
+
+__global__ __launch_bounds__(64) void k_trsm_row(TrsmRowArgs a) { trsm_row_body(a, blockIdx.x); }
+
+// batch: blockIdx.y is the instance
+__global__ __launch_bounds__(64) void k_trsm_row_b(const TrsmRowArgs* __restrict__ tab) {
+  trsm_row_body(tab[blockIdx.y], blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +221,15 @@ __global__ __launch_bounds__(64) void k_block_final(const u32* __restrict__ msum
 hipError_t launch_trsm_row(const u32* ACC, const Dims& dm, int r, const i32* s, const i32* h, u32* X,
                            DevStatus* st, hipStream_t stream) {
   const size_t lds = (size_t)(dm.nw + 4 + dm.nl + 4) * 4;
-  hipLaunchKernelGGL(k_trsm_row, dim3(dm.k), dim3(64), lds, stream, ACC, dm, r, s, h, X, st);
+  const TrsmRowArgs a{ACC, dm, r, s, h, X, st};
+  hipLaunchKernelGGL(k_trsm_row, dim3(dm.k), dim3(64), lds, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_row_batch(const TrsmRowArgs* tab, int count, int k_max, int nl_max, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = (size_t)(2 * nl_max + 4 + nl_max + 4) * 4;
+  hipLaunchKernelGGL(k_trsm_row_b, dim3(k_max, count), dim3(64), lds, stream, tab);
   return hipGetLastError();
 }
 

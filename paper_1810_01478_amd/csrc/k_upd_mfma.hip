@@ -41,13 +41,6 @@ constexpr int MF_LPB = MF_T / 4;     // limbs per block (one 16-byte slab of an 
 constexpr int MF_WIN = MF_T + 4;     // B window: MF_T slices in use, two steps in flight
 constexpr int MF_ROT = MF_WIN / 2;   // steps per rotation of the window
 
-constexpr int MF_MAX_RANGES = 64;
-
-struct RangeTab {
-  int n;                        // ranges
-  int tb[MF_MAX_RANGES + 1];    // t-block boundaries, tb[0] = 0, tb[n] = nl
-};
-
 // entry (m, n) of the 32 x 32 MFMA result held by lane l, register v
 __device__ __forceinline__ int mf_row(int l, int v) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
 __device__ __forceinline__ int mf_col(int l) { return l & 31; }
@@ -55,9 +48,8 @@ __device__ __forceinline__ int mf_col(int l) { return l & 31; }
 // ---------------------------------------------------------------------------
 // Recode the panel factors (two's complement, nl limbs) into balanced digits.
 // src: [16][NT][nl] limbs; dst: [slices][NT][16] bytes, slice = digit + pad.
-__global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows, int nl, int pad,
-                         int8_t* __restrict__ dst) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void recode_body(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows,
+                                            int nl, int pad, int8_t* __restrict__ dst, int gid) {
   const int il = gid & 15, row = gid >> 4;
   if (row >= NT) return;
   const int S = 4 * nl;
@@ -89,6 +81,17 @@ __global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int 
   }
 }
 
+__global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows, int nl, int pad,
+                         int8_t* __restrict__ dst) {
+  recode_body(src, lds, npan, NT, nrows, nl, pad, dst, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batch: blockIdx.y is the record
+__global__ void k_recode_b(const RecodeArgs* __restrict__ tab) {
+  const RecodeArgs& a = tab[blockIdx.y];
+  recode_body(a.src, a.lds, a.npan, a.NT, a.nrows, a.nl, a.pad, a.dst, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
 
 // index of tile (R, C) among the tiles of one launch, for its carry slots
@@ -100,32 +103,10 @@ __device__ __forceinline__ size_t launch_tile_index(const UpdArgs& g, int R, int
   return (size_t)(R - C_lo) * g.ntc + C;
 }
 
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
+// The update of tile (R, C) over output blocks [tb0, tb1); the carry out of the
+// range goes to cb (1024 entries).
+__device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int tb0, int tb1, long long* cb) {
   const UpdArgs& g = m.g;
-  // Work items (range rg, tile lt) in range-major order; the workgroups of a
-  // launch are dealt to the 8 XCDs in turn, so block b takes item
-  // (b % 8) * per_xcd + b / 8: the waves resident on one XCD share a limb range
-  // and hold neighbouring tiles, and read the same digit slices from its L2.
-  const int b = blockIdx.x;
-  const int item = (b & 7) * per_xcd + (b >> 3);
-  if (item >= ntiles * rt.n) return;
-  const int rg = item / ntiles, lt = item - rg * ntiles;
-  // triangular target: tiles (R, C), C_lo <= C <= R, row by row; rectangular:
-  // tile rows from C_lo (here the first tile row), all g.ntc tile columns
-  int R, C;
-  if (g.tri) {
-    int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
-    while (r > 0 && r * (r + 1) / 2 > lt) --r;
-    while ((r + 1) * (r + 2) / 2 <= lt) ++r;
-    R = C_lo + r;
-    C = C_lo + (lt - r * (r + 1) / 2);
-  } else {
-    R = C_lo + lt / g.ntc;
-    C = lt % g.ntc;
-  }
-  if (R * 32 >= m.NT) return;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   if (has_error(g.st)) return;
   __shared__ i64 carry_s[16 * WAVE];  // carry of each of the lane's 16 entries
@@ -143,7 +124,6 @@ void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
     const int r = R * 32 + mf_row(l, v), c = C * 32 + mf_col(l);
     if ((!g.tri || r >= c) && r >= g.r_lo && r < g.r_hi && c >= g.c_lo && c < g.c_hi) live |= 1u << v;
   }
-  const int tb0 = rt.tb[rg], tb1 = rt.tb[rg + 1];
   for (int tb = tb0; tb < tb1; ++tb) {
     const int t0 = MF_T * tb;
     v16i acc[MF_T];
@@ -211,16 +191,73 @@ void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
     }
   }
   // carries out of this range
-  long long* cb = m.carry + ((size_t)lt * rt.n + rg) * 1024;
 #pragma unroll
   for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry_s[v * WAVE + l];
 }
 
-// Add the carries of range w at limb MF_LPB tb[w+1] of every entry, w = 0..n-2.
-__global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) {
+// tile (R, C) of work item lt of an entry's launch (see k_upd_mfma)
+__device__ __forceinline__ void item_tile(const UpdArgs& g, int C_lo, int lt, int* R, int* C) {
+  if (g.tri) {
+    int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
+    while (r > 0 && r * (r + 1) / 2 > lt) --r;
+    while ((r + 1) * (r + 2) / 2 <= lt) ++r;
+    *R = C_lo + r;
+    *C = C_lo + (lt - r * (r + 1) / 2);
+  } else {
+    *R = C_lo + lt / g.ntc;
+    *C = lt % g.ntc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   const UpdArgs& g = m.g;
-  const int R = C_lo + blockIdx.x, C = g.tri ? C_lo + blockIdx.y : blockIdx.y;
-  if ((g.tri && R < C) || R * 32 >= m.NT) return;
+  // Work items (range rg, tile lt) in range-major order; the workgroups of a
+  // launch are dealt to the 8 XCDs in turn, so block b takes item
+  // (b % 8) * per_xcd + b / 8: the waves resident on one XCD share a limb range
+  // and hold neighbouring tiles, and read the same digit slices from its L2.
+  const int b = blockIdx.x;
+  const int item = (b & 7) * per_xcd + (b >> 3);
+  if (item >= ntiles * rt.n) return;
+  const int rg = item / ntiles, lt = item - rg * ntiles;
+  // triangular target: tiles (R, C), C_lo <= C <= R, row by row; rectangular:
+  // tile rows from C_lo (here the first tile row), all g.ntc tile columns
+  int R, C;
+  item_tile(g, C_lo, lt, &R, &C);
+  if (R * 32 >= m.NT) return;
+  mfma_tile(m, R, C, rt.tb[rg], rt.tb[rg + 1], m.carry + ((size_t)lt * rt.n + rg) * 1024);
+}
+
+// Batch of updates (one entry per instance) in one persistent launch.  Work
+// items (entry, tile, range) sit in 8 queues, one per XCD, each largest first;
+// a wave takes the next item of its XCD's queue until the queue is empty (every
+// wave reaches that exit: the queues are finite and nothing waits on another
+// wave).  heads[8] must be zero at launch.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_upd_mfma_b(const MfmaEntry* __restrict__ tab, const int4* __restrict__ items, int per_xcd,
+                  unsigned* __restrict__ heads) {
+  const int xcd = blockIdx.x & 7;
+  for (;;) {
+    int k = 0;
+    if (lane_id() == 0) k = (int)atomicAdd(heads + xcd, 1u);
+    k = __shfl(k, 0, WAVE);
+    if (k >= per_xcd) break;
+    const int4 it = items[(size_t)xcd * per_xcd + k];
+    if (it.x < 0) continue;
+    const MfmaEntry& e = tab[it.x];
+    int R, C;
+    item_tile(e.m.g, e.C_lo, it.y, &R, &C);
+    if (R * 32 >= e.m.NT) continue;
+    mfma_tile(e.m, R, C, e.rt.tb[it.z], e.rt.tb[it.z + 1], e.m.carry + ((size_t)it.y * e.rt.n + it.z) * 1024);
+  }
+}
+
+// Add the carries of range w at limb MF_LPB tb[w+1] of every entry, w = 0..n-2.
+__device__ __forceinline__ void carry_fix_body(const MfmaArgs& m, const RangeTab& rt, int C_lo, int bx, int by) {
+  const UpdArgs& g = m.g;
+  const int R = C_lo + bx, C = g.tri ? C_lo + by : by;
+  if ((g.tri && R < C) || R * 32 >= m.NT || (!g.tri && C >= g.ntc)) return;
   if (has_error(g.st)) return;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   const int e = threadIdx.x;  // 0..1023
@@ -259,6 +296,14 @@ __global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) {
   }
 }
 
+__global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) { carry_fix_body(m, rt, C_lo, blockIdx.x, blockIdx.y); }
+
+// batch: blockIdx.z is the entry
+__global__ void k_carry_fix_b(const MfmaEntry* __restrict__ tab) {
+  const MfmaEntry& e = tab[blockIdx.z];
+  if (e.rt.n > 1) carry_fix_body(e.m, e.rt, e.C_lo, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // MFMA output layout probe (test hook): out[v * 64 + l] for two operand patterns.
 __global__ __launch_bounds__(64) void k_mfma_probe(int* out) {
@@ -286,7 +331,7 @@ __global__ __launch_bounds__(64) void k_mfma_probe(int* out) {
 
 // ---------------------------------------------------------------------------
 // Digit-pair work of output block tb (the (t, j) pairs it multiplies).
-static double block_work(int tb, int S) {
+double block_work(int tb, int S) {
   double w = 0;
   for (int q = 0; q < MF_T; ++q) {
     const int t = MF_T * tb + q;
@@ -302,9 +347,8 @@ static double block_work(int tb, int S) {
 // number of ranges minimises the launch's time in units of one tile's work,
 // rounds x (1/n + per-item cost), where one round is one wave on each of the
 // 1024 SIMDs (8 XCDs x 128).
-static RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items) {
+RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items) {
   const int ntb = 8 * nl / MF_T;
-  RangeTab rt{};
   int cap = max_ranges < MF_MAX_RANGES ? max_ranges : MF_MAX_RANGES;
   if (cap > ntb) cap = ntb;
   if (cap < 1) cap = 1;
@@ -321,6 +365,16 @@ static RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t ma
       want = n;
     }
   }
+  return split_ranges(nl, S, want);
+}
+
+// n ranges of about equal work
+RangeTab split_ranges(int nl, int S, int want) {
+  const int ntb = 8 * nl / MF_T;
+  RangeTab rt{};
+  if (want < 1) want = 1;
+  if (want > MF_MAX_RANGES) want = MF_MAX_RANGES;
+  if (want > ntb) want = ntb;
   double total = 0;
   for (int tb = 0; tb < ntb; ++tb) total += block_work(tb, S);
   rt.tb[0] = 0;
@@ -398,6 +452,30 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int NT_max, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const int threads = NT_max * 16;
+  hipLaunchKernelGGL(k_recode_b, dim3((threads + 255) / 256, count), dim3(256), 0, stream, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_upd_mfma_batch(const MfmaEntry* tab, const int4* items, int per_xcd, unsigned* heads,
+                                 hipStream_t stream) {
+  if (per_xcd <= 0) return hipSuccess;
+  hipError_t e = launch_fill(heads, 8, 0u, stream);
+  if (e != hipSuccess) return e;
+  // one wave per SIMD of each XCD (32 CUs x 4), no more than the queue holds
+  const int waves = per_xcd < 128 ? per_xcd : 128;
+  hipLaunchKernelGGL(k_upd_mfma_b, dim3(8 * waves), dim3(64), 0, stream, tab, items, per_xcd, heads);
+  return hipGetLastError();
+}
+
+hipError_t launch_carry_fix_batch(const MfmaEntry* tab, int count, int nrow_max, int ncol_max, hipStream_t stream) {
+  if (count <= 0 || nrow_max <= 0 || ncol_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_carry_fix_b, dim3(nrow_max, ncol_max, count), dim3(1024), 0, stream, tab);
+  return hipGetLastError();
 }
 
 hipError_t launch_mfma_probe(int* out, hipStream_t stream) {

@@ -27,9 +27,9 @@ __device__ __forceinline__ u32* entry_base(const UpdArgs& g, int r, int c) {
 }
 
 template <int Q>
-__global__ __launch_bounds__(64) void k_upd_valu(UpdArgs g) {
-  const int r = g.r_lo + blockIdx.x;
-  const int c = g.c_lo + blockIdx.y;
+__device__ void upd_valu_body(const UpdArgs& g, int bx, int by) {
+  const int r = g.r_lo + bx;
+  const int c = g.c_lo + by;
   if (r >= g.r_hi || c >= g.c_hi) return;
   if (g.tri && r < c) return;
   if (has_error(g.st)) return;
@@ -103,32 +103,58 @@ __global__ __launch_bounds__(64) void k_upd_valu(UpdArgs g) {
 }
 
 template <int Q>
-static hipError_t launch_q(const UpdArgs& g, hipStream_t stream) {
-  const int nr = g.r_hi - g.r_lo, nc = g.c_hi - g.c_lo;
-  if (nr <= 0 || nc <= 0 || g.npan <= 0) return hipSuccess;
-  const size_t lds = (size_t)2 * g.nl * 4;
-  hipLaunchKernelGGL(k_upd_valu<Q>, dim3(nr, nc), dim3(64), lds, stream, g);
+__global__ __launch_bounds__(64) void k_upd_valu(UpdArgs g) {
+  upd_valu_body<Q>(g, blockIdx.x, blockIdx.y);
+}
+
+// batch: blockIdx.z is the instance; every record fits Q
+template <int Q>
+__global__ __launch_bounds__(64) void k_upd_valu_b(const UpdArgs* __restrict__ tab) {
+  upd_valu_body<Q>(tab[blockIdx.z], blockIdx.x, blockIdx.y);
+}
+
+// one launch of either form: g != nullptr (single record by value) or tab
+template <int Q>
+static hipError_t launch_q(const UpdArgs* g, const UpdArgs* tab, int count, int nr, int nc, int nl,
+                           hipStream_t stream) {
+  if (nr <= 0 || nc <= 0 || count <= 0) return hipSuccess;
+  const size_t lds = (size_t)2 * nl * 4;
+  if (g)
+    hipLaunchKernelGGL(k_upd_valu<Q>, dim3(nr, nc), dim3(64), lds, stream, *g);
+  else
+    hipLaunchKernelGGL(k_upd_valu_b<Q>, dim3(nr, nc, count), dim3(64), lds, stream, tab);
   return hipGetLastError();
 }
 
+static hipError_t launch_any(const UpdArgs* g, const UpdArgs* tab, int count, int nr, int nc, int nw, int nl,
+                             hipStream_t stream) {
+  const int Qn = (nw + WAVE - 1) / WAVE;
+  if (Qn <= 1) return launch_q<1>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 2) return launch_q<2>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 3) return launch_q<3>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 4) return launch_q<4>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 6) return launch_q<6>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 8) return launch_q<8>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 10) return launch_q<10>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 12) return launch_q<12>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 16) return launch_q<16>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 20) return launch_q<20>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 24) return launch_q<24>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 32) return launch_q<32>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 40) return launch_q<40>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 48) return launch_q<48>(g, tab, count, nr, nc, nl, stream);
+  if (Qn <= 56) return launch_q<56>(g, tab, count, nr, nc, nl, stream);
+  return launch_q<64>(g, tab, count, nr, nc, nl, stream);
+}
+
 hipError_t launch_upd_valu(const UpdArgs& g, hipStream_t stream) {
-  const int Qn = (g.nw + WAVE - 1) / WAVE;
-  if (Qn <= 1) return launch_q<1>(g, stream);
-  if (Qn <= 2) return launch_q<2>(g, stream);
-  if (Qn <= 3) return launch_q<3>(g, stream);
-  if (Qn <= 4) return launch_q<4>(g, stream);
-  if (Qn <= 6) return launch_q<6>(g, stream);
-  if (Qn <= 8) return launch_q<8>(g, stream);
-  if (Qn <= 10) return launch_q<10>(g, stream);
-  if (Qn <= 12) return launch_q<12>(g, stream);
-  if (Qn <= 16) return launch_q<16>(g, stream);
-  if (Qn <= 20) return launch_q<20>(g, stream);
-  if (Qn <= 24) return launch_q<24>(g, stream);
-  if (Qn <= 32) return launch_q<32>(g, stream);
-  if (Qn <= 40) return launch_q<40>(g, stream);
-  if (Qn <= 48) return launch_q<48>(g, stream);
-  if (Qn <= 56) return launch_q<56>(g, stream);
-  return launch_q<64>(g, stream);
+  if (g.npan <= 0) return hipSuccess;
+  return launch_any(&g, nullptr, 1, g.r_hi - g.r_lo, g.c_hi - g.c_lo, g.nw, g.nl, stream);
+}
+
+hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int nc_max, int nw_max, int nl_max,
+                                 hipStream_t stream) {
+  return launch_any(nullptr, tab, count, nr_max, nc_max, nw_max, nl_max, stream);
 }
 
 }  // namespace hl

@@ -1,0 +1,113 @@
+"""Batched path (hl_batch_*): a batch of uneven instances gives, on every replay
+of its captured graph, the same bits as the single-instance path (itself
+bit-exact with the oracle), and the oracle's pivots and block directly for the
+small instances; the autotuner's choice gives the same bits."""
+import math
+from fractions import Fraction
+
+import pytest
+import torch
+
+from hankel_inputs import batch_configs, moments
+from oracle import contract as C
+
+from gpu_util import ctx, say
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    (Fraction(1, 2), 64, 8, 2048, 16, "mfma"),
+    (Fraction(1), 40, 5, 1024, 7, "valu"),
+    (Fraction(1, 3), 100, 8, 4096, 16, "mfma"),
+    (Fraction(2, 3), 33, 3, 1536, 16, "mfma"),
+    (Fraction(1, 2), 130, 16, 8192, 16, "mfma"),
+    (Fraction(1), 17, 1, 512, 1, "valu"),
+]
+
+
+def _mu(beta, N, P):
+    return moments(beta, 2 * N - 1, P + 64)
+
+
+def _single(mu, N, k, P, E, form):
+    fac = ctx().factor(mu, N, k, P, E, form)
+    res = ctx().lambda_min(fac)
+    return fac, res
+
+
+def _same(fb, fs, N):
+    assert fb.pivots() == fs.pivots()
+    assert torch.equal(fb.l, fs.l)
+    assert torch.equal(fb.x[:fs.x.numel()], fs.x)
+    assert fb.block() == fs.block()
+
+
+def test_batch_matches_single_instances_over_replays():
+    from paper_1810_01478_amd.api import Batch
+    mus = [_mu(b, N, P) for (b, N, k, P, E, f) in SPECS]
+    say("batch of", len(SPECS))
+    batch = Batch(ctx(), [(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, SPECS)])
+    singles = [_single(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, SPECS)]
+    for rep in range(3):
+        say("replay", rep)
+        batch.launch()
+        res = batch.results()
+        for j, ((b, N, k, P, E, f), (fs, rs)) in enumerate(zip(SPECS, singles)):
+            assert res[j]["status"] == 0
+            _same(batch.facs[j], fs, N)
+            assert res[j]["lambda1"] == rs["lambda1"], j
+            assert res[j]["trunc"] == rs["trunc"] or (math.isnan(res[j]["trunc"]) and math.isnan(rs["trunc"])), j
+        # eager work on the same device between replays
+        _single(mus[0], *SPECS[0][1:])
+        torch.cuda.synchronize()
+    # the oracle directly, for the instances it finishes quickly
+    for j, (b, N, k, P, E, f) in enumerate(SPECS):
+        if N > 70:
+            continue
+        fo, sv, bl, ev = C.lambda_min(mus[j], N, k, P, E)
+        assert batch.facs[j].pivots() == fo.d, j
+        blk, bexp = batch.facs[j].block()
+        assert blk == bl.blk and bexp == bl.blk_exp, j
+    batch.close()
+
+
+def test_autotuned_batch_gives_the_same_bits():
+    from paper_1810_01478_amd.api import Batch, autotune
+    specs = SPECS[:4]
+    mus = [_mu(b, N, P) for (b, N, k, P, E, f) in specs]
+    batch = Batch(ctx(), [(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, specs)])
+    tune, ms = autotune(batch, panels=2)
+    say("autotune", tune, "%.2f ms" % ms)
+    assert tune["items_per_simd"] in (1, 2, 4, 8) and ms > 0
+    tuned = Batch(ctx(), [(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, specs)], tune=tune)
+    batch.launch()
+    r0 = batch.results()
+    tuned.launch()
+    r1 = tuned.results()
+    for j in range(len(specs)):
+        _same(tuned.facs[j], batch.facs[j], specs[j][1])
+        assert r0[j]["lambda1"] == r1[j]["lambda1"]
+    batch.close()
+    tuned.close()
+
+
+@pytest.mark.timeout(600)
+def test_batched_workload_sampled_against_single_instances():
+    # the batched workload: 64 instances, beta in {1/3, 1/2, 2/3, 1}, N in
+    # [32, 512], P from the condition estimate; four instances re-run alone
+    from paper_1810_01478_amd.api import Batch
+    cfg = batch_configs()
+    specs = [(moments(b, 2 * N - 1, P + 64), N, 8, P, 16, "mfma") for (b, N, P) in cfg]
+    say("batched workload", len(specs))
+    batch = Batch(ctx(), specs)
+    batch.launch()
+    res = batch.results()
+    assert all(r["status"] == 0 for r in res)
+    assert all(r["lambda1"] > 0 and r["trunc"] <= 0 for r in res)
+    for j in (0, 7, 31, 63):
+        mu, N, k, P, E, f = specs[j]
+        say("  instance", j, cfg[j])
+        fs, rs = _single(mu, N, k, P, E, f)
+        _same(batch.facs[j], fs, N)
+        assert res[j]["lambda1"] == rs["lambda1"]
+    batch.close()
