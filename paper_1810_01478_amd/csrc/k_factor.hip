@@ -297,7 +297,10 @@ __global__ __launch_bounds__(PIVOT_THREADS) void k_pivot_b(const PivotArgs* __re
 // Factor columns of pivot i for rows r in [r0, NT):
 //   u_r = rnd(a_ri / 2^h_i),  b_r = rnd(u_r w_i / 2^P),
 // both two's complement over nl limbs; rows r <= i and r >= N give zeros.
-// u goes to the panel buffer, b to the multiplier array L (column i).
+// u goes to the panel buffer, b to the multiplier array L (column i).  One
+// workgroup of COL_THREADS per row: the product u w is formed by all its waves.
+constexpr int COL_THREADS = 256;
+
 __device__ void col_body(const ColArgs& a, int bx) {
   const u32* __restrict__ A = a.A;
   const Dims dm = a.dm;
@@ -315,71 +318,71 @@ __device__ void col_body(const ColArgs& a, int bx) {
   u32* uo = u_out + (size_t)r * nl;
   u32* bo = l_col + (size_t)r * nl;
   if (r <= i || r >= dm.N) {
-    for (int l = lane_id(); l < nl; l += WAVE) {
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
       uo[l] = 0;
       bo[l] = 0;
     }
     return;
   }
   extern __shared__ u32 lds[];
-  u32* As = lds;                 // nw + 4
-  u32* Us = As + nw + 4;         // nl + 4
-  u32* Ws = Us + nl + 4;         // nl + 4
-  u32* Bs = Ws + nl + 4;         // nl + 4
+  int* flag = (int*)lds;              // 4
+  u32* As = lds + 4;                  // nw + 4
+  u32* Us = As + nw + 4;              // nl + 4
+  u32* Ws = Us + nl + 4;              // nl + 4
+  u32* Pr = Ws + nl + 4;              // 2 nl + 4
+  u32* cb = Pr + 2 * nl + 4;          // 3 (2 nl + 1)
+  const int w0 = wave_id() == 0;
   const u32* src = A + tri_tile_index(r >> 5, i >> 5) * tile_words(nw);
-  for (int l = lane_id(); l < nw; l += WAVE) As[l] = src[in_tile(r, i, l)];
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) As[l] = src[in_tile(r, i, l)];
   const u32* om = omega_tab + (size_t)i * omega_stride;
-  for (int l = lane_id(); l < nl + 4; l += WAVE) Ws[l] = l < omega_stride ? om[l] : 0u;
+  for (int l = threadIdx.x; l < nl + 4; l += blockDim.x) Ws[l] = l < omega_stride ? om[l] : 0u;
   __syncthreads();
   const bool neg = (As[nw - 1] >> 31) != 0;
-  if (neg) w_neg(As, nw);
-  __syncthreads();
-  const int h = h_tab[i];
-  if (h > 0) w_add_word(As, nw, (h - 1) >> 5, 1u << ((h - 1) & 31));
-  __syncthreads();
-  w_shift_right(As, nw, h, Us, nl + 1);
-  __syncthreads();
   const u32 lim_top = 0x60000000u;  // 3 * 2^(P-3) in the top limb
-  if (Us[nl] != 0 || Us[nl - 1] >= lim_top) {
-    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
-    return;
-  }
-  // Bs = (Us * w + 2^(P-1)) >> P : limbs nl .. 2nl of the sum
-  const int nch = (2 * nl + 1 + WAVE - 1) / WAVE;
-  w_mul_stream(
-      Us, nl, Ws, nl + 1, nch,
-      [&](int ch, u32 limb) {
-        const int p = ch * WAVE + lane_id();
-        if (p >= nl && p <= 2 * nl) Bs[p - nl] = limb;
-      },
-      [&](int ch, u64& lo, u32& hi) {
-        const int t = ch * WAVE + lane_id();
-        if (t == nl - 1) {
-          const u64 s2 = lo + 0x80000000ull;
-          hi += (s2 < lo) ? 1u : 0u;
-          lo = s2;
-        }
-      });
-  __syncthreads();
-  if (Bs[nl] != 0 || Bs[nl - 1] >= lim_top) {
-    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
-    return;
-  }
-  if (neg) {
-    w_neg(Us, nl);
-    w_neg(Bs, nl);
+  if (w0) {
+    if (neg) w_neg(As, nw);
+    wsync();
+    const int h = h_tab[i];
+    if (h > 0) w_add_word(As, nw, (h - 1) >> 5, 1u << ((h - 1) & 31));
+    wsync();
+    w_shift_right(As, nw, h, Us, nl + 1);
+    wsync();
+    if (lane_id() == 0) flag[0] = (Us[nl] != 0 || Us[nl - 1] >= lim_top) ? 1 : 0;
   }
   __syncthreads();
-  for (int l = lane_id(); l < nl; l += WAVE) {
-    uo[l] = Us[l];
-    bo[l] = Bs[l];
+  if (flag[0]) {
+    if (threadIdx.x == 0) set_status(st, HL_EOVERFLOW, i);
+    return;
   }
+  // b = (u w + 2^(P-1)) >> P: limbs nl .. 2nl of the product plus the half
+  g_mul(Us, nl, Ws, nl + 1, Pr, 2 * nl + 1, cb);
+  if (w0) {
+    w_add_word(Pr, 2 * nl + 1, nl - 1, 0x80000000u);
+    wsync();
+    if (lane_id() == 0) flag[1] = (Pr[2 * nl] != 0 || Pr[2 * nl - 1] >= lim_top) ? 1 : 0;
+    wsync();
+    if (!flag[1]) {
+      if (neg) {
+        w_neg(Us, nl);
+        w_neg(Pr + nl, nl);
+      }
+      wsync();
+      for (int l = lane_id(); l < nl; l += WAVE) {
+        uo[l] = Us[l];
+        bo[l] = Pr[nl + l];
+      }
+    }
+  }
+  __syncthreads();
+  if (flag[1] && threadIdx.x == 0) set_status(st, HL_EOVERFLOW, i);
 }
 
-__global__ __launch_bounds__(64) void k_col(ColArgs a) { col_body(a, blockIdx.x); }
+__global__ __launch_bounds__(COL_THREADS) void k_col(ColArgs a) { col_body(a, blockIdx.x); }
 
 // batch: blockIdx.y is the instance, blockIdx.x the row offset
-__global__ __launch_bounds__(64) void k_col_b(const ColArgs* __restrict__ tab) { col_body(tab[blockIdx.y], blockIdx.x); }
+__global__ __launch_bounds__(COL_THREADS) void k_col_b(const ColArgs* __restrict__ tab) {
+  col_body(tab[blockIdx.y], blockIdx.x);
+}
 
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u32(u32* __restrict__ p, size_t n, u32 v) {
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(PIVOT_THREADS) void k_debug_recip(const u32* d, int
 // ---------------------------------------------------------------------------
 // host launchers
 size_t pivot_lds_bytes(int nl) { return (size_t)(15 * (nl + 8) + 2 * nl + 8) * 4; }
-size_t col_lds_bytes(int nl) { return (size_t)(2 * nl + 4 + 3 * (nl + 4)) * 4; }
+size_t col_lds_bytes(int nl) { return (size_t)(4 + 2 * nl + 4 + 2 * (nl + 4) + 2 * nl + 4 + 3 * (2 * nl + 1)) * 4; }
 
 hipError_t launch_scales(const u32* mu, const i64* mu_exp, int w, int N, int E, i32* s, DevStatus* st,
                          hipStream_t stream) {
@@ -444,7 +447,9 @@ hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h,
   const int nrows = dm.NT - r0;
   if (nrows <= 0) return hipSuccess;
   const ColArgs a{A, dm, i, r0, h, omega, ostride, u_out, l_col, st};
-  hipLaunchKernelGGL(k_col, dim3(nrows), dim3(64), col_lds_bytes(dm.nl), stream, a);
+  hipError_t e = allow_lds((const void*)k_col, col_lds_bytes(dm.nl));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col, dim3(nrows), dim3(COL_THREADS), col_lds_bytes(dm.nl), stream, a);
   return hipGetLastError();
 }
 
@@ -458,7 +463,9 @@ hipError_t launch_pivot_batch(const PivotArgs* tab, int count, int nl_max, hipSt
 
 hipError_t launch_col_batch(const ColArgs* tab, int count, int rows_max, int nl_max, hipStream_t stream) {
   if (count <= 0 || rows_max <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_col_b, dim3(rows_max, count), dim3(64), col_lds_bytes(nl_max), stream, tab);
+  hipError_t e = allow_lds((const void*)k_col_b, col_lds_bytes(nl_max));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_b, dim3(rows_max, count), dim3(COL_THREADS), col_lds_bytes(nl_max), stream, tab);
   return hipGetLastError();
 }
 
