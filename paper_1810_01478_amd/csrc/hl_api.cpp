@@ -492,7 +492,7 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   DevStatus* dst = (DevStatus*)(base + L.status);
   void* ews = base + L.eig;
   Stamp te(ctx, st, 4);
-  HIPCHK(launch_eig(blk, dm, ews, dst, st));
+  HIPCHK(launch_eig_host(blk, dm, ews, dst, st));
   te.end();
   int32_t idx = 0;
   if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;

@@ -134,6 +134,8 @@ struct EigArgs {
   DevStatus* st;
 };
 EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st);
+// the same eigen-step driven from the host, one workgroup per product (synchronises)
+hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
 hipError_t launch_eig_batch(const EigArgs* tab, int count, int nl_max, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
 void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out);

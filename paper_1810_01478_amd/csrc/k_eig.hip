@@ -315,7 +315,11 @@ __host__ __device__ __forceinline__ int ix_inv(int n, int a) { return 3 * n * n 
 __host__ __device__ __forceinline__ int ix_s(int n, int j) { return 3 * n * n + 4 * n + j; }  // scalars
 // per-wave scratch numbers: after the scalars
 __host__ __device__ __forceinline__ int ix_w(int n, int w, int j) { return 3 * n * n + 4 * n + EIG_NSCAL + w * 4 + j; }
-__host__ __device__ __forceinline__ int eig_numbers(int n) { return 3 * n * n + 4 * n + EIG_NSCAL + EIG_WAVES * 4; }
+// per-target scratch numbers of the multi-workgroup form: n x n after the above
+__host__ __device__ __forceinline__ int ix_T(int n, int a, int b) {
+  return 3 * n * n + 4 * n + EIG_NSCAL + EIG_WAVES * 4 + a * n + b;
+}
+__host__ __device__ __forceinline__ int eig_numbers(int n) { return 4 * n * n + 4 * n + EIG_NSCAL + EIG_WAVES * 4; }
 
 __device__ __forceinline__ FpRef num(const EigMat& M, int i) {
   return FpRef{M.hdr + 2 * i, M.mant + (size_t)i * M.NWM};
@@ -688,6 +692,605 @@ __device__ void eig_diff_body(const EigArgs& ea) {
 
 __global__ __launch_bounds__(64) void k_eig_diff(EigArgs a) { eig_diff_body(a); }
 __global__ __launch_bounds__(64) void k_eig_diff_b(const EigArgs* __restrict__ tab) { eig_diff_body(tab[blockIdx.x]); }
+
+// ---------------------------------------------------------------------------
+// The same iteration, run from the host as a sequence of launches: every
+// independent multiprecision product of a phase gets a workgroup of its own
+// (EIG2_THREADS threads, the product formed by all its waves), so a step costs
+// about one product's time instead of (products / waves) of them.  Each
+// number sees exactly the operations, in the same order, as in k_eig, so the
+// results are the same bits.  The host reads the bracket's state back at the
+// two decision points of an iteration (positive definite?  bits resolved?).
+constexpr int EIG2_THREADS = 256;
+
+// workgroup context: wave scratch la, lb (NWM + 8 each), product (2 NWM),
+// column sums (6 NWM)
+struct WgCtx {
+  FpCtx c;
+  u32* pr;
+  u32* cb;
+};
+
+__device__ __forceinline__ WgCtx wg_ctx(int NWM, int nw) {
+  extern __shared__ u32 lds2[];
+  WgCtx g;
+  g.c.NWM = NWM;
+  g.c.nw = nw;
+  g.c.la = lds2 + 16;
+  g.c.lb = g.c.la + NWM + 8;
+  g.pr = g.c.lb + NWM + 8;
+  g.cb = g.pr + 2 * NWM + 8;
+  return g;
+}
+
+size_t eig2_lds_bytes(int NWM) { return (size_t)(16 + 2 * (NWM + 8) + 2 * NWM + 8 + 6 * NWM + 8) * 4; }
+
+// z = x * y with every thread of the workgroup (the bits of fp_mul)
+__device__ void wg_fp_mul(const WgCtx& g, FpRef z, const FpRef& x, const FpRef& y) {
+  const FpCtx& c = g.c;
+  const bool zero = fp_is_zero(x) || fp_is_zero(y);
+  const int sx = x.hdr[0], sy = y.hdr[0], e = x.hdr[1] + y.hdr[1];
+  __syncthreads();
+  if (zero) {
+    if (wave_id() == 0) fp_set_zero(c, z);
+    __syncthreads();
+    return;
+  }
+  const int nw = c.nw, top = c.NWM - nw;
+  u32* A = c.la;
+  u32* B = c.lb;
+  for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+    A[j] = x.m[top + j];
+    B[j] = y.m[top + j];
+  }
+  __syncthreads();
+  g_mul(A, nw, B, nw, g.pr, 2 * nw, g.cb);
+  // product limbs nw-1 .. 2nw-1, normalised by at most one bit, to the top nw
+  const u32* Q = g.pr + (nw - 1);
+  const bool low = (Q[nw] >> 31) == 0;
+  for (int j = threadIdx.x; j < c.NWM; j += blockDim.x) {
+    u32 v = 0;
+    if (j >= top) {
+      const int i = j - top;  // 0 .. nw-1
+      v = low ? ((Q[i + 1] << 1) | (Q[i] >> 31)) : Q[i + 1];
+    }
+    z.m[j] = v;
+  }
+  if (threadIdx.x == 0) {
+    z.hdr[0] = sx ^ sy;
+    z.hdr[1] = e - (low ? 1 : 0);
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+// wave 0 runs a wave operation, then the workgroup meets
+#define WG_WAVE0(...)                   \
+  do {                                  \
+    if (wave_id() == 0) { __VA_ARGS__; } \
+    __syncthreads();                    \
+  } while (0)
+
+// 1 / x as fp_recip does it, the products on the workgroup
+__device__ void wg_fp_recip(const WgCtx& g0, FpRef z, const FpRef& x, FpRef t1, FpRef t2) {
+  WgCtx g = g0;
+  const FpCtx& c0 = g0.c;
+  const u32 m1 = x.m[c0.NWM - 1], m0 = x.m[c0.NWM - 2];
+  const u64 topv = ((u64)m1 << 32) | m0;
+  const u64 top32 = topv >> 32;
+  u64 q = (~0ull) / (top32 + 1);
+  if (q < (1ull << 32)) q = 1ull << 32;
+  const int xs = x.hdr[0], xe = x.hdr[1];
+  __syncthreads();
+  for (int j = threadIdx.x; j < c0.NWM; j += blockDim.x) {
+    u32 v = 0;
+    if (j == c0.NWM - 1) v = (u32)(q >> 1);
+    if (j == c0.NWM - 2) v = (u32)(q << 31);
+    z.m[j] = v;
+  }
+  if (threadIdx.x == 0) {
+    z.hdr[0] = xs;
+    z.hdr[1] = 1 - xe;
+  }
+  __threadfence_block();
+  __syncthreads();
+  const int target = c0.nw;
+  int prec = 1;
+  for (int it = 0; it < 40; ++it) {
+    int np = 2 * prec;
+    if (np > target) np = target;
+    g.c.nw = np + 1 <= c0.NWM - 1 ? np + 1 : c0.NWM - 1;
+    if (g.c.nw > target) g.c.nw = target;
+    const int passes = (np >= target && it > 0 && np == target) ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+      wg_fp_mul(g, t1, x, z);
+      WG_WAVE0({
+        for (int j = lane_id(); j < g.c.NWM; j += WAVE) t2.m[j] = (j == g.c.NWM - 1) ? 0x80000000u : 0u;
+        if (lane_id() == 0) {
+          t2.hdr[0] = 0;
+          t2.hdr[1] = 1;
+        }
+        wsync();
+        fp_add(g.c, t2, t2, t1, true);
+      });
+      wg_fp_mul(g, t1, z, t2);
+      WG_WAVE0(fp_add(g.c, z, z, t1, false));
+    }
+    prec = np;
+    if (np >= target) break;
+  }
+}
+
+__device__ __forceinline__ EigMat eig_mat(const EigArgs& ea, int which) {
+  EigMat M;
+  M.n = ea.k - which;
+  M.NWM = ea.NWM;
+  M.hdr = ea.hdr + (size_t)which * ea.nums_per * 2;
+  M.mant = ea.mant + (size_t)which * ea.nums_per * ea.NWM;
+  M.flags = ea.flags + which * 8;
+  return M;
+}
+
+// flags of a block: [0] status, [1] iterations, [2] positive definite, [3] bits
+__global__ __launch_bounds__(64) void k_e2_init_b(EigArgs a, int which) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  extern __shared__ u32 lds2[];
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = a.NWM - 1;
+  c.la = lds2;
+  c.lb = lds2 + a.NWM + 8;
+  const int idx = blockIdx.x;
+  if (idx >= n * n) return;
+  fp_from_int(c, num(M, ix_B(n, idx / n, idx % n)), a.blk + ((size_t)(idx / n) * a.k + (idx % n)) * a.nl, a.nl);
+}
+
+// hi = Gershgorin bound (1 + 2^-16), lo = max diagonal, y = 1 (as k_eig)
+__global__ __launch_bounds__(64) void k_e2_init(EigArgs a, int which) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  extern __shared__ u32 lds2[];
+  FpCtx cf;
+  cf.NWM = a.NWM;
+  cf.nw = a.NWM - 1;
+  cf.la = lds2;
+  cf.lb = lds2 + a.NWM + 8;
+  if (n == 1) {
+    fp_copy(cf, num(M, ix_s(n, S_RES)), num(M, ix_B(n, 0, 0)));
+    if (lane_id() == 0) M.flags[1] = 0;
+    return;
+  }
+  FpRef hi = num(M, ix_s(n, S_HI)), lo = num(M, ix_s(n, S_LO));
+  FpRef T = num(M, ix_w(n, 0, 0)), R = num(M, ix_w(n, 0, 1));
+  fp_set_zero(cf, hi);
+  fp_copy(cf, lo, num(M, ix_B(n, 0, 0)));
+  wsync();
+  for (int ia = 0; ia < n; ++ia) {
+    fp_set_zero(cf, R);
+    wsync();
+    for (int ib = 0; ib < n; ++ib) {
+      fp_copy(cf, T, num(M, ix_B(n, ia, ib)));
+      wsync();
+      if (lane_id() == 0 && T.hdr[0] == 1) T.hdr[0] = 0;
+      wsync();
+      fp_add(cf, R, R, T, false);
+    }
+    if (fp_cmp(cf, R, hi) > 0) fp_copy(cf, hi, R);
+    wsync();
+    if (fp_cmp(cf, num(M, ix_B(n, ia, ia)), lo) > 0) fp_copy(cf, lo, num(M, ix_B(n, ia, ia)));
+    wsync();
+  }
+  fp_copy(cf, T, hi);
+  wsync();
+  fp_ldexp(T, -16);
+  fp_add(cf, hi, hi, T, false);
+  for (int ia = 0; ia < n; ++ia) {
+    FpRef y = num(M, ix_y(n, ia));
+    for (int j = lane_id(); j < a.NWM; j += WAVE) y.m[j] = (j == a.NWM - 1) ? 0x80000000u : 0u;
+    if (lane_id() == 0) {
+      y.hdr[0] = 0;
+      y.hdr[1] = 1;
+    }
+  }
+  wsync();
+}
+
+// C = sigma I - B (one wave per entry)
+__global__ __launch_bounds__(64) void k_e2_shift(EigArgs a, int which, int nw, int sig) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n, idx = blockIdx.x;
+  extern __shared__ u32 lds2[];
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = nw;
+  c.la = lds2;
+  c.lb = lds2 + a.NWM + 8;
+  const int ia = idx / n, ib = idx % n;
+  FpRef C = num(M, ix_C(n, ia, ib));
+  FpRef B = num(M, ix_B(n, ia, ib));
+  if (ia == ib) {
+    fp_add(c, C, num(M, ix_s(n, sig)), B, true);
+  } else {
+    fp_copy(c, C, B);
+    wsync();
+    if (lane_id() == 0 && C.hdr[0] != FPZERO_TAG) C.hdr[0] ^= 1;
+  }
+  if (idx == 0 && lane_id() == 0) M.flags[2] = 1;
+}
+
+// pivot i: positive?  inv_i = 1 / C_ii
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_pivot(EigArgs a, int which, int nw, int i) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  if (!M.flags[2]) return;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  FpRef d = num(M, ix_C(n, i, i));
+  const bool pos = !fp_is_zero(d) && d.hdr[0] == 0;
+  __syncthreads();
+  if (!pos) {
+    if (threadIdx.x == 0) M.flags[2] = 0;
+    return;
+  }
+  wg_fp_recip(g, num(M, ix_inv(n, i)), d, num(M, ix_w(n, 0, 0)), num(M, ix_w(n, 0, 1)));
+}
+
+// L_ri = C_ri inv_i, r = i + 1 + blockIdx.x
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_lcol(EigArgs a, int which, int nw, int i) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n, r = i + 1 + blockIdx.x;
+  if (!M.flags[2] || r >= n) return;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  wg_fp_mul(g, num(M, ix_L(n, r, i)), num(M, ix_C(n, r, i)), num(M, ix_inv(n, i)));
+}
+
+// C_rc -= L_ri C_ci for r >= c > i (one workgroup per pair)
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_update(EigArgs a, int which, int nw, int i) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  if (!M.flags[2]) return;
+  // pair index p -> (r, c) with i < c <= r < n, row by row
+  const int p = blockIdx.x;
+  int rr = 0;
+  while ((rr + 1) * (rr + 2) / 2 <= p) ++rr;
+  const int r = i + 1 + rr, cc = i + 1 + (p - rr * (rr + 1) / 2);
+  if (r >= n) return;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  FpRef T = num(M, ix_T(n, r, cc));
+  wg_fp_mul(g, T, num(M, ix_L(n, r, i)), num(M, ix_C(n, cc, i)));
+  WG_WAVE0(fp_add(g.c, num(M, ix_C(n, r, cc)), num(M, ix_C(n, r, cc)), T, true));
+}
+
+// vector copies: mode 0 t = y, 1 z = t
+__global__ __launch_bounds__(64) void k_e2_copy(EigArgs a, int which, int nw, int mode) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n, ia = blockIdx.x;
+  if (ia >= n) return;
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = nw;
+  if (mode == 0) fp_copy(c, num(M, ix_t(n, ia)), num(M, ix_y(n, ia)));
+  else fp_copy(c, num(M, ix_z(n, ia)), num(M, ix_t(n, ia)));
+}
+
+// forward (dir 0): t_r -= L_rj t_j, r > j;  backward (dir 1): t_r -= L_jr t_j, r < j
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_sweep(EigArgs a, int which, int nw, int j, int dir) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  const int r = dir == 0 ? j + 1 + blockIdx.x : blockIdx.x;
+  if (dir == 0 ? r >= n : r >= j) return;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  FpRef T = num(M, ix_T(n, r, 0));
+  if (dir == 0) wg_fp_mul(g, T, num(M, ix_L(n, r, j)), num(M, ix_t(n, j)));
+  else wg_fp_mul(g, T, num(M, ix_L(n, j, r)), num(M, ix_t(n, j)));
+  WG_WAVE0(fp_add(g.c, num(M, ix_t(n, r)), num(M, ix_t(n, r)), T, true));
+}
+
+// t_a *= inv_a
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_scale(EigArgs a, int which, int nw) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n, ia = blockIdx.x;
+  if (ia >= n) return;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  wg_fp_mul(g, num(M, ix_t(n, ia)), num(M, ix_t(n, ia)), num(M, ix_inv(n, ia)));
+}
+
+// y = z 2^-e (as eig_normalise)
+__global__ __launch_bounds__(64) void k_e2_normalise(EigArgs a, int which, int nw) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = nw;
+  int e = INT_MIN;
+  for (int ia = 0; ia < n; ++ia) {
+    FpRef z = num(M, ix_z(n, ia));
+    if (!fp_is_zero(z) && z.hdr[1] > e) e = z.hdr[1];
+  }
+  if (e == INT_MIN) e = 0;
+  for (int ia = 0; ia < n; ++ia) {
+    FpRef y = num(M, ix_y(n, ia));
+    fp_copy(c, y, num(M, ix_z(n, ia)));
+    wsync();
+    fp_ldexp(y, -e);
+  }
+}
+
+// Rayleigh quotient, products: P_ab = B_ab y_b (mode 0), then U_a = y_a t_a,
+// V_a = y_a y_a (mode 1, blockIdx.x = 2a + {0, 1})
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_rq_prod(EigArgs a, int which, int nw, int mode) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n, idx = blockIdx.x;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  if (mode == 0) {
+    if (idx >= n * n) return;
+    const int ia = idx / n, ib = idx % n;
+    wg_fp_mul(g, num(M, ix_T(n, ia, ib)), num(M, ix_B(n, ia, ib)), num(M, ix_y(n, ib)));
+  } else {
+    if (idx >= 2 * n) return;
+    const int ia = idx >> 1;
+    if (idx & 1) wg_fp_mul(g, num(M, ix_T(n, ia, 1)), num(M, ix_y(n, ia)), num(M, ix_y(n, ia)));
+    else wg_fp_mul(g, num(M, ix_T(n, ia, 0)), num(M, ix_y(n, ia)), num(M, ix_t(n, ia)));
+  }
+}
+
+// t_a = sum_b P_ab in order b = 0 .. n-1
+__global__ __launch_bounds__(64) void k_e2_rq_rows(EigArgs a, int which, int nw) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n, ia = blockIdx.x;
+  if (ia >= n) return;
+  extern __shared__ u32 lds2[];
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = nw;
+  c.la = lds2;
+  c.lb = lds2 + a.NWM + 8;
+  FpRef ta = num(M, ix_t(n, ia));
+  fp_set_zero(c, ta);
+  wsync();
+  for (int ib = 0; ib < n; ++ib) fp_add(c, ta, ta, num(M, ix_T(n, ia, ib)), false);
+}
+
+// num = sum U_a, den = sum V_a (in the order of eig_rayleigh), RQ = num / den,
+// lo = max(lo, RQ), bits, trace
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_rq_final(EigArgs a, int which, int nw, int it) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  FpRef num_ = num(M, ix_s(n, S_NUM)), den = num(M, ix_s(n, S_DEN));
+  WG_WAVE0({
+    fp_set_zero(g.c, num_);
+    fp_set_zero(g.c, den);
+    wsync();
+    for (int ia = 0; ia < n; ++ia) {
+      fp_add(g.c, num_, num_, num(M, ix_T(n, ia, 0)), false);
+      fp_add(g.c, den, den, num(M, ix_T(n, ia, 1)), false);
+    }
+  });
+  FpRef inv = num(M, ix_s(n, S_T1));
+  wg_fp_recip(g, inv, den, num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
+  wg_fp_mul(g, num(M, ix_s(n, S_RQ)), num_, inv);
+  WG_WAVE0({
+    FpRef lo = num(M, ix_s(n, S_LO)), rq = num(M, ix_s(n, S_RQ));
+    if (fp_cmp(g.c, rq, lo) > 0) fp_copy(g.c, lo, rq);
+    wsync();
+    const int bits = eig_bits(M, g.c);
+    if (lane_id() == 0) {
+      M.flags[3] = bits;
+      if (it < 24) a.flags[16 + which * 24 + it] = bits * 1000 + nw;
+    }
+  });
+}
+
+// trial upper bound lo + c (hi - lo)^2 / hi, capped at lo + (hi - lo) / 2 and
+// floored at hi 2^-(32 nw - 40) (as k_eig)
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_trial(EigArgs a, int which, int nw, int cexp) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  const WgCtx g = wg_ctx(a.NWM, nw);
+  FpRef hi = num(M, ix_s(n, S_HI)), lo = num(M, ix_s(n, S_LO)), Wd = num(M, ix_s(n, S_W));
+  FpRef T = num(M, ix_s(n, S_T1)), U = num(M, ix_s(n, S_T2)), tr = num(M, ix_s(n, S_TRY));
+  WG_WAVE0(fp_add(g.c, Wd, hi, lo, true));
+  wg_fp_mul(g, T, Wd, Wd);
+  wg_fp_recip(g, U, hi, num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
+  wg_fp_mul(g, T, T, U);
+  WG_WAVE0({
+    fp_ldexp(T, cexp);
+    FpRef half = num(M, ix_s(n, S_T3));
+    fp_copy(g.c, half, Wd);
+    wsync();
+    fp_ldexp(half, -1);
+    if (fp_cmp(g.c, T, half) > 0) fp_copy(g.c, T, half);
+    wsync();
+    fp_copy(g.c, half, hi);
+    wsync();
+    fp_ldexp(half, -(32 * nw - 40));
+    if (fp_cmp(g.c, T, half) < 0) fp_copy(g.c, T, half);
+    wsync();
+    fp_add(g.c, tr, lo, T, false);
+  });
+}
+
+// mode 0: after the trial factorisation, hi = trial (positive definite) or
+// lo = trial; mode 1: widen hi (the factorisation at hi failed); mode 2: the
+// result lo; mode 3: iterations
+__global__ __launch_bounds__(64) void k_e2_control(EigArgs a, int which, int nw, int mode, int val) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  extern __shared__ u32 lds2[];
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = nw;
+  c.la = lds2;
+  c.lb = lds2 + a.NWM + 8;
+  if (mode == 0) {
+    if (M.flags[2]) fp_copy(c, num(M, ix_s(n, S_HI)), num(M, ix_s(n, S_TRY)));
+    else fp_copy(c, num(M, ix_s(n, S_LO)), num(M, ix_s(n, S_TRY)));
+  } else if (mode == 1) {
+    FpRef hi = num(M, ix_s(n, S_HI)), lo = num(M, ix_s(n, S_LO)), T = num(M, ix_w(n, 0, 0));
+    fp_add(c, T, hi, lo, true);
+    if (fp_is_zero(T) || T.hdr[0]) {
+      fp_copy(c, T, hi);
+      wsync();
+      fp_ldexp(T, -20);
+    }
+    fp_add(c, hi, hi, T, false);
+  } else if (mode == 2) {
+    fp_copy(c, num(M, ix_s(n, S_RES)), num(M, ix_s(n, S_LO)));
+  } else if (lane_id() == 0) {
+    M.flags[1] = val;
+  }
+}
+
+// lambda_1 (without the block exponent) = 1 / lambda_max
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_finish(EigArgs a, int which) {
+  const EigMat M = eig_mat(a, which);
+  const int n = M.n;
+  const WgCtx g = wg_ctx(a.NWM, a.NWM - 1);
+  wg_fp_recip(g, num(M, ix_s(n, S_ONE)), num(M, ix_s(n, S_RES)), num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
+}
+
+namespace {
+int read_flag(const EigArgs& a, int which, int slot, hipStream_t st, hipError_t* err) {
+  int v = 0;
+  *err = hipMemcpyAsync(&v, a.flags + which * 8 + slot, 4, hipMemcpyDeviceToHost, st);
+  if (*err == hipSuccess) *err = hipStreamSynchronize(st);
+  return v;
+}
+}  // namespace
+
+#define E2CHK(x)                           \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return e_;       \
+  } while (0)
+
+// one block (which = 0: k x k, 1: (k-1) x (k-1)); *conv = 0 if it did not converge
+static hipError_t eig2_block(const EigArgs& a, int which, hipStream_t st, int* conv) {
+  const int n = a.k - which, NWM = a.NWM, NWF = NWM - 1;
+  const size_t lw = (size_t)2 * (NWM + 8) * 4;   // one wave's scratch
+  const size_t lg = eig2_lds_bytes(NWM);
+  *conv = 1;
+  hipLaunchKernelGGL(k_e2_init_b, dim3(n * n), dim3(64), lw, st, a, which);
+  E2CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_e2_init, dim3(1), dim3(64), lw, st, a, which);
+  E2CHK(hipGetLastError());
+  if (n > 1) {
+    const long target_bits = (long)a.P + 32;
+    int nw = 4 < NWF ? 4 : NWF;
+    float cexp = 2.0f;
+    bool have_factor = false;
+    hipError_t err = hipSuccess;
+    auto factor = [&](int sig) -> hipError_t {
+      hipLaunchKernelGGL(k_e2_shift, dim3(n * n), dim3(64), lw, st, a, which, nw, sig);
+      E2CHK(hipGetLastError());
+      for (int i = 0; i < n; ++i) {
+        hipLaunchKernelGGL(k_e2_pivot, dim3(1), dim3(EIG2_THREADS), lg, st, a, which, nw, i);
+        E2CHK(hipGetLastError());
+        const int m = n - i - 1;
+        if (m > 0) {
+          hipLaunchKernelGGL(k_e2_lcol, dim3(m), dim3(EIG2_THREADS), lg, st, a, which, nw, i);
+          E2CHK(hipGetLastError());
+          hipLaunchKernelGGL(k_e2_update, dim3(m * (m + 1) / 2), dim3(EIG2_THREADS), lg, st, a, which, nw, i);
+          E2CHK(hipGetLastError());
+        }
+      }
+      return hipSuccess;
+    };
+    int it = 0;
+    for (; it < EIG_MAXIT; ++it) {
+      if (!have_factor) {
+        E2CHK(factor(S_HI));
+        const int pd = read_flag(a, which, 2, st, &err);
+        E2CHK(err);
+        if (!pd) {
+          hipLaunchKernelGGL(k_e2_control, dim3(1), dim3(64), lw, st, a, which, nw, 1, 0);
+          E2CHK(hipGetLastError());
+          continue;
+        }
+      }
+      // z = C^-1 y, y = normalised z, Rayleigh quotient
+      hipLaunchKernelGGL(k_e2_copy, dim3(n), dim3(64), 0, st, a, which, nw, 0);
+      for (int j = 0; j < n - 1; ++j)
+        hipLaunchKernelGGL(k_e2_sweep, dim3(n - j - 1), dim3(EIG2_THREADS), lg, st, a, which, nw, j, 0);
+      hipLaunchKernelGGL(k_e2_scale, dim3(n), dim3(EIG2_THREADS), lg, st, a, which, nw);
+      for (int j = n - 1; j >= 1; --j)
+        hipLaunchKernelGGL(k_e2_sweep, dim3(j), dim3(EIG2_THREADS), lg, st, a, which, nw, j, 1);
+      hipLaunchKernelGGL(k_e2_copy, dim3(n), dim3(64), 0, st, a, which, nw, 1);
+      hipLaunchKernelGGL(k_e2_normalise, dim3(1), dim3(64), 0, st, a, which, nw);
+      hipLaunchKernelGGL(k_e2_rq_prod, dim3(n * n), dim3(EIG2_THREADS), lg, st, a, which, nw, 0);
+      hipLaunchKernelGGL(k_e2_rq_rows, dim3(n), dim3(64), lw, st, a, which, nw);
+      hipLaunchKernelGGL(k_e2_rq_prod, dim3(2 * n), dim3(EIG2_THREADS), lg, st, a, which, nw, 1);
+      hipLaunchKernelGGL(k_e2_rq_final, dim3(1), dim3(EIG2_THREADS), lg, st, a, which, nw, it);
+      E2CHK(hipGetLastError());
+      const int bits = read_flag(a, which, 3, st, &err);
+      E2CHK(err);
+      if (bits < 0) {
+        if (nw == NWF) break;
+        *conv = 0;
+        return hipSuccess;
+      }
+      if (bits >= target_bits && nw == NWF) break;
+      long need = 4L * bits + 160;
+      int nwn = (int)((need + 31) / 32);
+      if (nwn < 4) nwn = 4;
+      if (nwn > NWF) nwn = NWF;
+      if (nwn > nw) nw = nwn;
+      hipLaunchKernelGGL(k_e2_trial, dim3(1), dim3(EIG2_THREADS), lg, st, a, which, nw, (int)cexp);
+      E2CHK(hipGetLastError());
+      E2CHK(factor(S_TRY));
+      hipLaunchKernelGGL(k_e2_control, dim3(1), dim3(64), lw, st, a, which, nw, 0, 0);
+      E2CHK(hipGetLastError());
+      const int pd = read_flag(a, which, 2, st, &err);
+      E2CHK(err);
+      if (pd) {
+        have_factor = true;
+        cexp = cexp - 4.0f > 2.0f ? cexp - 4.0f : 2.0f;
+      } else {
+        have_factor = false;
+        cexp += 8.0f;
+      }
+    }
+    hipLaunchKernelGGL(k_e2_control, dim3(1), dim3(64), lw, st, a, which, nw, 3, it);
+    E2CHK(hipGetLastError());
+    if (it >= EIG_MAXIT) {
+      *conv = 0;
+      return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_e2_control, dim3(1), dim3(64), lw, st, a, which, nw, 2, 0);
+    E2CHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_e2_finish, dim3(1), dim3(EIG2_THREADS), lg, st, a, which);
+  return hipGetLastError();
+}
+
+// Host-driven eigen-step of both blocks; ENOCONV goes to the status word.
+hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream) {
+  const EigArgs a = eig_args(blk, dm, eig_ws, st);
+  const size_t lg = eig2_lds_bytes(a.NWM);
+  const void* big[] = {(const void*)k_e2_pivot, (const void*)k_e2_lcol, (const void*)k_e2_update,
+                       (const void*)k_e2_sweep, (const void*)k_e2_scale, (const void*)k_e2_rq_prod,
+                       (const void*)k_e2_rq_final, (const void*)k_e2_trial, (const void*)k_e2_finish};
+  if (lg > 65536)
+    for (const void* f : big) E2CHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg));
+  // a device error from an earlier stage stops here
+  unsigned long long sw = 0;
+  E2CHK(hipMemcpyAsync(&sw, st, 8, hipMemcpyDeviceToHost, stream));
+  E2CHK(hipStreamSynchronize(stream));
+  if (sw) return hipSuccess;
+  for (int which = 0; which < (dm.k >= 2 ? 2 : 1); ++which) {
+    int conv = 1;
+    E2CHK(eig2_block(a, which, stream, &conv));
+    if (!conv) {
+      const unsigned long long v = ((unsigned long long)HL_ENOCONV << 32) | (unsigned)which;
+      E2CHK(hipMemcpyAsync(st, &v, 8, hipMemcpyHostToDevice, stream));
+      E2CHK(hipStreamSynchronize(stream));
+      return hipSuccess;
+    }
+  }
+  hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (a.NWM + 8) * 4, stream, a);
+  return hipGetLastError();
+}
 
 size_t eig_ws_bytes(const Dims& dm) {
   const int NWM = dm.nl + 4;
