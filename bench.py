@@ -16,6 +16,7 @@ update as exact int8 MFMA GEMMs.  Prints one JSON line:
                matrix, checked bit-identical against the MFMA form
   adjoint      d lambda_1 / d beta on the same factorisation (hl_lambda_grad)
                and its time
+  batch        the batched workload (64 uneven instances, one hipGraph replay)
 """
 import argparse
 import json
@@ -84,6 +85,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (d lambda_1 / d beta)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance workload")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--progress", action="store_true",
                     help="factor in pieces of 128 columns, printing a line after each (profiler runs)")
@@ -219,6 +221,30 @@ def main():
         tg2 = (time.perf_counter() - t0) * 1e3
         out["adjoint"] = {"dlambda1_dbeta": g["dlambda1"], "ms": tg2, "device_ms": tg,
                           "time_to_dlambda1_dbeta_s": dt + tg2 * 1e-3}
+
+    # the batched workload: 64 instances in one captured graph
+    if not a.no_batch:
+        from hankel_inputs import batch_configs
+        from paper_1810_01478_amd.api import Batch
+        cfg = batch_configs()
+        log("batched workload", len(cfg))
+        specs = [(moments(b, 2 * n - 1, p + 64), n, 8, p, 16, "mfma") for (b, n, p) in cfg]
+        bt = Batch(ctx, specs)
+        bt.launch()
+        bt.results()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.launch()
+        rb = bt.results()
+        tb = time.perf_counter() - t0
+        bmacs = sum(schur_limb_macs(n, p // 32) for (b, n, p) in cfg)
+        out["batch"] = {"workload": "64 instances, beta in {1/3,1/2,2/3,1}, N in [32,512], P = condition estimate "
+                                    "+ 512 bits, k = 8 (seed 1810)",
+                        "s": tb, "instances_per_s": len(cfg) / tb, "schur_limb_mac_per_s": bmacs / tb,
+                        "all_ok": all(r["status"] == 0 for r in rb)}
+        bt.close()
+        del bt
+        torch.cuda.empty_cache()
 
     # CPU oracle on a bounded sample, doubling as a parity check of the leading block
     if not a.no_cpu:

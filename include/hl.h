@@ -264,8 +264,8 @@ hl_status hl_batch_results(hl_batch *b, void *stream, hl_lambda_t *out, hl_statu
 hl_status hl_batch_destroy(hl_batch *b);
 
 /* Autotuner: builds and times the batch's first `panels` panel steps under each
- * candidate launch shape (items per SIMD 1, 2, 4, 8; range cap 16, 64; VALU
- * below 0, 2048, 4096 bits) and returns the fastest in *best (its time per
+ * candidate launch shape (items per SIMD 2, 4, 8; range cap 16, 64; VALU
+ * below 0, 4096 bits) and returns the fastest in *best (its time per
  * replay in *best_ms).  Uses the instances' workspaces and `plan` as scratch. */
 hl_status hl_autotune(hl_ctx *ctx, int32_t count, const hl_instance *inst, void *plan, size_t plan_bytes,
                       int32_t panels, hl_tune_t *best, double *best_ms);

@@ -733,15 +733,15 @@ extern "C" hl_status hl_batch_destroy(hl_batch* B) {
 
 // Autotuner: times the first `panels` panel steps of the factorisation under
 // each candidate tuning (each replayed `reps` times after one warm-up) and
-// returns the fastest.  Candidates: items per SIMD in {1, 2, 4, 8} x range cap
-// in {16, 64} x VALU below {0, 2048, 4096} bits.  Results are bit-identical
+// returns the fastest.  Candidates: items per SIMD in {2, 4, 8} x range cap
+// in {16, 64} x VALU below {0, 4096} bits.  Results are bit-identical
 // under every candidate; only the time differs.
 extern "C" hl_status hl_autotune(hl_ctx* ctx, int32_t count, const hl_instance* inst, void* plan, size_t plan_bytes,
                                  int32_t panels, hl_tune_t* best, double* best_ms) {
   if (!best) return fail(HL_EINVAL, "null output");
-  const int ips[] = {1, 2, 4, 8};
+  const int ips[] = {2, 4, 8};
   const int caps[] = {16, 64};
-  const int valu[] = {0, 2048, 4096};
+  const int valu[] = {0, 4096};
   double bt = 1e300;
   hl_tune_t bb{4, kMaxRanges, 0, 0};
   hipStream_t st = nullptr;

@@ -78,7 +78,7 @@ def test_autotuned_batch_gives_the_same_bits():
     batch = Batch(ctx(), [(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, specs)])
     tune, ms = autotune(batch, panels=2)
     say("autotune", tune, "%.2f ms" % ms)
-    assert tune["items_per_simd"] in (1, 2, 4, 8) and ms > 0
+    assert tune["items_per_simd"] in (2, 4, 8) and ms > 0
     tuned = Batch(ctx(), [(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, specs)], tune=tune)
     batch.launch()
     r0 = batch.results()
