@@ -38,8 +38,10 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int MF_T = 16;             // output digits per accumulation block
 constexpr int MF_LPB = MF_T / 4;     // limbs per block (one 16-byte slab of an entry)
-constexpr int MF_WIN = MF_T + 4;     // B window: MF_T slices in use, two steps in flight
-constexpr int MF_ROT = MF_WIN / 2;   // steps per rotation of the window
+constexpr int MF_PF = 4;             // operands are loaded this many steps ahead
+constexpr int MF_WIN = MF_T + 2 * MF_PF;  // B window: MF_T slices in use, the rest in flight
+constexpr int MF_ROT = MF_WIN / 2;   // steps per rotation of the window (a multiple of MF_PF)
+static_assert(MF_ROT % MF_PF == 0, "the A ring must turn a whole number of times per rotation");
 
 // entry (m, n) of the 32 x 32 MFMA result held by lane l, register v
 __device__ __forceinline__ int mf_row(int l, int v) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
@@ -140,26 +142,27 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int t
     const int nsteps = (jhi - jlo) / 2 + 1;
     const int nrot = (nsteps + MF_ROT - 1) / MF_ROT;
     // Window slot (y mod MF_WIN) holds the slice at offset t0 - jlo + y; step s
-    // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -4 - 2s, -3 - 2s
-    // for step s + 2.  A digits are likewise loaded two steps ahead.
+    // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -2 MF_PF - 2s,
+    // -2 MF_PF + 1 - 2s for step s + MF_PF.  A digits are likewise loaded
+    // MF_PF steps ahead into a ring.
     const int8_t* ub = Ub + (long)(t0 - jlo) * sstride;
     v4i w[MF_WIN];
 #pragma unroll
     for (int y = 0; y < MF_T; ++y) w[y] = ld16(ub + y * sstride);
-    w[MF_WIN - 2] = ld16(ub - 2 * sstride);
-    w[MF_WIN - 1] = ld16(ub - 1 * sstride);
+#pragma unroll
+    for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = ld16(ub + y * sstride);
     const int8_t* ap = Ab + (long)jlo * sstride;
-    v4i an[2];
-    an[0] = ld16(ap);
-    an[1] = ld16(ap + 2 * sstride);
-    ap += 4 * sstride;
-    const int8_t* un = ub - 4 * sstride;
+    v4i an[MF_PF];
+#pragma unroll
+    for (int q = 0; q < MF_PF; ++q) an[q] = ld16(ap + 2 * q * sstride);
+    ap += 2 * MF_PF * sstride;
+    const int8_t* un = ub - 2 * MF_PF * sstride;
     for (int rot = 0; rot < nrot; ++rot) {
 #pragma unroll
       for (int st = 0; st < MF_ROT; ++st) {
-        const v4i a = an[st & 1];
-        an[st & 1] = ld16(ap);
-        const int k0 = (MF_WIN * 4 - 4 - 2 * st) % MF_WIN;  // slot of y = -4 - 2 st (even)
+        const v4i a = an[st % MF_PF];
+        an[st % MF_PF] = ld16(ap);
+        const int k0 = (MF_WIN * 4 - 2 * MF_PF - 2 * st) % MF_WIN;  // slot of y = -2 MF_PF - 2 st (even)
         w[k0] = ld16(un);
         w[k0 + 1] = ld16(un + sstride);
 #pragma unroll
