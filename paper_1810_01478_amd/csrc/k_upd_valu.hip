@@ -107,6 +107,116 @@ __global__ __launch_bounds__(64) void k_upd_valu(UpdArgs g) {
   upd_valu_body<Q>(g, blockIdx.x, blockIdx.y);
 }
 
+// Workgroup form for launches with few entries: VW waves per entry, wave w
+// owning the 64-column chunks w, w + VW, ...; the 96-bit column sums meet in
+// LDS and wave 0 resolves them into limbs (as g_mul does).  Same result bits.
+constexpr int VW = 4;
+
+template <int QW>
+__global__ __launch_bounds__(VW * 64) void k_upd_valu_wg(UpdArgs g) {
+  const int r = g.r_lo + blockIdx.x;
+  const int c = g.c_lo + blockIdx.y;
+  if (r >= g.r_hi || c >= g.c_hi) return;
+  if (g.tri && r < c) return;
+  if (has_error(g.st)) return;
+  extern __shared__ u32 sm[];
+  const int nl = g.nl, nw = g.nw;
+  const int Qn = (nw + WAVE - 1) / WAVE;
+  u32* sb = sm;
+  u32* su = sm + nl;
+  u32* cs = sm + 2 * nl;  // 3 words per column, 64 Qn columns
+  const int l = lane_id(), w = wave_id();
+  u32* Ab = entry_base(g, r, c);
+  u64 lo[QW];
+  u32 hi[QW];
+#pragma unroll
+  for (int i = 0; i < QW; ++i) {
+    const int t = WAVE * (w + VW * i) + l;
+    lo[i] = (t < nw) ? (u64)(~Ab[in_tile(r, c, t)]) : 0ull;
+    hi[i] = 0;
+  }
+  for (int il = 0; il < g.npan; ++il) {
+    const u32* bp = g.Bop + (size_t)il * g.ldb + (size_t)r * (g.rsb ? g.rsb : (size_t)nl);
+    const u32* up = g.Uop + (size_t)il * g.ldu + (size_t)c * nl;
+    __syncthreads();
+    for (int p = threadIdx.x; p < nl; p += blockDim.x) {
+      sb[p] = bp[p];
+      su[p] = up[p];
+    }
+    __syncthreads();
+    const u32 sgb = sb[nl - 1] >> 31, sgu = su[nl - 1] >> 31;
+    int lane = l;
+    asm volatile("" : "+v"(lane));
+#pragma unroll
+    for (int i = 0; i < QW; ++i) {
+      const int t = lane + WAVE * (w + VW * i);
+      if (t < 2 * nl - 1) {
+        const int x0 = t - nl + 1 > 0 ? t - nl + 1 : 0;
+        const int x1 = t < nl - 1 ? t : nl - 1;
+        col_sum(sb, su, t, x0, x1, lo[i], hi[i]);
+      }
+      if (t >= nl && t < 2 * nl) {
+        u64 s2 = 0;
+        if (sgb) s2 += (u64)(~su[t - nl]);
+        if (sgu) s2 += (u64)(~sb[t - nl]);
+        if (t == nl) s2 += (u64)(sgb + sgu);
+        const u64 n2 = lo[i] + s2;
+        hi[i] += (n2 < s2) ? 1u : 0u;
+        lo[i] = n2;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < QW; ++i) {
+    const int t = WAVE * (w + VW * i) + l;
+    if (t < WAVE * Qn) {
+      cs[3 * t] = (u32)lo[i];
+      cs[3 * t + 1] = (u32)(lo[i] >> 32);
+      cs[3 * t + 2] = hi[i];
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    u32 carry = 0;
+    for (int ch = 0; ch < Qn; ++ch) {
+      const int p = ch * WAVE + l;
+      u64 v = cs[3 * p];
+      if (p >= 1) v += cs[3 * (p - 1) + 1];
+      if (p >= 2) v += cs[3 * (p - 2) + 2];
+      const u32 limb = w_resolve(v, carry);
+      if (p < nw) Ab[in_tile(r, c, p)] = ~limb;
+    }
+  }
+}
+
+template <int QW>
+static hipError_t launch_wg(const UpdArgs& g, hipStream_t stream) {
+  const int nr = g.r_hi - g.r_lo, nc = g.c_hi - g.c_lo;
+  const int Qn = (g.nw + WAVE - 1) / WAVE;
+  const size_t lds = ((size_t)2 * g.nl + (size_t)3 * WAVE * Qn) * 4;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_upd_valu_wg<QW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_upd_valu_wg<QW>, dim3(nr, nc), dim3(VW * 64), lds, stream, g);
+  return hipGetLastError();
+}
+
+static hipError_t launch_wg_any(const UpdArgs& g, hipStream_t stream) {
+  const int Qn = (g.nw + WAVE - 1) / WAVE;
+  const int QW = (Qn + VW - 1) / VW;
+  if (QW <= 2) return launch_wg<2>(g, stream);
+  if (QW <= 3) return launch_wg<3>(g, stream);
+  if (QW <= 4) return launch_wg<4>(g, stream);
+  if (QW <= 6) return launch_wg<6>(g, stream);
+  if (QW <= 8) return launch_wg<8>(g, stream);
+  if (QW <= 10) return launch_wg<10>(g, stream);
+  if (QW <= 12) return launch_wg<12>(g, stream);
+  if (QW <= 14) return launch_wg<14>(g, stream);
+  return launch_wg<16>(g, stream);
+}
+
 // batch: blockIdx.z is the instance; every record fits Q
 template <int Q>
 __global__ __launch_bounds__(64) void k_upd_valu_b(const UpdArgs* __restrict__ tab) {
@@ -149,7 +259,12 @@ static hipError_t launch_any(const UpdArgs* g, const UpdArgs* tab, int count, in
 
 hipError_t launch_upd_valu(const UpdArgs& g, hipStream_t stream) {
   if (g.npan <= 0) return hipSuccess;
-  return launch_any(&g, nullptr, 1, g.r_hi - g.r_lo, g.c_hi - g.c_lo, g.nw, g.nl, stream);
+  const int nr = g.r_hi - g.r_lo, nc = g.c_hi - g.c_lo;
+  if (nr <= 0 || nc <= 0) return hipSuccess;
+  // few entries of long numbers: one wave per entry would leave most SIMDs idle
+  const int Qn = (g.nw + WAVE - 1) / WAVE;
+  if ((long)nr * nc < 1536 && Qn >= 8) return launch_wg_any(g, stream);
+  return launch_any(&g, nullptr, 1, nr, nc, g.nw, g.nl, stream);
 }
 
 hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int nc_max, int nw_max, int nl_max,
