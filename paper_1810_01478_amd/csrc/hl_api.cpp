@@ -130,11 +130,39 @@ Layout make_layout(const Dims& dm) {
     L.adj_tot = off;
     off += al(ns * 4);
   }
+  {
+    // Toeplitz-form updates: up to 16 factor columns, max(16, k) target columns
+    const size_t cols = dm.k > 16 ? dm.k : 16;
+    L.toep_b_bytes = (size_t)16 * dm.NT * tp_bstride(dm.S);
+    L.toep_b = off;
+    off += al(L.toep_b_bytes);
+    L.toep_u_bytes = (size_t)16 * cols * tp_ustride(dm.S);
+    L.toep_u = off;
+    off += al(L.toep_u_bytes);
+    L.toep_carry_words = (size_t)dm.nt * 32 * cols * tp_ranges(dm.nw);
+    L.toep_carry = off;
+    off += al(L.toep_carry_words * 8);
+  }
   L.total = off;
   return L;
 }
 
 }  // namespace hl
+
+// Toeplitz-form update over the workspace's digit and carry regions
+static ToepArgs toep_args(const UpdArgs& g, const Layout& L, char* base, const Dims& dm) {
+  ToepArgs a{};
+  a.g = g;
+  a.bd = (int8_t*)(base + L.toep_b);
+  a.ud = (int8_t*)(base + L.toep_u);
+  a.carry = (long long*)(base + L.toep_carry);
+  a.bd_bytes = L.toep_b_bytes;
+  a.ud_bytes = L.toep_u_bytes;
+  a.carry_words = L.toep_carry_words;
+  a.S = dm.S;
+  a.NT = dm.NT;
+  return a;
+}
 
 extern "C" hl_status hl_get_sizes(const hl_shape* sh, hl_sizes* out) {
   Dims dm;
@@ -293,7 +321,11 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         g.c_lo = i + 1;
         g.c_hi = i0 + npan;
         g.st = dst;
-        HIPCHK(launch_upd_valu(g, st));
+        if (sh->form == HL_FORM_MFMA8) {
+          HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
+        } else {
+          HIPCHK(launch_upd_valu(g, st));
+        }
       }
     }
     pn.end();

@@ -16,6 +16,9 @@ struct Layout {
   // adjoint: Y and Yc (k x nl each), sum Y^2 (2 nl + 2), z (NT x nl), W' (int64),
   // per-row parts (N x (4 nl + 4)), their column sums (u64) and total (4 nl + 4)
   size_t adj_y, adj_yc, adj_ysq, adj_z, adj_wp, adj_part, adj_col, adj_tot;
+  // Toeplitz-form MFMA updates: b digits, reversed u digits, carries
+  size_t toep_b, toep_u, toep_carry;
+  size_t toep_b_bytes, toep_u_bytes, toep_carry_words;
   int omega_stride;
   int digit_slices;
   int blk_stride;

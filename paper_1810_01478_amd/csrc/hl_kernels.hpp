@@ -157,3 +157,27 @@ hipError_t launch_adj_contract(const u32* dmu, const i64* dexp, const int* dneg,
 namespace hl {
 hipError_t launch_mfma_probe(int* out, hipStream_t stream);
 }  // namespace hl
+
+namespace hl {
+// Exact update A[r][c] -= sum_i b_ri u_ci with int8 MFMA GEMMs in Toeplitz form
+// (narrow targets: few columns, any rank npan <= 16).  A work item is 32 rows x
+// one column x TP_DIGITS output digits.
+constexpr int TP_DIGITS = 512;    // output digits (128 limbs) per work item
+constexpr int TP_PADB = 640;      // zero digits after the S digits of each b row
+constexpr int TP_PADU_LO = 576;   // zero digits before / after the reversed digits of each u
+constexpr int TP_PADU_HI = 1216;
+__host__ __device__ __forceinline__ int tp_bstride(int S) { return S + TP_PADB; }
+__host__ __device__ __forceinline__ int tp_ustride(int S) { return TP_PADU_LO + S + TP_PADU_HI; }
+__host__ __device__ __forceinline__ int tp_ranges(int nw) { return (4 * nw + TP_DIGITS - 1) / TP_DIGITS; }
+struct ToepArgs {
+  UpdArgs g;
+  int8_t* bd;          // [npan][NT][tp_bstride(S)] digits of b_r, rows RB_lo*32 .. up
+  int8_t* ud;          // [npan][ncols][tp_ustride(S)] digits of u_c, reversed
+  long long* carry;    // 32 carries per work item
+  size_t bd_bytes, ud_bytes, carry_words;  // capacities (host checks)
+  int S, NT;
+  // derived by the launcher
+  int RB_lo, nrb, ncols, nrg;
+};
+hipError_t launch_upd_toep(const ToepArgs& a, hipStream_t stream);
+}  // namespace hl

@@ -1,0 +1,358 @@
+// Exact update A[r][c] <- A[r][c] - sum_{i in panel} b_ri u_ci as int8 MFMA
+// GEMMs in Toeplitz form, for targets with few columns: the updates inside a
+// panel of the LDL^T (rank 1), the triangular solve with k right-hand sides and
+// the adjoint's back substitution (Algorithm 1 and the solves of Section 3).
+//
+// Digits.  As in the slice form, each P-bit two's complement factor is recoded
+// into S = P/8 balanced base-256 digits, and entry (r, c) receives
+//   sum_t 256^t out_t(r, c),  out_t(r, c) = sum_i sum_j beta_{r,i,j} upsilon_{c,i,t-j}.
+// The slice form takes K over the 16 panel columns, which wastes most of each
+// MFMA when the panel has one column or the target has fewer than 32.  Here, for
+// one column c and factor column i, 32 rows x 32 consecutive output digits
+// t0..t0+31 x 32 consecutive digits j0..j0+31 is one GEMM
+//   out[t][r] += sum_j U[t][j] B[j][r],  U[t][j] = upsilon_{c,i,t-j} (Toeplitz),
+// B[j][r] = beta_{r,i,j}.  v_mfma_i32_32x32x32_i8 takes the Toeplitz operand as
+// its first (M = output digits) and the b digits as its second (N = rows); the
+// output digit of MFMA row m is chosen so that each lane ends up holding 16
+// consecutive digits (4 limbs) of one entry.
+//
+// Kernel.  One wave owns 32 rows x one column x TP_DIGITS = 512 output digits
+// (16 accumulators of 32 digits).  Step s multiplies digits j0 = jb + 32 s: the
+// accumulator of output block q needs the Toeplitz window for t0 + 32 q - j0,
+// which is the window accumulator q - 1 used at step s - 1, so a ring of 16
+// windows turns by one per step: each step loads one window (two aligned
+// 16-byte chunks, shifted into place with v_alignbyte by the lane's offset) and
+// one 16-byte run of b digits, and issues 16 MFMAs.  The u digits are stored
+// reversed so that a window is a forward run of bytes.  Digits outside [0, S)
+// are zero padding.
+//
+// Recombination.  Each lane folds its 16 digit sums of a 4-limb chunk into
+// A - sum_t 256^t out_t (exact, 128 bits plus a small carry); the carries then
+// run through the 32 chunks of the item in order, alternating between the two
+// lane halves.  The carry out of the item's limb range is stored and added by
+// k_toep_carry, so the ranges of one entry run in parallel.
+#include "hl_kernels.hpp"
+
+namespace hl {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int TP_Q = TP_DIGITS / 32;  // accumulators (output blocks of 32 digits)
+constexpr int TP_PF = 4;              // operands are loaded this many steps ahead
+constexpr int TP_ROT = TP_Q;          // steps per unrolled rotation of the window ring
+static_assert(TP_Q == 16, "the lane layout below assumes 16 blocks of 32 digits");
+static_assert(TP_ROT % TP_PF == 0, "the load rings must turn a whole number of times per rotation");
+// padding: with n_s steps rounded up to whole rotations, windows are loaded for
+// d in [-(TP_Q-1), n_s + TP_ROT - 1 + TP_PF] and b runs for steps up to
+// n_s + TP_ROT - 2 + TP_PF (see toep_item)
+static_assert(TP_PADB >= 32 * (TP_ROT - 2 + TP_PF) + 64, "b padding");
+static_assert(TP_PADU_LO >= 32 * TP_Q + 32, "u padding below");
+static_assert(TP_PADU_HI >= TP_DIGITS + 32 * (TP_ROT + TP_PF) + 48, "u padding above");
+
+__device__ __forceinline__ v4i tp_ld16(const int8_t* p) { return *(const v4i*)p; }
+
+// 16 bytes at byte offset 4 aw + ab of the 32 bytes (lo, hi): two rounds of
+// selects by the bits of aw, then byte funnel shifts
+__device__ __forceinline__ v4i tp_window(v4i lo, v4i hi, int aw, int ab) {
+  const bool s2 = (aw & 2) != 0, s1 = (aw & 1) != 0;
+  const u32 f0 = s2 ? (u32)lo.z : (u32)lo.x, f1 = s2 ? (u32)lo.w : (u32)lo.y;
+  const u32 f2 = s2 ? (u32)hi.x : (u32)lo.z, f3 = s2 ? (u32)hi.y : (u32)lo.w;
+  const u32 f4 = s2 ? (u32)hi.z : (u32)hi.x, f5 = s2 ? (u32)hi.w : (u32)hi.y;
+  const u32 e0 = s1 ? f1 : f0, e1 = s1 ? f2 : f1, e2 = s1 ? f3 : f2, e3 = s1 ? f4 : f3, e4 = s1 ? f5 : f4;
+  v4i o;
+  o.x = (int)__builtin_amdgcn_alignbyte(e1, e0, (u32)ab);
+  o.y = (int)__builtin_amdgcn_alignbyte(e2, e1, (u32)ab);
+  o.z = (int)__builtin_amdgcn_alignbyte(e3, e2, (u32)ab);
+  o.w = (int)__builtin_amdgcn_alignbyte(e4, e3, (u32)ab);
+  return o;
+}
+
+// Output digit (within a block of 32) of row m of the MFMA result: chosen so
+// that lane l, register v of the result holds digit 16 (l >> 5) + v.
+__device__ __forceinline__ int tp_digit_of_row(int m) { return 16 * ((m >> 2) & 1) + 4 * (m >> 3) + (m & 3); }
+
+// One work item: rows 32 RB .. 32 RB + 31, column c_lo + cc, output digits
+// [512 rg, 512 rg + 512); the carry out of the range goes to cb[0..31].
+__device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int cc, long long* cb) {
+  const UpdArgs& g = a.g;
+  if (has_error(g.st)) return;
+  const int l = lane_id(), h = l >> 5, n = l & 31;
+  const int S = a.S;
+  const int BS = tp_bstride(S), US = tp_ustride(S);
+  const int t0 = TP_DIGITS * rg;
+  v16i acc[TP_Q];
+#pragma unroll
+  for (int q = 0; q < TP_Q; ++q) acc[q] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int jlo = t0 - (S - 1);
+  if (jlo < 0) jlo = 0;
+  int jhi = t0 + TP_DIGITS - 1;
+  if (jhi > S - 1) jhi = S - 1;
+  if (jlo <= jhi) {
+    const int jb = jlo & ~31;
+    const int n_s = (jhi - jb) / 32 + 1;
+    const int nrot = (n_s + TP_ROT - 1) / TP_ROT;
+    // Window d (accumulator q at step s uses d = s - q) of this lane (A row m = n,
+    // K half h) holds upsilon_{T - x}, x = 0..15, T = t0 + t(m) - jb - 16 h - 32 d,
+    // i.e. reversed digits S-1-T .. S-1-T+15: byte offset wb + 32 d of the padded row.
+    const int wb = TP_PADU_LO + S - 1 - t0 - tp_digit_of_row(n) + 16 * h + jb;
+    const int aoff = wb & 15, aw = aoff >> 2, ab = aoff & 3;
+    for (int p = 0; p < g.npan; ++p) {
+      const int8_t* ur = a.ud + ((size_t)p * a.ncols + cc) * US + (wb & ~15);
+      const int8_t* br = a.bd + ((size_t)p * a.NT + (size_t)RB * 32 + n) * BS + jb + 16 * h;
+      // ring: slot d mod 16 holds window d; step s first multiplies accumulator
+      // 15 (window s - 15), then shifts window s + 1 into that slot, so each
+      // window is ready a step before its first use
+      v4i win[TP_Q];
+#pragma unroll
+      for (int d = -(TP_Q - 1); d <= 0; ++d)
+        win[(d + TP_Q) % TP_Q] = tp_window(tp_ld16(ur + 32 * d), tp_ld16(ur + 32 * d + 16), aw, ab);
+      v4i rlo[TP_PF], rhi[TP_PF], bq[TP_PF];
+#pragma unroll
+      for (int d = 1; d <= TP_PF; ++d) {
+        rlo[d % TP_PF] = tp_ld16(ur + 32 * d);
+        rhi[d % TP_PF] = tp_ld16(ur + 32 * d + 16);
+      }
+#pragma unroll
+      for (int s = 0; s < TP_PF; ++s) bq[s] = tp_ld16(br + 32 * s);
+      const int8_t* un = ur + 32 * (TP_PF + 1);  // raw window s + 1 + TP_PF, loaded at step s
+      const int8_t* bn = br + 32 * TP_PF;        // b digits of step s + TP_PF, loaded at step s
+      for (int rot = 0; rot < nrot; ++rot) {
+        const int s_end = n_s - rot * TP_ROT;  // steps of this rotation that multiply
+#pragma unroll
+        for (int st = 0; st < TP_ROT; ++st) {
+          const v4i bv = bq[st % TP_PF];
+          const bool run = st < s_end;
+          if (run)
+            acc[TP_Q - 1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[(st + 1) % TP_Q], bv, acc[TP_Q - 1], 0, 0, 0);
+          win[(st + 1) % TP_Q] = tp_window(rlo[(st + 1) % TP_PF], rhi[(st + 1) % TP_PF], aw, ab);
+          rlo[(st + 1) % TP_PF] = tp_ld16(un);
+          rhi[(st + 1) % TP_PF] = tp_ld16(un + 16);
+          bq[st % TP_PF] = tp_ld16(bn);
+          un += 32;
+          bn += 32;
+          if (run) {
+#pragma unroll
+            for (int q = TP_Q - 2; q >= 0; --q)
+              acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[(st - q + TP_Q) % TP_Q], bv, acc[q], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // entry (r, c) of this lane; lane half h holds chunks (q, h): limbs t0/4 + 8q + 4h .. + 3
+  const int r = RB * 32 + n, c = g.c_lo + cc;
+  const bool live = r >= g.r_lo && r < g.r_hi && c < g.c_hi && (!g.tri || r >= c);
+  const size_t tix = g.tri ? tri_tile_index(r >> 5, c >> 5) : (size_t)(r >> 5) * g.ntc + (c >> 5);
+  u32* At = g.A + (live ? tix * tile_words(g.nw) : 0);
+  const int L0 = t0 / 4 + 4 * h;
+  uint4 x[TP_Q];
+#pragma unroll
+  for (int q = 0; q < TP_Q; ++q) {
+    const int Lq = L0 + 8 * q;
+    x[q] = (live && Lq < g.nw) ? *(const uint4*)(At + in_tile(r, c, Lq)) : make_uint4(0, 0, 0, 0);
+  }
+  // x - sum_v 256^v out_v per chunk: 128 bits in x, the rest in zc
+  i64 zc[TP_Q];
+#pragma unroll
+  for (int q = 0; q < TP_Q; ++q) {
+    i64 dd[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 16; ++v) dd[v >> 2] += (i64)acc[q][v] << (8 * (v & 3));
+    const __int128 X = (__int128)(((u64)x[q].y << 32) | x[q].x) - (__int128)dd[0] - ((__int128)dd[1] << 32);
+    const __int128 Y = (__int128)(((u64)x[q].w << 32) | x[q].z) - (__int128)dd[2] - ((__int128)dd[3] << 32) +
+                       (__int128)(i64)(X >> 64);
+    const u64 lo = (u64)X, hi = (u64)Y;
+    x[q] = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
+    zc[q] = (i64)(Y >> 64);
+  }
+  // carries through the chunks in limb order: (0,0), (0,1), (1,0), ...
+  i64 carry = 0;
+#pragma unroll
+  for (int k = 0; k < 2 * TP_Q; ++k) {
+    const int q = k >> 1, half = k & 1;
+    i64 cout = 0;
+    if (h == half) {
+      const unsigned __int128 U = ((unsigned __int128)(((u64)x[q].w << 32) | x[q].z) << 64) |
+                                  (((u64)x[q].y << 32) | x[q].x);
+      const unsigned __int128 V = U + (unsigned __int128)(__int128)carry;
+      const int delta = carry >= 0 ? (V < U ? 1 : 0) : (V > U ? -1 : 0);
+      const u64 lo = (u64)V, hi = (u64)(V >> 64);
+      x[q] = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
+      cout = zc[q] + delta;
+    }
+    carry = __shfl(cout, half * 32 + n, WAVE);
+  }
+#pragma unroll
+  for (int q = 0; q < TP_Q; ++q) {
+    const int Lq = L0 + 8 * q;
+    if (live && Lq < g.nw) *(uint4*)(At + in_tile(r, c, Lq)) = x[q];
+  }
+  if (h == 0) cb[n] = live ? carry : 0;
+}
+
+// Work items (range rg, row block, column) in range-major order; the workgroups
+// of a launch are dealt to the 8 XCDs in turn, so block b takes item
+// (b % 8) * per_xcd + b / 8 and the waves of one XCD share a limb range.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_upd_toep(ToepArgs a, int per_xcd) {
+  const int b = blockIdx.x;
+  const int item = (b & 7) * per_xcd + (b >> 3);
+  const int per_rg = a.nrb * a.ncols;
+  if (item >= a.nrg * per_rg) return;
+  const int rg = item / per_rg, rem = item - rg * per_rg;
+  const int rb = rem / a.ncols, cc = rem - rb * a.ncols;
+  toep_item(a, rg, a.RB_lo + rb, cc, a.carry + (size_t)item * 32);
+}
+
+// Add the carry of range w at limb 128 (w + 1) of every entry, w = 0 .. nrg-2
+// (one thread per entry of the target).
+__global__ void k_toep_carry(ToepArgs a) {
+  const UpdArgs& g = a.g;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nrb * 32 * a.ncols) return;
+  if (has_error(g.st)) return;
+  const int rr = e / a.ncols, cc = e - rr * a.ncols;
+  const int rb = rr >> 5, n = rr & 31;
+  const int r = (a.RB_lo + rb) * 32 + n, c = g.c_lo + cc;
+  if (!(r >= g.r_lo && r < g.r_hi && c < g.c_hi && (!g.tri || r >= c))) return;
+  const size_t tix = g.tri ? tri_tile_index(r >> 5, c >> 5) : (size_t)(r >> 5) * g.ntc + (c >> 5);
+  u32* At = g.A + tix * tile_words(g.nw);
+  const int nw = g.nw;
+  const size_t per_rg = (size_t)a.nrb * a.ncols;
+  for (int w = 0; w + 1 < a.nrg; ++w) {
+    const i64 cv = a.carry[((size_t)w * per_rg + (size_t)rb * a.ncols + cc) * 32 + n];
+    if (cv == 0) continue;
+    int li = (TP_DIGITS / 4) * (w + 1);
+    if (li >= nw) continue;
+    u32* p0 = At + in_tile(r, c, li);
+    const u64 x0 = ((u64)p0[1] << 32) | p0[0];
+    const u64 s2 = x0 + (u64)cv;
+    const u64 cy = s2 < x0 ? 1 : 0;
+    p0[0] = (u32)s2;
+    p0[1] = (u32)(s2 >> 32);
+    const u64 add = (cv < 0 ? ~0ull : 0ull) + cy;  // 0 (done), 1 (carry) or ~0 (borrow)
+    if (add == 0) continue;
+    for (li += 2; li < nw; li += 2) {
+      u32* p = At + in_tile(r, c, li);
+      const u64 xv = ((u64)p[1] << 32) | p[0];
+      const u64 y = xv + add;
+      p[0] = (u32)y;
+      p[1] = (u32)(y >> 32);
+      if (add == 1 ? (y != 0) : (xv != 0)) break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Balanced digits 4q .. 4q+3 of the nl-limb two's complement x, packed in a
+// word (digit 4q in the low byte).  Digit j is byte_j + c_j - 256 c_{j+1} with
+// c_{j+1} = [byte_j + c_j >= 128], except the top digit, which keeps the sign.
+// The carry into digit 4q is found by looking down past bytes 0x7f.
+__device__ __forceinline__ u32 tp_digits4(const u32* __restrict__ x, int nl, int q) {
+  int cin = 0;
+  for (int j = 4 * q - 1; j >= 0; --j) {
+    const u32 byte = (x[j >> 2] >> (8 * (j & 3))) & 0xffu;
+    if (byte != 0x7fu) {
+      cin = byte >= 0x80u ? 1 : 0;
+      break;
+    }
+  }
+  const u32 limb = x[q];
+  const int top = 4 * nl - 1;
+  u32 out = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = 4 * q + b;
+    int v;
+    if (j == top) {
+      v = (int)(int8_t)(limb >> 24) + cin;
+      cin = 0;
+    } else {
+      v = (int)((limb >> (8 * b)) & 0xffu) + cin;
+      cin = v >= 128 ? 1 : 0;
+      if (cin) v -= 256;
+    }
+    out |= (u32)(v & 0xff) << (8 * b);
+  }
+  return out;
+}
+
+// b digits, forward: bd[p][row][j], rows 32 RB_lo .. 32 (RB_lo + nrb) - 1
+// (rows outside [r_lo, r_hi) read as zero), zero for j >= S.
+__global__ void k_toep_recode_b(ToepArgs a) {
+  const UpdArgs& g = a.g;
+  const int BS4 = tp_bstride(a.S) / 4;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t rows = (size_t)a.nrb * 32;
+  if (gid >= (size_t)g.npan * rows * BS4) return;
+  const int w = (int)(gid % BS4);
+  const size_t pr = gid / BS4;
+  const int p = (int)(pr / rows);
+  const int row = a.RB_lo * 32 + (int)(pr % rows);
+  u32 v = 0;
+  if (4 * w < a.S && row >= g.r_lo && row < g.r_hi) {
+    const size_t rsb = g.rsb ? g.rsb : (size_t)g.nl;
+    v = tp_digits4(g.Bop + (size_t)p * g.ldb + (size_t)row * rsb, g.nl, w);
+  }
+  u32* dst = (u32*)(a.bd + ((size_t)p * a.NT + row) * tp_bstride(a.S));
+  dst[w] = v;
+}
+
+// u digits, reversed: ud[p][cc][TP_PADU_LO + y] = digit S-1-y of u_(c_lo+cc), zero padded
+__global__ void k_toep_recode_u(ToepArgs a) {
+  const UpdArgs& g = a.g;
+  const int US4 = tp_ustride(a.S) / 4;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)g.npan * a.ncols * US4) return;
+  const int w = (int)(gid % US4);
+  const size_t pc = gid / US4;
+  const int p = (int)(pc / a.ncols), cc = (int)(pc % a.ncols);
+  const int y = 4 * w - TP_PADU_LO;
+  u32 v = 0;
+  if (y >= 0 && y < a.S) {
+    // bytes y .. y+3 are digits S-1-y .. S-4-y: limb nl-1-y/4, reversed
+    const int c = g.c_lo + cc;
+    v = __builtin_bswap32(tp_digits4(g.Uop + (size_t)p * g.ldu + (size_t)c * g.nl, g.nl, g.nl - 1 - y / 4));
+  }
+  u32* dst = (u32*)(a.ud + ((size_t)p * a.ncols + cc) * tp_ustride(a.S));
+  dst[w] = v;
+}
+
+hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
+  const UpdArgs& g = a0.g;
+  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  if (g.npan > 16 || a0.S != 4 * g.nl || g.nw != 2 * g.nl || (a0.S & 15)) return hipErrorInvalidValue;
+  ToepArgs a = a0;
+  a.RB_lo = g.r_lo / 32;
+  a.nrb = (g.r_hi - 1) / 32 + 1 - a.RB_lo;
+  a.ncols = g.c_hi - g.c_lo;
+  a.nrg = tp_ranges(g.nw);
+  if ((a.RB_lo + a.nrb) * 32 > a.NT) return hipErrorInvalidValue;
+  const size_t rows = (size_t)a.nrb * 32;
+  const size_t bneed = ((size_t)(g.npan - 1) * a.NT + (size_t)(a.RB_lo + a.nrb) * 32) * tp_bstride(a.S);
+  const size_t uneed = (size_t)g.npan * a.ncols * tp_ustride(a.S);
+  const long items = (long)a.nrg * a.nrb * a.ncols;
+  if (bneed > a.bd_bytes || uneed > a.ud_bytes || (size_t)items * 32 > a.carry_words) return hipErrorInvalidValue;
+  {
+    const size_t n = (size_t)g.npan * rows * (tp_bstride(a.S) / 4);
+    hipLaunchKernelGGL(k_toep_recode_b, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const size_t n = (size_t)g.npan * a.ncols * (tp_ustride(a.S) / 4);
+    hipLaunchKernelGGL(k_toep_recode_u, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int per_xcd = (int)((items + 7) / 8);
+  hipLaunchKernelGGL(k_upd_toep, dim3(8 * per_xcd), dim3(64), 0, stream, a, per_xcd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.nrg < 2) return e;
+  const size_t ne = rows * a.ncols;
+  hipLaunchKernelGGL(k_toep_carry, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace hl

@@ -113,6 +113,7 @@ def test_mfma_output_layout():
     (Fraction(1, 2), 80, 1024, 7),
     (Fraction(1, 3), 45, 1536, 1),
     (Fraction(1, 2), 100, 4096, 16),
+    (Fraction(1, 2), 70, 2176, 16),   # 2S = 544 digits: a second, partial limb range
 ])
 def test_factor_mfma_bit_exact_vs_oracle(beta, N, P, E):
     say("factor mfma", beta, N, P, E)
