@@ -425,11 +425,6 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
   Stamp ts(ctx, st, 2);
   HIPCHK(launch_fill(ACC, (size_t)dm.nt * tile_words(dm.nw), 0u, st));
   HIPCHK(launch_fill(x, (size_t)dm.NT * dm.k * dm.nl, 0u, st));  // rows N .. NT-1 stay zero
-  if (sh->form == HL_FORM_MFMA8) {
-    // digit slices outside [0, S) must read as zero whatever ran before
-    HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
-    HIPCHK(launch_fill((u32*)(base + L.udig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
-  }
   for (int R0 = 0; R0 < dm.N; R0 += 16) {
     const int nb = dm.N - R0 < 16 ? dm.N - R0 : 16;
     for (int j = 0; j < nb; ++j) {
@@ -452,7 +447,11 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
         g.c_lo = 0;
         g.c_hi = dm.k;
         g.st = dst;
-        HIPCHK(launch_upd_valu(g, st));
+        if (sh->form == HL_FORM_MFMA8) {
+          HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
+        } else {
+          HIPCHK(launch_upd_valu(g, st));
+        }
       }
     }
     if (R0 + nb < dm.N) {
@@ -473,20 +472,8 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
       g.c_hi = dm.k;
       g.st = dst;
       if (sh->form == HL_FORM_MFMA8) {
-        MfmaArgs m{};
-        m.g = g;
-        m.bdig = (int8_t*)(base + L.bdig);
-        m.udig = (int8_t*)(base + L.udig);
-        m.slices = L.digit_slices;
-        m.pad = kDigitPad;
-        m.S = dm.S;
-        m.NT = dm.NT;
-        m.carry = (long long*)(base + L.carry);
-        m.max_ranges = kMaxRanges;
-        m.carry_tiles = L.carry_tiles;
-        m.timing = nullptr;
-        m.u_rows = dm.k;
-        HIPCHK(launch_upd_mfma(m, st));
+        // k <= 32 target columns: the Toeplitz form keeps every MFMA column busy
+        HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
       } else {
         HIPCHK(launch_upd_valu(g, st));
       }
@@ -702,7 +689,11 @@ extern "C" hl_status hl_lambda_grad(hl_ctx* ctx, const hl_shape* sh, const hl_fa
         g.c_lo = 0;
         g.c_hi = 1;
         g.st = dst;
-        HIPCHK(launch_upd_valu(g, st));
+        if (sh->form == HL_FORM_MFMA8) {
+          HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
+        } else {
+          HIPCHK(launch_upd_valu(g, st));
+        }
       }
     }
     if (i0 > 0) {
@@ -724,7 +715,11 @@ extern "C" hl_status hl_lambda_grad(hl_ctx* ctx, const hl_shape* sh, const hl_fa
       g.c_lo = 0;
       g.c_hi = 1;
       g.st = dst;
-      HIPCHK(launch_upd_valu(g, st));
+      if (sh->form == HL_FORM_MFMA8) {
+        HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
+      } else {
+        HIPCHK(launch_upd_valu(g, st));
+      }
     }
   }
   HIPCHK(launch_adj_contract(dmu, dmu_exp, (const int*)dmu_neg, w, dm, f->s, wp, Z, part, col, tot, dst, st));

@@ -32,6 +32,9 @@ def _run(beta, N, k, P, E, form):
     (Fraction(1, 2), 80, 5, 1024, 7, "valu"),
     (Fraction(1), 64, 8, 4096, 16, "valu"),
     (Fraction(1, 3), 40, 6, 1536, 1, "valu"),
+    (Fraction(1, 2), 64, 8, 2048, 16, "mfma"),
+    (Fraction(1, 2), 70, 20, 2176, 16, "mfma"),   # k > 16 columns, a partial second limb range
+    (Fraction(1, 3), 45, 32, 1024, 1, "mfma"),    # k = 32, the widest target
 ])
 def test_block_and_lambda_vs_oracle(beta, N, k, P, E, form):
     say("path", beta, N, k, P, E, form)
