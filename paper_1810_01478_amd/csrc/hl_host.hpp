@@ -6,7 +6,7 @@
 namespace hl {
 
 constexpr int kMaxPrec = 57344;   // pivot kernel keeps ~9 (P/32 + 8) words in LDS
-constexpr int kDigitPad = 48;     // zero digit slices below 0 and above S-1
+constexpr int kDigitPad = 64;     // zero digit slices below 0 and above S-1
 constexpr int kMaxRanges = 64;    // output-limb ranges per tile in the MFMA updates
 constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 

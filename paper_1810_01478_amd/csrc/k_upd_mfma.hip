@@ -38,10 +38,13 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int MF_T = 16;             // output digits per accumulation block
 constexpr int MF_LPB = MF_T / 4;     // limbs per block (one 16-byte slab of an entry)
-constexpr int MF_PF = 4;             // operands are loaded this many steps ahead
+constexpr int MF_PF = 8;             // operands are loaded this many steps ahead
 constexpr int MF_WIN = MF_T + 2 * MF_PF;  // B window: MF_T slices in use, the rest in flight
 constexpr int MF_ROT = MF_WIN / 2;   // steps per rotation of the window (a multiple of MF_PF)
 static_assert(MF_ROT % MF_PF == 0, "the A ring must turn a whole number of times per rotation");
+// zero slices needed at each end of the digit panels: the loads run MF_PF steps
+// (2 MF_PF slices) ahead and the steps are rounded up to whole rotations
+constexpr int MF_PAD_MIN = 2 * (MF_ROT + MF_PF) + 14;
 
 // entry (m, n) of the 32 x 32 MFMA result held by lane l, register v
 __device__ __forceinline__ int mf_row(int l, int v) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
@@ -96,6 +99,16 @@ __global__ void k_recode_b(const RecodeArgs* __restrict__ tab) {
 
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
 
+// 16 bytes at byte offset voff (per lane) + soff (wave-uniform) of a buffer
+__device__ __forceinline__ v4i bld16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
+
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left at their
+// maxima (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kVmcntZero = 0x0F70;
+
 // index of tile (R, C) among the tiles of one launch, for its carry slots
 __device__ __forceinline__ size_t launch_tile_index(const UpdArgs& g, int R, int C, int C_lo) {
   if (g.tri) {
@@ -114,10 +127,15 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int t
   __shared__ i64 carry_s[16 * WAVE];  // carry of each of the lane's 16 entries
   const int l = lane_id(), h = l >> 5, mm = l & 31;
   const int S = m.S, NT = m.NT, pad = m.pad;
-  const long sstride = (long)NT * 16;  // bytes per digit slice
-  // A operand (b digits of tile rows), B operand (u digits of tile columns)
-  const int8_t* Ab = m.bdig + (long)(pad + h) * sstride + (long)(R * 32 + mm) * 16;
-  const int8_t* Ub = m.udig + (long)(pad - h) * sstride + (long)(C * 32 + mm) * 16;
+  const int sst = NT * 16;  // bytes per digit slice
+  // A operand (b digits of tile rows), B operand (u digits of tile columns),
+  // read through buffer descriptors: a 32-bit lane offset plus a wave-uniform
+  // slice offset stepped in scalar registers, so no load in flight holds a
+  // per-lane 64-bit address
+  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(m.bdig, 0, m.slices * sst, kRawBufferWord3);
+  const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(m.udig, 0, m.slices * sst, kRawBufferWord3);
+  const int aoff = h * sst + R * 512 + mm * 16;
+  const int uoff = (1 - h) * sst + C * 512 + mm * 16;
   u32* At = g.A + tix * tile_words(g.nw);
   unsigned live = 0;  // entries of the trailing matrix proper (r >= c, inside the target)
 #pragma unroll
@@ -145,31 +163,35 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int t
     // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -2 MF_PF - 2s,
     // -2 MF_PF + 1 - 2s for step s + MF_PF.  A digits are likewise loaded
     // MF_PF steps ahead into a ring.
-    const int8_t* ub = Ub + (long)(t0 - jlo) * sstride;
+    const int ub = (pad - 1 + t0 - jlo) * sst;
     v4i w[MF_WIN];
 #pragma unroll
-    for (int y = 0; y < MF_T; ++y) w[y] = ld16(ub + y * sstride);
+    for (int y = 0; y < MF_T; ++y) w[y] = bld16(ru, uoff, ub + y * sst);
 #pragma unroll
-    for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = ld16(ub + y * sstride);
-    const int8_t* ap = Ab + (long)jlo * sstride;
+    for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = bld16(ru, uoff, ub + y * sst);
+    int ap = (pad + jlo) * sst;
     v4i an[MF_PF];
 #pragma unroll
-    for (int q = 0; q < MF_PF; ++q) an[q] = ld16(ap + 2 * q * sstride);
-    ap += 2 * MF_PF * sstride;
-    const int8_t* un = ub - 2 * MF_PF * sstride;
+    for (int q = 0; q < MF_PF; ++q) an[q] = bld16(rb, aoff, ap + 2 * q * sst);
+    ap += 2 * MF_PF * sst;
+    int un = ub - 2 * MF_PF * sst;
+    // Let the prologue's loads land here, once per block: the loop header then
+    // only sees the loads in flight from the previous rotation, and its wait
+    // keeps the MF_PF steps of prefetch instead of draining them every rotation.
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);
     for (int rot = 0; rot < nrot; ++rot) {
 #pragma unroll
       for (int st = 0; st < MF_ROT; ++st) {
         const v4i a = an[st % MF_PF];
-        an[st % MF_PF] = ld16(ap);
+        an[st % MF_PF] = bld16(rb, aoff, ap);
         const int k0 = (MF_WIN * 4 - 2 * MF_PF - 2 * st) % MF_WIN;  // slot of y = -2 MF_PF - 2 st (even)
-        w[k0] = ld16(un);
-        w[k0 + 1] = ld16(un + sstride);
+        w[k0] = bld16(ru, uoff, un);
+        w[k0 + 1] = bld16(ru, uoff, un + sst);
 #pragma unroll
         for (int q = 0; q < MF_T; ++q)
           acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, w[(q - 2 * st + MF_WIN * 4) % MF_WIN], acc[q], 0, 0, 0);
-        ap += 2 * sstride;
-        un -= 2 * sstride;
+        ap += 2 * sst;
+        un -= 2 * sst;
         __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, MF_T, 0);
       }
@@ -409,6 +431,8 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   const UpdArgs& g = m.g;
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
   if (g.rsb != 0 && g.rsb != (size_t)g.nl) return hipErrorInvalidValue;  // digit recode reads rows nl apart
+  if (m.pad < MF_PAD_MIN || m.slices != m.S + 2 * m.pad || (size_t)m.slices * m.NT * 16 > 0x7fffffffu)
+    return hipErrorInvalidValue;  // digit panels: padding and 32-bit buffer offsets
   // digits of the panel: b from the multiplier array, u from the panel buffer
   hipError_t e = launch_recode(g.Bop, g.ldb, g.npan, m.NT, m.NT, g.nl, m.pad, m.bdig, stream);
   if (e != hipSuccess) return e;
