@@ -297,6 +297,12 @@ hl_status hl_debug_mul(const uint32_t *a, int32_t na, const uint32_t *b, int32_t
                        int32_t nout, void *stream);
 hl_status hl_debug_recip(const uint32_t *d, int32_t nd, int32_t P, uint32_t *omega, int32_t *h,
                          void *stream);
+/* out[0..nout) = a b mod 2^(32 nout) for non-negative a (na limbs) and b (nb
+ * limbs), all device pointers, by the one-workgroup int8 MFMA product that the
+ * pivot reciprocal uses (threads: 256 or 1024 per workgroup).  HL_EHIP when the
+ * operands and scratch exceed the 160 KiB of LDS. */
+hl_status hl_debug_mul_wg(const uint32_t *a, int32_t na, const uint32_t *b, int32_t nb, uint32_t *out,
+                          int32_t nout, int32_t threads, void *stream);
 /* Output layout of v_mfma_i32_32x32x32_i8: out (device, 2048 int32) holds, per
  * accumulator register v and lane l at out[v*64 + l], 32(m+1) for A rows m+1,
  * B ones, then at out[1024 + v*64 + l] 32(n+1) for A ones, B columns n+1. */

@@ -266,6 +266,14 @@ class Context:
         torch.cuda.synchronize()
         return _ints(O, nout, signed=False)[0]
 
+    def debug_mul_wg(self, a: int, b: int, na: int, nb: int, nout: int, threads: int = 1024) -> int:
+        A = _u32_tensor(pack_limbs([a], na), self.device)
+        B = _u32_tensor(pack_limbs([b], nb), self.device)
+        O = torch.zeros(nout, dtype=torch.int32, device=self.device)
+        L.check(L.lib().hl_debug_mul_wg(_ptr(A), na, _ptr(B), nb, _ptr(O), nout, threads, _stream()))
+        torch.cuda.synchronize()
+        return _ints(O, nout, signed=False)[0]
+
     def debug_mfma_layout(self):
         O = torch.zeros(2048, dtype=torch.int32, device=self.device)
         L.check(L.lib().hl_debug_mfma_layout(_ptr(O), _stream()))

@@ -133,15 +133,33 @@ Layout make_layout(const Dims& dm) {
   {
     // Toeplitz-form updates: up to 16 factor columns, max(16, k) target columns
     const size_t cols = dm.k > 16 ? dm.k : 16;
-    L.toep_b_bytes = (size_t)16 * dm.NT * tp_bstride(dm.S);
+    L.colprod_ld = 2 * dm.nl + 4;
+    L.blk_ny = 2 * dm.nl + 4;
+    L.blk_nm = 3 * dm.nl + 4;
+    // users: trailing-matrix targets (nw limbs, up to NT rows), the column
+    // products (one column of colprod_ld limbs), the block sums (32 rows of b
+    // digits of 2 nl + 1 limbs, k columns of blk_nm limbs)
+    const size_t b1 = (size_t)16 * dm.NT * tp_bstride(dm.S);
+    const size_t b2 = (size_t)16 * 32 * tp_bstride(4 * (2 * dm.nl + 1));
+    L.toep_b_bytes = b1 > b2 ? b1 : b2;
     L.toep_b = off;
     off += al(L.toep_b_bytes);
-    L.toep_u_bytes = (size_t)16 * cols * tp_ustride(dm.S);
+    L.toep_u_bytes = (size_t)16 * cols * tp_ustride(dm.S + 4);
     L.toep_u = off;
     off += al(L.toep_u_bytes);
-    L.toep_carry_words = (size_t)dm.nt * 32 * cols * tp_ranges(dm.nw);
+    size_t items = (size_t)dm.nt * cols * tp_ranges(dm.nw);
+    const size_t i2 = (size_t)dm.nt * tp_ranges(L.colprod_ld), i3 = (size_t)dm.k * tp_ranges(L.blk_nm);
+    if (i2 > items) items = i2;
+    if (i3 > items) items = i3;
+    L.toep_carry_words = items * 32;
     L.toep_carry = off;
     off += al(L.toep_carry_words * 8);
+    L.colprod = off;
+    off += al((size_t)dm.NT * L.colprod_ld * 4);
+    L.blk_y = off;
+    off += al((size_t)dm.k * dm.NT * L.blk_ny * 4);
+    L.blk_m = off;
+    off += al((size_t)dm.k * dm.k * L.blk_nm * 4);
   }
   L.total = off;
   return L;
@@ -303,8 +321,36 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
     for (int il = 0; il < npan; ++il) {
       const int i = i0 + il;
       HIPCHK(launch_pivot(A, dm, i, out->d, out->h, omega, L.omega_stride, dst, st));
-      HIPCHK(launch_col(A, dm, i, i0, out->h, omega, L.omega_stride, up + (size_t)il * ldb,
-                        out->l + (size_t)i * ldb, dst, st));
+      if (sh->form == HL_FORM_MFMA8) {
+        u32* ucol = up + (size_t)il * ldb;
+        u32* P = (u32*)(base + L.colprod);
+        HIPCHK(launch_col_u(A, dm, i, i0, out->h, ucol, dst, st));
+        // P_r = u_r w_i for rows i+1 .. N-1: rank 1 against the single column w_i
+        UpdArgs g{};
+        g.A = P;
+        g.nw = L.colprod_ld;
+        g.nl = dm.nl;
+        g.Bop = ucol;
+        g.Uop = omega + (size_t)i * L.omega_stride;
+        g.npan = 1;
+        g.r_lo = i + 1;
+        g.r_hi = dm.N;
+        g.c_lo = 0;
+        g.c_hi = 1;
+        g.st = dst;
+        ToepArgs ta = toep_args(g, L, base, dm);
+        ta.nlb = dm.nl;
+        ta.nlu = dm.nl + 1;  // w_i <= 2^P
+        ta.plain = 1;
+        ta.ldr = (size_t)L.colprod_ld;
+        ta.ldc = 0;
+        ta.add = 2;
+        HIPCHK(launch_upd_toep(ta, st));
+        HIPCHK(launch_col_fin(dm, i, i0, P, L.colprod_ld, out->l + (size_t)i * ldb, dst, st));
+      } else {
+        HIPCHK(launch_col(A, dm, i, i0, out->h, omega, L.omega_stride, up + (size_t)il * ldb,
+                          out->l + (size_t)i * ldb, dst, st));
+      }
       if (il + 1 < npan) {
         UpdArgs g{};
         g.A = A;
@@ -396,6 +442,14 @@ extern "C" hl_status hl_debug_mul(const uint32_t* a, int32_t na, const uint32_t*
   return HL_OK;
 }
 
+extern "C" hl_status hl_debug_mul_wg(const uint32_t* a, int32_t na, const uint32_t* b, int32_t nb, uint32_t* out,
+                                     int32_t nout, int32_t threads, void* stream) {
+  if (!a || !b || !out || na < 1 || nb < 1 || nout < 1 || (threads != 256 && threads != 1024))
+    return fail(HL_EINVAL, "bad debug_mul_wg args");
+  HIPCHK(launch_debug_mul_wg(a, na, b, nb, out, nout, threads, (hipStream_t)stream));
+  return HL_OK;
+}
+
 extern "C" hl_status hl_debug_recip(const uint32_t* d, int32_t nd, int32_t P, uint32_t* omega, int32_t* h,
                                     void* stream) {
   if (!d || !omega || !h || P % 128 || P < 256 || P > kMaxPrec || nd < 1 || nd > 2 * (P / 32))
@@ -481,8 +535,49 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
   }
   ts.end();
   Stamp tb(ctx, st, 3);
-  HIPCHK(launch_block(x, dm, omega, L.omega_stride, f->s, (u32*)(base + L.blk_part), L.blk_stride, L.blk_chunks,
-                      kBlockRows, (u32*)(base + L.blk_sum), L.blk_stride + 64, blk, blk_exp, dst, st));
+  if (sh->form == HL_FORM_MFMA8) {
+    // M_ab = sum_r (x_rb w_r) x_ra: y by products, the sum over r as Toeplitz
+    // MFMA GEMMs of rank 16 accumulated into M (rows b, columns a <= b)
+    u32* Y = (u32*)(base + L.blk_y);
+    u32* M = (u32*)(base + L.blk_m);
+    HIPCHK(launch_fill(M, (size_t)dm.k * dm.k * L.blk_nm, 0u, st));
+    HIPCHK(launch_block_y(x, dm, omega, L.omega_stride, Y, L.blk_ny, dst, st));
+    for (int r0 = 0; r0 < dm.N; r0 += 16) {
+      UpdArgs g{};
+      g.A = M;
+      g.tri = 1;
+      g.nw = L.blk_nm;
+      g.nl = dm.nl;
+      g.Bop = Y + (size_t)r0 * L.blk_ny;
+      g.ldb = L.blk_ny;
+      g.rsb = (size_t)dm.NT * L.blk_ny;
+      g.Uop = x + (size_t)r0 * ldx;
+      g.ldu = ldx;
+      g.npan = dm.N - r0 < 16 ? dm.N - r0 : 16;
+      g.r_lo = 0;
+      g.r_hi = dm.k;
+      g.c_lo = 0;
+      g.c_hi = dm.k;
+      g.st = dst;
+      ToepArgs ta = toep_args(g, L, base, dm);
+      ta.NT = 32;  // b digit rows: the k <= 32 columns of y
+      ta.nlb = 2 * dm.nl + 1;
+      ta.nlu = dm.nl;
+      ta.ucs = (size_t)dm.nl;
+      ta.plain = 1;
+      ta.ldr = (size_t)dm.k * L.blk_nm;
+      ta.ldc = (size_t)L.blk_nm;
+      ta.add = 1;
+      HIPCHK(launch_upd_toep(ta, st));
+    }
+    u32* part = (u32*)(base + L.blk_part);
+    HIPCHK(launch_block_gather(M, L.blk_nm, dm, part, L.blk_stride, dst, st));
+    HIPCHK(launch_block_sums(dm, f->s, part, L.blk_stride, 1, (u32*)(base + L.blk_sum), L.blk_stride + 64, blk,
+                             blk_exp, dst, st));
+  } else {
+    HIPCHK(launch_block(x, dm, omega, L.omega_stride, f->s, (u32*)(base + L.blk_part), L.blk_stride, L.blk_chunks,
+                        kBlockRows, (u32*)(base + L.blk_sum), L.blk_stride + 64, blk, blk_exp, dst, st));
+  }
   tb.end();
   return HL_OK;
 }

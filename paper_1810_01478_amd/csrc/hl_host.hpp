@@ -19,6 +19,10 @@ struct Layout {
   // Toeplitz-form MFMA updates: b digits, reversed u digits, carries
   size_t toep_b, toep_u, toep_carry;
   size_t toep_b_bytes, toep_u_bytes, toep_carry_words;
+  size_t colprod;      // column products u_r w_i: NT rows of colprod_ld limbs
+  int colprod_ld;
+  size_t blk_y, blk_m;  // MFMA block sums: y_rb = x_rb w_r ([k][NT][blk_ny]), M ([k][k][blk_nm])
+  int blk_ny, blk_nm;
   int omega_stride;
   int digit_slices;
   int blk_stride;

@@ -18,6 +18,11 @@ hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u
 hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
                       int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
 hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream);
+// the column step split around an MFMA product (see k_col_u, k_col_fin)
+hipError_t launch_col_u(const u32* A, const Dims& dm, int i, int r0, const i32* h, u32* u_out, DevStatus* st,
+                        hipStream_t stream);
+hipError_t launch_col_fin(const Dims& dm, int i, int r0, const u32* P, int ldp, u32* l_col, DevStatus* st,
+                          hipStream_t stream);
 
 // Argument records of the per-pivot kernels; a batch launch takes a device array
 // of them, one per instance.
@@ -48,6 +53,8 @@ hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out
                             hipStream_t stream);
 hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_omega, i32* h,
                               hipStream_t stream);
+hipError_t launch_debug_mul_wg(const u32* a, int na, const u32* b, int nb, u32* out, int nout, int threads,
+                               hipStream_t stream);
 
 // exact update A[r][c] -= sum_i b_ri u_ci on the vector ALU; the batch form
 // takes a device array of records (grid nr_max x nc_max x count, each record
@@ -123,6 +130,13 @@ hipError_t launch_trsm_row_batch(const TrsmRowArgs* tab, int count, int k_max, i
 hipError_t launch_block(const u32* X, const Dims& dm, const u32* omega, int ostride, const i32* s,
                         u32* part, int ns, int nchunks, int rows_per_chunk, u32* msum, int nm, u32* blk,
                         i64* blk_exp, DevStatus* st, hipStream_t stream);
+hipError_t launch_block_sums(const Dims& dm, const i32* s, const u32* part, int ns, int nchunks, u32* msum, int nm,
+                             u32* blk, i64* blk_exp, DevStatus* st, hipStream_t stream);
+// MFMA form of the block sums (see k_block_y)
+hipError_t launch_block_y(const u32* X, const Dims& dm, const u32* omega, int ostride, u32* Y, int ny,
+                          DevStatus* st, hipStream_t stream);
+hipError_t launch_block_gather(const u32* M, int nm, const Dims& dm, u32* part, int ns, DevStatus* st,
+                               hipStream_t stream);
 hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
 struct EigArgs {
   const u32* blk;
@@ -170,14 +184,20 @@ __host__ __device__ __forceinline__ int tp_bstride(int S) { return S + TP_PADB; 
 __host__ __device__ __forceinline__ int tp_ustride(int S) { return TP_PADU_LO + S + TP_PADU_HI; }
 __host__ __device__ __forceinline__ int tp_ranges(int nw) { return (4 * nw + TP_DIGITS - 1) / TP_DIGITS; }
 struct ToepArgs {
-  UpdArgs g;
-  int8_t* bd;          // [npan][NT][tp_bstride(S)] digits of b_r, rows RB_lo*32 .. up
-  int8_t* ud;          // [npan][ncols][tp_ustride(S)] digits of u_c, reversed
+  UpdArgs g;           // target, factors, ranges; g.nw = limbs of a target entry
+  int8_t* bd;          // [npan][NT][tp_bstride(Sb)] digits of b_r, rows RB_lo*32 .. up
+  int8_t* ud;          // [npan][ncols][tp_ustride(Su)] digits of u_c, reversed
   long long* carry;    // 32 carries per work item
   size_t bd_bytes, ud_bytes, carry_words;  // capacities (host checks)
-  int S, NT;
+  int S, NT;           // S: digits of an nl-limb factor (4 nl)
+  // optional (0: the trailing-matrix defaults)
+  int nlb, nlu;        // limbs of b_r and of u_c (0: g.nl)
+  size_t ucs;          // u_c at Uop + il*ldu + c*ucs (0: nlu)
+  int plain;           // 1: entry (r, c) at A + r*ldr + c*ldc (limbs), else tile storage
+  size_t ldr, ldc;
+  int add;             // 0: A -= sum b u, 1: A += sum b u, 2: A = sum b u
   // derived by the launcher
-  int RB_lo, nrb, ncols, nrg;
+  int RB_lo, nrb, ncols, nrg, Sb, Su;
 };
 hipError_t launch_upd_toep(const ToepArgs& a, hipStream_t stream);
 }  // namespace hl

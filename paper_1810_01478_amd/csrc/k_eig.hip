@@ -20,6 +20,7 @@
 //     resolved, so only the last steps run at full precision.
 // The iteration stops when the bracket is narrower than 2^-(P+32) relative.
 #include "hl_kernels.hpp"
+#include "mp_mfma.hpp"
 #include "hl_host.hpp"
 
 namespace hl {
@@ -744,7 +745,12 @@ __device__ void wg_fp_mul(const WgCtx& g, FpRef z, const FpRef& x, const FpRef& 
     B[j] = y.m[top + j];
   }
   __syncthreads();
-  g_mul(A, nw, B, nw, g.pr, 2 * nw, g.cb);
+  // the exact product: int8 MFMA once the mantissas are long and its scratch
+  // fits in the column-sum buffer (6 NWM words), else the vector-ALU scan
+  if ((long)nw * nw >= 16384 && wm_scratch_bytes(nw, nw) <= (size_t)6 * c.NWM * 4)
+    wg_mfma_mul(A, nw, B, nw, g.pr, 2 * nw, g.cb);
+  else
+    g_mul(A, nw, B, nw, g.pr, 2 * nw, g.cb);
   // product limbs nw-1 .. 2nw-1, normalised by at most one bit, to the top nw
   const u32* Q = g.pr + (nw - 1);
   const bool low = (Q[nw] >> 31) == 0;

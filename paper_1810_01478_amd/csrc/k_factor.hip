@@ -3,6 +3,7 @@
 // factor columns u (the paper's A_i[j], cut to P bits) and b (the paper's
 // B_i[k] = A_i[k] / A_i[i], scaled by 2^h_i).
 #include "hl_kernels.hpp"
+#include "mp_mfma.hpp"
 
 namespace hl {
 
@@ -122,6 +123,17 @@ __device__ void add_i32(u32* x, int n, int d) {
   }
 }
 
+// Product for the reciprocal's steps (non-negative operands): the one-workgroup
+// MFMA form once the operands are large and its scratch fits in the column-sum
+// buffer (cap bytes), else the product scan on the vector ALU.  Same bits.
+__device__ __forceinline__ void pv_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout, u32* buf,
+                                       size_t cap) {
+  if ((long)na * nb >= 16384 && wm_scratch_bytes(na, nb) <= cap)
+    wg_mfma_mul(a, na, b, nb, out, nout, buf);
+  else
+    g_mul(a, na, b, nb, out, nout, buf);
+}
+
 __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_omega, u32* lds,
                                 int nl) {
   // every thread of the block calls this: the products use all waves, the
@@ -136,7 +148,8 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   u32* Z = dq + NB;
   u32* T = Z + NB;         // 2 NB
   u32* T2 = T + 2 * NB;    // 2 NB
-  u32* colbuf = T2 + 2 * NB;  // 6 NB: column sums of g_mul
+  u32* colbuf = T2 + 2 * NB;  // 6 NB: scratch of the products
+  const size_t cap = (size_t)6 * NB * 4;
   const int Ld = w_bitlen(d, nw);
   const int h = Ld / 2;
   res.h = h;
@@ -167,7 +180,7 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
     __syncthreads();
     // T = dq * Y
     const int nT = nq + ny;
-    g_mul(dq, nq, Y, ny, T, nT, colbuf);
+    pv_mul(dq, nq, Y, ny, T, nT, colbuf, cap);
     // E = 2^(p+q) - T  (two's complement over nT + 1 limbs)
     const int nE = nT + 1;
     if (w0) sub_from_pow2(p + q, T, nT, T, nE);
@@ -184,7 +197,7 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
       break;
     }
     const int nT2 = ny + ne;
-    g_mul(Y, ny, T, ne, T2, nT2, colbuf);
+    pv_mul(Y, ny, T, ne, T2, nT2, colbuf, cap);
     const int nyn = (int)((pn + 2) / 32) + 2;
     // Yn = Y << (pn - p);   Z = T2 >> (2p + q - pn)
     if (w0) {
@@ -210,7 +223,7 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   __syncthreads();
   // R = 2^e - Z D, exact, over nR limbs
   const int nR = (int)(e / 32) + 3;
-  g_mul(Z, nz, D, nd, T, nR, colbuf);
+  pv_mul(Z, nz, D, nd, T, nR, colbuf, cap);
   if (w0) {
     sub_from_pow2(e, T, nR, T, nR);
     // T2 = D zero-extended to nR (and zero up to NB for the comparison below)
@@ -385,6 +398,77 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_b(const ColArgs* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// The same column in three launches, for the MFMA form: k_col_u forms the
+// signed u_r, the product P_r = u_r w_i runs as an int8 MFMA GEMM (Toeplitz
+// form, all rows against the one w_i), and k_col_fin rounds
+// b_r = sign(P_r) ((|P_r| + 2^(P-1)) >> P).  Same bits as k_col.  One wave per row.
+__global__ __launch_bounds__(64) void k_col_u(ColArgs a) {
+  const Dims dm = a.dm;
+  const int i = a.i, r = a.r0 + blockIdx.x;
+  DevStatus* st = a.st;
+  if (has_error(st) || r >= dm.NT) return;
+  const int nl = dm.nl, nw = dm.nw;
+  u32* uo = a.u_out + (size_t)r * nl;
+  if (r <= i || r >= dm.N) {
+    for (int l = lane_id(); l < nl; l += WAVE) uo[l] = 0;
+    return;
+  }
+  extern __shared__ u32 lds[];
+  u32* As = lds;            // nw
+  u32* Us = As + nw;        // nl + 1
+  const u32* src = a.A + tri_tile_index(r >> 5, i >> 5) * tile_words(nw);
+  for (int l = lane_id(); l < nw; l += WAVE) As[l] = src[in_tile(r, i, l)];
+  wsync();
+  const bool neg = (As[nw - 1] >> 31) != 0;
+  if (neg) w_neg(As, nw);
+  wsync();
+  const int h = a.h[i];
+  if (h > 0) w_add_word(As, nw, (h - 1) >> 5, 1u << ((h - 1) & 31));
+  wsync();
+  w_shift_right(As, nw, h, Us, nl + 1);
+  wsync();
+  if (Us[nl] != 0 || Us[nl - 1] >= 0x60000000u) {  // |u| < 3 2^(P-3)
+    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
+    return;
+  }
+  if (neg) w_neg(Us, nl);
+  wsync();
+  for (int l = lane_id(); l < nl; l += WAVE) uo[l] = Us[l];
+}
+
+// P: row r at P + r ldp (ldp >= 2 nl + 1 limbs, two's complement)
+__global__ __launch_bounds__(64) void k_col_fin(ColArgs a, const u32* __restrict__ P, int ldp) {
+  const Dims dm = a.dm;
+  const int i = a.i, r = a.r0 + blockIdx.x;
+  DevStatus* st = a.st;
+  if (has_error(st) || r >= dm.NT) return;
+  const int nl = dm.nl;
+  u32* bo = a.l_col + (size_t)r * nl;
+  if (r <= i || r >= dm.N) {
+    for (int l = lane_id(); l < nl; l += WAVE) bo[l] = 0;
+    return;
+  }
+  extern __shared__ u32 lds[];
+  u32* Ps = lds;  // ldp
+  for (int l = lane_id(); l < ldp; l += WAVE) Ps[l] = P[(size_t)r * ldp + l];
+  wsync();
+  const bool neg = (Ps[ldp - 1] >> 31) != 0;
+  if (neg) w_neg(Ps, ldp);
+  wsync();
+  w_add_word(Ps, ldp, nl - 1, 0x80000000u);
+  wsync();
+  bool over = Ps[2 * nl - 1] >= 0x60000000u;
+  for (int l = 2 * nl; l < ldp; ++l) over = over || Ps[l] != 0;
+  if (over) {
+    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
+    return;
+  }
+  if (neg) w_neg(Ps + nl, nl);
+  wsync();
+  for (int l = lane_id(); l < nl; l += WAVE) bo[l] = Ps[nl + l];
+}
+
+// ---------------------------------------------------------------------------
 __global__ void k_fill_u32(u32* __restrict__ p, size_t n, u32 v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -396,6 +480,21 @@ __global__ void k_fill_u32(u32* __restrict__ p, size_t n, u32 v) {
 __global__ __launch_bounds__(64) void k_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out,
                                                   int nout) {
   w_mul(a, na, b, nb, out, nout);
+}
+
+// the one-workgroup MFMA product, on operands staged in LDS
+__global__ __launch_bounds__(1024) void k_debug_mul_wg(const u32* a, int na, const u32* b, int nb, u32* out,
+                                                     int nout) {
+  extern __shared__ u32 lds[];
+  u32* as = lds;
+  u32* bs = as + ((na + 3) & ~3);
+  u32* os = bs + ((nb + 3) & ~3);
+  u32* sc = os + ((nout + 3) & ~3);
+  for (int i = threadIdx.x; i < na; i += blockDim.x) as[i] = a[i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) bs[i] = b[i];
+  __syncthreads();
+  wg_mfma_mul(as, na, bs, nb, os, nout, sc);
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) out[i] = os[i];
 }
 
 __global__ __launch_bounds__(PIVOT_THREADS) void k_debug_recip(const u32* d, int nd, int P, int nl, u32* omega,
@@ -453,6 +552,31 @@ hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h,
   return hipGetLastError();
 }
 
+hipError_t launch_col_u(const u32* A, const Dims& dm, int i, int r0, const i32* h, u32* u_out, DevStatus* st,
+                        hipStream_t stream) {
+  const int nrows = dm.NT - r0;
+  if (nrows <= 0) return hipSuccess;
+  const ColArgs a{A, dm, i, r0, h, nullptr, 0, u_out, nullptr, st};
+  const size_t lds = (size_t)(dm.nw + dm.nl + 1) * 4;
+  hipError_t e = allow_lds((const void*)k_col_u, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_u, dim3(nrows), dim3(64), lds, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_fin(const Dims& dm, int i, int r0, const u32* P, int ldp, u32* l_col, DevStatus* st,
+                          hipStream_t stream) {
+  const int nrows = dm.NT - r0;
+  if (nrows <= 0) return hipSuccess;
+  if (ldp < 2 * dm.nl + 1) return hipErrorInvalidValue;
+  const ColArgs a{nullptr, dm, i, r0, nullptr, nullptr, 0, nullptr, l_col, st};
+  const size_t lds = (size_t)ldp * 4;
+  hipError_t e = allow_lds((const void*)k_col_fin, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_fin, dim3(nrows), dim3(64), lds, stream, a, P, ldp);
+  return hipGetLastError();
+}
+
 hipError_t launch_pivot_batch(const PivotArgs* tab, int count, int nl_max, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   hipError_t e = allow_lds((const void*)k_pivot_b, pivot_lds_bytes(nl_max));
@@ -480,6 +604,17 @@ hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream) {
 hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout,
                             hipStream_t stream) {
   hipLaunchKernelGGL(k_debug_mul, dim3(1), dim3(64), 0, stream, a, na, b, nb, out, nout);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_mul_wg(const u32* a, int na, const u32* b, int nb, u32* out, int nout, int threads,
+                               hipStream_t stream) {
+  if (threads != 256 && threads != 1024) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(((na + 3) & ~3) + ((nb + 3) & ~3) + ((nout + 3) & ~3)) * 4 + wm_scratch_bytes(na, nb);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = allow_lds((const void*)k_debug_mul_wg, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_debug_mul_wg, dim3(1), dim3(threads), lds, stream, a, na, b, nb, out, nout);
   return hipGetLastError();
 }
 

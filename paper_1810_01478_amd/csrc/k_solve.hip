@@ -218,6 +218,64 @@ __global__ __launch_bounds__(64) void k_block_final(const u32* __restrict__ msum
 }
 
 // ---------------------------------------------------------------------------
+// MFMA form of the block sums: M_ab = sum_r (x_rb w_r) x_ra.  k_block_y forms
+// y_rb = x_rb w_r (one workgroup per (r, b), both factors in LDS); the sum over
+// r is a Toeplitz-form MFMA GEMM of y against x (k rows b, k columns a, rank r),
+// and k_block_gather moves M_ab (a <= b) into the pair layout of k_block_reduce.
+constexpr int BY_THREADS = 256;
+size_t block_y_lds_bytes(int nl) { return (size_t)(nl + (nl + 1) + (2 * nl + 1) + 3 * (2 * nl + 1) + 8) * 4; }
+
+__global__ __launch_bounds__(BY_THREADS) void k_block_y(const u32* __restrict__ X, Dims dm,
+                                                         const u32* __restrict__ omega, int ostride,
+                                                         u32* __restrict__ Y, int ny, DevStatus* st) {
+  if (has_error(st)) return;
+  const int r = blockIdx.x, b = blockIdx.y;
+  const int nl = dm.nl, k = dm.k;
+  u32* yo = Y + ((size_t)b * dm.NT + r) * ny;
+  if (r >= dm.N) {
+    for (int l = threadIdx.x; l < ny; l += blockDim.x) yo[l] = 0;
+    return;
+  }
+  extern __shared__ u32 lds[];
+  u32* xs = lds;                 // nl
+  u32* om = xs + nl;             // nl + 1
+  u32* pr = om + nl + 1;         // 2 nl + 1
+  u32* cb = pr + 2 * nl + 1;     // 3 (2 nl + 1)
+  int* flag = (int*)(cb + 3 * (2 * nl + 1));
+  const u32* px = X + ((size_t)r * k + b) * nl;
+  const u32* po = omega + (size_t)r * ostride;
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) xs[l] = px[l];
+  for (int l = threadIdx.x; l < nl + 1; l += blockDim.x) om[l] = po[l];
+  __syncthreads();
+  if (wave_id() == 0) {
+    const bool neg = (xs[nl - 1] >> 31) != 0;
+    if (neg) w_neg(xs, nl);
+    if (lane_id() == 0) flag[0] = neg ? 1 : 0;
+  }
+  __syncthreads();
+  const bool neg = flag[0] != 0;
+  g_mul(xs, nl, om, nl + 1, pr, 2 * nl + 1, cb);
+  if (wave_id() == 0 && neg) w_neg(pr, 2 * nl + 1);
+  __syncthreads();
+  const u32 ext = neg && !w_is_zero(pr, 2 * nl + 1) ? 0xffffffffu : 0u;
+  for (int l = threadIdx.x; l < ny; l += blockDim.x) yo[l] = l < 2 * nl + 1 ? pr[l] : ext;
+}
+
+// part[p][0] = M_(b, a) (nm limbs, sign-extended to ns), p = b (b + 1) / 2 + a
+__global__ __launch_bounds__(64) void k_block_gather(const u32* __restrict__ M, int nm, Dims dm,
+                                                     u32* __restrict__ part, int ns, DevStatus* st) {
+  if (has_error(st)) return;
+  const int p = blockIdx.x;
+  int b = 0;
+  while ((b + 1) * (b + 2) / 2 <= p) ++b;
+  const int a = p - b * (b + 1) / 2;
+  const u32* m = M + ((size_t)b * dm.k + a) * nm;
+  const u32 ext = (m[nm - 1] >> 31) ? 0xffffffffu : 0u;
+  u32* o = part + (size_t)p * ns;
+  for (int l = lane_id(); l < ns; l += WAVE) o[l] = l < nm ? m[l] : ext;
+}
+
+// ---------------------------------------------------------------------------
 hipError_t launch_trsm_row(const u32* ACC, const Dims& dm, int r, const i32* s, const i32* h, u32* X,
                            DevStatus* st, hipStream_t stream) {
   const size_t lds = (size_t)(dm.nw + 4 + dm.nl + 4) * 4;
@@ -242,6 +300,36 @@ hipError_t launch_block(const u32* X, const Dims& dm, const u32* omega, int ostr
                      rows_per_chunk, part, ns, nchunks, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_block_sums(dm, s, part, ns, nchunks, msum, nm, blk, blk_exp, st, stream);
+}
+
+static hipError_t allow_lds_solve(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_block_y(const u32* X, const Dims& dm, const u32* omega, int ostride, u32* Y, int ny,
+                          DevStatus* st, hipStream_t stream) {
+  if (ny < 2 * dm.nl + 1) return hipErrorInvalidValue;
+  const size_t lds = block_y_lds_bytes(dm.nl);
+  hipError_t e = allow_lds_solve((const void*)k_block_y, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_y, dim3(dm.NT, dm.k), dim3(BY_THREADS), lds, stream, X, dm, omega, ostride, Y, ny, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_gather(const u32* M, int nm, const Dims& dm, u32* part, int ns, DevStatus* st,
+                               hipStream_t stream) {
+  if (ns < nm) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_block_gather, dim3(dm.k * (dm.k + 1) / 2), dim3(64), 0, stream, M, nm, dm, part, ns, st);
+  return hipGetLastError();
+}
+
+// sum of the nchunks partials of each pair, common exponent, rounding
+hipError_t launch_block_sums(const Dims& dm, const i32* s, const u32* part, int ns, int nchunks, u32* msum, int nm,
+                             u32* blk, i64* blk_exp, DevStatus* st, hipStream_t stream) {
+  const int npairs = dm.k * (dm.k + 1) / 2;
+  hipError_t e;
   hipLaunchKernelGGL(k_block_reduce, dim3(npairs), dim3(64), (size_t)nm * 4, stream, part, ns, nchunks, s,
                      dm, msum, nm, st);
   e = hipGetLastError();

@@ -370,8 +370,9 @@ double block_work(int tb, int S) {
 
 // Split the output blocks of every tile into ranges of about equal work.  The
 // number of ranges minimises the launch's time in units of one tile's work,
-// rounds x (1/n + per-item cost), where one round is one wave on each of the
-// 1024 SIMDs (8 XCDs x 128).
+// rounds x (1/n + c), where one round is one wave on each of the 1024 SIMDs
+// (8 XCDs x 128) and c = 0.2% of a tile is the cost of one more work item (its
+// first block's operand fetch and its carry slot).
 RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items) {
   const int ntb = 8 * nl / MF_T;
   int cap = max_ranges < MF_MAX_RANGES ? max_ranges : MF_MAX_RANGES;
@@ -384,7 +385,7 @@ RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items
     if (n > 1 && (size_t)total > max_items) break;
     const long per = (total + 7) / 8;
     const long rounds = (per + 127) / 128;
-    const double cost = (double)rounds * (1.0 / n + 0.01);
+    const double cost = (double)rounds * (1.0 / n + 0.002);
     if (cost < best * 0.999) {
       best = cost;
       want = n;

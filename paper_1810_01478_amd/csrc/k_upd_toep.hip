@@ -72,30 +72,39 @@ __device__ __forceinline__ v4i tp_window(v4i lo, v4i hi, int aw, int ab) {
 // that lane l, register v of the result holds digit 16 (l >> 5) + v.
 __device__ __forceinline__ int tp_digit_of_row(int m) { return 16 * ((m >> 2) & 1) + 4 * (m >> 3) + (m & 3); }
 
+// limb Lq of target entry (r, c)
+__device__ __forceinline__ u32* tp_entry(const ToepArgs& a, int r, int c, int Lq) {
+  const UpdArgs& g = a.g;
+  if (a.plain) return g.A + (size_t)r * a.ldr + (size_t)c * a.ldc + Lq;
+  const size_t tix = g.tri ? tri_tile_index(r >> 5, c >> 5) : (size_t)(r >> 5) * g.ntc + (c >> 5);
+  return g.A + tix * tile_words(g.nw) + in_tile(r, c, Lq);
+}
+
 // One work item: rows 32 RB .. 32 RB + 31, column c_lo + cc, output digits
 // [512 rg, 512 rg + 512); the carry out of the range goes to cb[0..31].
 __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int cc, long long* cb) {
   const UpdArgs& g = a.g;
   if (has_error(g.st)) return;
   const int l = lane_id(), h = l >> 5, n = l & 31;
-  const int S = a.S;
-  const int BS = tp_bstride(S), US = tp_ustride(S);
+  const int Sb = a.Sb, Su = a.Su;
+  const int BS = tp_bstride(Sb), US = tp_ustride(Su);
   const int t0 = TP_DIGITS * rg;
   v16i acc[TP_Q];
 #pragma unroll
   for (int q = 0; q < TP_Q; ++q) acc[q] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  int jlo = t0 - (S - 1);
+  // digit j of b pairs with digit t - j of u: j in [t - (Su-1), t] and [0, Sb)
+  int jlo = t0 - (Su - 1);
   if (jlo < 0) jlo = 0;
   int jhi = t0 + TP_DIGITS - 1;
-  if (jhi > S - 1) jhi = S - 1;
+  if (jhi > Sb - 1) jhi = Sb - 1;
   if (jlo <= jhi) {
     const int jb = jlo & ~31;
     const int n_s = (jhi - jb) / 32 + 1;
     const int nrot = (n_s + TP_ROT - 1) / TP_ROT;
     // Window d (accumulator q at step s uses d = s - q) of this lane (A row m = n,
     // K half h) holds upsilon_{T - x}, x = 0..15, T = t0 + t(m) - jb - 16 h - 32 d,
-    // i.e. reversed digits S-1-T .. S-1-T+15: byte offset wb + 32 d of the padded row.
-    const int wb = TP_PADU_LO + S - 1 - t0 - tp_digit_of_row(n) + 16 * h + jb;
+    // i.e. reversed digits Su-1-T .. Su-1-T+15: byte offset wb + 32 d of the padded row.
+    const int wb = TP_PADU_LO + Su - 1 - t0 - tp_digit_of_row(n) + 16 * h + jb;
     const int aoff = wb & 15, aw = aoff >> 2, ab = aoff & 3;
     for (int p = 0; p < g.npan; ++p) {
       const int8_t* ur = a.ud + ((size_t)p * a.ncols + cc) * US + (wb & ~15);
@@ -143,14 +152,16 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
   // entry (r, c) of this lane; lane half h holds chunks (q, h): limbs t0/4 + 8q + 4h .. + 3
   const int r = RB * 32 + n, c = g.c_lo + cc;
   const bool live = r >= g.r_lo && r < g.r_hi && c < g.c_hi && (!g.tri || r >= c);
-  const size_t tix = g.tri ? tri_tile_index(r >> 5, c >> 5) : (size_t)(r >> 5) * g.ntc + (c >> 5);
-  u32* At = g.A + (live ? tix * tile_words(g.nw) : 0);
   const int L0 = t0 / 4 + 4 * h;
   uint4 x[TP_Q];
 #pragma unroll
   for (int q = 0; q < TP_Q; ++q) {
     const int Lq = L0 + 8 * q;
-    x[q] = (live && Lq < g.nw) ? *(const uint4*)(At + in_tile(r, c, Lq)) : make_uint4(0, 0, 0, 0);
+    x[q] = (live && Lq < g.nw && a.add != 2) ? *(const uint4*)tp_entry(a, r, c, Lq) : make_uint4(0, 0, 0, 0);
+  }
+  if (a.add) {
+#pragma unroll
+    for (int q = 0; q < TP_Q; ++q) acc[q] = -acc[q];
   }
   // x - sum_v 256^v out_v per chunk: 128 bits in x, the rest in zc
   i64 zc[TP_Q];
@@ -186,7 +197,7 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
 #pragma unroll
   for (int q = 0; q < TP_Q; ++q) {
     const int Lq = L0 + 8 * q;
-    if (live && Lq < g.nw) *(uint4*)(At + in_tile(r, c, Lq)) = x[q];
+    if (live && Lq < g.nw) *(uint4*)tp_entry(a, r, c, Lq) = x[q];
   }
   if (h == 0) cb[n] = live ? carry : 0;
 }
@@ -216,8 +227,6 @@ __global__ void k_toep_carry(ToepArgs a) {
   const int rb = rr >> 5, n = rr & 31;
   const int r = (a.RB_lo + rb) * 32 + n, c = g.c_lo + cc;
   if (!(r >= g.r_lo && r < g.r_hi && c < g.c_hi && (!g.tri || r >= c))) return;
-  const size_t tix = g.tri ? tri_tile_index(r >> 5, c >> 5) : (size_t)(r >> 5) * g.ntc + (c >> 5);
-  u32* At = g.A + tix * tile_words(g.nw);
   const int nw = g.nw;
   const size_t per_rg = (size_t)a.nrb * a.ncols;
   for (int w = 0; w + 1 < a.nrg; ++w) {
@@ -225,7 +234,7 @@ __global__ void k_toep_carry(ToepArgs a) {
     if (cv == 0) continue;
     int li = (TP_DIGITS / 4) * (w + 1);
     if (li >= nw) continue;
-    u32* p0 = At + in_tile(r, c, li);
+    u32* p0 = tp_entry(a, r, c, li);
     const u64 x0 = ((u64)p0[1] << 32) | p0[0];
     const u64 s2 = x0 + (u64)cv;
     const u64 cy = s2 < x0 ? 1 : 0;
@@ -234,7 +243,7 @@ __global__ void k_toep_carry(ToepArgs a) {
     const u64 add = (cv < 0 ? ~0ull : 0ull) + cy;  // 0 (done), 1 (carry) or ~0 (borrow)
     if (add == 0) continue;
     for (li += 2; li < nw; li += 2) {
-      u32* p = At + in_tile(r, c, li);
+      u32* p = tp_entry(a, r, c, li);
       const u64 xv = ((u64)p[1] << 32) | p[0];
       const u64 y = xv + add;
       p[0] = (u32)y;
@@ -279,10 +288,10 @@ __device__ __forceinline__ u32 tp_digits4(const u32* __restrict__ x, int nl, int
 }
 
 // b digits, forward: bd[p][row][j], rows 32 RB_lo .. 32 (RB_lo + nrb) - 1
-// (rows outside [r_lo, r_hi) read as zero), zero for j >= S.
+// (rows outside [r_lo, r_hi) read as zero), zero for j >= Sb.
 __global__ void k_toep_recode_b(ToepArgs a) {
   const UpdArgs& g = a.g;
-  const int BS4 = tp_bstride(a.S) / 4;
+  const int BS4 = tp_bstride(a.Sb) / 4;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t rows = (size_t)a.nrb * 32;
   if (gid >= (size_t)g.npan * rows * BS4) return;
@@ -291,18 +300,18 @@ __global__ void k_toep_recode_b(ToepArgs a) {
   const int p = (int)(pr / rows);
   const int row = a.RB_lo * 32 + (int)(pr % rows);
   u32 v = 0;
-  if (4 * w < a.S && row >= g.r_lo && row < g.r_hi) {
-    const size_t rsb = g.rsb ? g.rsb : (size_t)g.nl;
-    v = tp_digits4(g.Bop + (size_t)p * g.ldb + (size_t)row * rsb, g.nl, w);
+  if (4 * w < a.Sb && row >= g.r_lo && row < g.r_hi) {
+    const size_t rsb = g.rsb ? g.rsb : (size_t)a.nlb;
+    v = tp_digits4(g.Bop + (size_t)p * g.ldb + (size_t)row * rsb, a.nlb, w);
   }
-  u32* dst = (u32*)(a.bd + ((size_t)p * a.NT + row) * tp_bstride(a.S));
+  u32* dst = (u32*)(a.bd + ((size_t)p * a.NT + row) * tp_bstride(a.Sb));
   dst[w] = v;
 }
 
-// u digits, reversed: ud[p][cc][TP_PADU_LO + y] = digit S-1-y of u_(c_lo+cc), zero padded
+// u digits, reversed: ud[p][cc][TP_PADU_LO + y] = digit Su-1-y of u_(c_lo+cc), zero padded
 __global__ void k_toep_recode_u(ToepArgs a) {
   const UpdArgs& g = a.g;
-  const int US4 = tp_ustride(a.S) / 4;
+  const int US4 = tp_ustride(a.Su) / 4;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (size_t)g.npan * a.ncols * US4) return;
   const int w = (int)(gid % US4);
@@ -310,38 +319,47 @@ __global__ void k_toep_recode_u(ToepArgs a) {
   const int p = (int)(pc / a.ncols), cc = (int)(pc % a.ncols);
   const int y = 4 * w - TP_PADU_LO;
   u32 v = 0;
-  if (y >= 0 && y < a.S) {
-    // bytes y .. y+3 are digits S-1-y .. S-4-y: limb nl-1-y/4, reversed
+  if (y >= 0 && y < a.Su) {
+    // bytes y .. y+3 are digits Su-1-y .. Su-4-y: limb nlu-1-y/4, reversed
     const int c = g.c_lo + cc;
-    v = __builtin_bswap32(tp_digits4(g.Uop + (size_t)p * g.ldu + (size_t)c * g.nl, g.nl, g.nl - 1 - y / 4));
+    v = __builtin_bswap32(tp_digits4(g.Uop + (size_t)p * g.ldu + (size_t)c * a.ucs, a.nlu, a.nlu - 1 - y / 4));
   }
-  u32* dst = (u32*)(a.ud + ((size_t)p * a.ncols + cc) * tp_ustride(a.S));
+  u32* dst = (u32*)(a.ud + ((size_t)p * a.ncols + cc) * tp_ustride(a.Su));
   dst[w] = v;
 }
 
 hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
   const UpdArgs& g = a0.g;
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
-  if (g.npan > 16 || a0.S != 4 * g.nl || g.nw != 2 * g.nl || (a0.S & 15)) return hipErrorInvalidValue;
   ToepArgs a = a0;
+  if (a.nlb <= 0) a.nlb = g.nl;
+  if (a.nlu <= 0) a.nlu = g.nl;
+  if (a.ucs == 0) a.ucs = (size_t)a.nlu;
+  a.Sb = 4 * a.nlb;
+  a.Su = 4 * a.nlu;
+  // digit sums stay below 2^31: npan x min(Sb, Su) x 2^14
+  const int smin = a.Sb < a.Su ? a.Sb : a.Su;
+  if (g.npan > 16 || (long)g.npan * smin > 131071 || g.nw < 1 || (g.nw & 3)) return hipErrorInvalidValue;
+  if (!a.plain && g.nw != 2 * g.nl) return hipErrorInvalidValue;
+  if (a.plain && ((a.ldr & 3) || (a.ldc & 3) || ((uintptr_t)g.A & 15))) return hipErrorInvalidValue;
   a.RB_lo = g.r_lo / 32;
   a.nrb = (g.r_hi - 1) / 32 + 1 - a.RB_lo;
   a.ncols = g.c_hi - g.c_lo;
   a.nrg = tp_ranges(g.nw);
   if ((a.RB_lo + a.nrb) * 32 > a.NT) return hipErrorInvalidValue;
   const size_t rows = (size_t)a.nrb * 32;
-  const size_t bneed = ((size_t)(g.npan - 1) * a.NT + (size_t)(a.RB_lo + a.nrb) * 32) * tp_bstride(a.S);
-  const size_t uneed = (size_t)g.npan * a.ncols * tp_ustride(a.S);
+  const size_t bneed = ((size_t)(g.npan - 1) * a.NT + (size_t)(a.RB_lo + a.nrb) * 32) * tp_bstride(a.Sb);
+  const size_t uneed = (size_t)g.npan * a.ncols * tp_ustride(a.Su);
   const long items = (long)a.nrg * a.nrb * a.ncols;
   if (bneed > a.bd_bytes || uneed > a.ud_bytes || (size_t)items * 32 > a.carry_words) return hipErrorInvalidValue;
   {
-    const size_t n = (size_t)g.npan * rows * (tp_bstride(a.S) / 4);
+    const size_t n = (size_t)g.npan * rows * (tp_bstride(a.Sb) / 4);
     hipLaunchKernelGGL(k_toep_recode_b, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
-    const size_t n = (size_t)g.npan * a.ncols * (tp_ustride(a.S) / 4);
+    const size_t n = (size_t)g.npan * a.ncols * (tp_ustride(a.Su) / 4);
     hipLaunchKernelGGL(k_toep_recode_u, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -29,6 +29,35 @@ def test_debug_mul_matches_host(na, nb):
         assert got == a * b
 
 
+def _structured(rng, n):
+    """Random, all-ones, a power of two, runs of 0x7f bytes (the balanced-digit
+    carry chains) and 0x80 bytes, for n limbs."""
+    kind = rng.randrange(5)
+    if kind == 0:
+        return rng.getrandbits(32 * n)
+    if kind == 1:
+        return (1 << (32 * n)) - 1
+    if kind == 2:
+        return 1 << rng.randrange(32 * n)
+    byte = 0x7f if kind == 3 else 0x80
+    x = int.from_bytes(bytes([byte]) * (4 * n), "little")
+    return x ^ (rng.getrandbits(8) << (8 * rng.randrange(4 * n)))
+
+
+@pytest.mark.parametrize("na,nb,threads", [(1, 1, 256), (3, 5, 1024), (7, 7, 256), (8, 300, 1024), (64, 64, 256),
+                                           (65, 63, 1024), (127, 135, 256), (200, 131, 256), (770, 1539, 1024),
+                                           (1539, 1538, 1024)])
+def test_debug_mul_wg_matches_host(na, nb, threads):
+    # the one-workgroup MFMA product: exact, also truncated to fewer limbs
+    say("debug_mul_wg", na, nb, threads)
+    rng = random.Random(na * 7919 + nb)
+    for it in range(5):
+        a, b = _structured(rng, na), _structured(rng, nb)
+        nout = na + nb if it % 2 == 0 else max(1, na + nb - rng.randrange(1, na + nb + 1))
+        got = ctx().debug_mul_wg(a, b, na, nb, nout, threads)
+        assert got == (a * b) % (1 << (32 * nout)), (it, nout)
+
+
 @pytest.mark.parametrize("P", [256, 2048, 8192])
 def test_debug_pivot_reciprocal(P):
     say("debug_recip", P)
