@@ -238,7 +238,7 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
                             (int8_t*)(I.base + I.L.bdig)});
     rc.push_back(RecodeArgs{u.usrc, u.ulds, u.g.npan, I.dm.NT, u.u_rows, I.dm.nl, kDigitPad,
                             (int8_t*)(I.base + I.L.udig)});
-    NTm = std::max(NTm, I.dm.NT);
+    NTm = std::max(NTm, I.dm.NT * I.dm.nl);  // recode threads / 16
     MfmaEntry E{};
     E.m = mfma_args(I, u.g, u.u_rows);
     const int n = pick_ranges(tile_cost[j], step_cost, u.ntiles, 8 * I.dm.nl / MF_BLOCK_DIGITS, B->tune,

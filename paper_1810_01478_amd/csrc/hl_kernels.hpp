@@ -107,7 +107,8 @@ struct RecodeArgs {
   int npan, NT, nrows, nl, pad;
   int8_t* dst;
 };
-hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int NT_max, hipStream_t stream);
+// rows_limbs_max: the largest NT x nl of the records
+hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int rows_limbs_max, hipStream_t stream);
 hipError_t launch_upd_mfma_batch(const MfmaEntry* tab, const int4* items, int per_xcd, unsigned* heads,
                                  hipStream_t stream);
 hipError_t launch_carry_fix_batch(const MfmaEntry* tab, int count, int nrow_max, int ncol_max, hipStream_t stream);
@@ -177,6 +178,7 @@ namespace hl {
 // (narrow targets: few columns, any rank npan <= 16).  A work item is 32 rows x
 // one column x TP_DIGITS output digits.
 constexpr int TP_DIGITS = 512;    // output digits (128 limbs) per work item
+constexpr int TP_MAX_RANGES = 64; // output ranges per entry (entries of up to 8192 limbs)
 constexpr int TP_PADB = 640;      // zero digits after the S digits of each b row
 constexpr int TP_PADU_LO = 576;   // zero digits before / after the reversed digits of each u
 constexpr int TP_PADU_HI = 1216;
@@ -198,6 +200,7 @@ struct ToepArgs {
   int add;             // 0: A -= sum b u, 1: A += sum b u, 2: A = sum b u
   // derived by the launcher
   int RB_lo, nrb, ncols, nrg, Sb, Su;
+  unsigned char rg_order[TP_MAX_RANGES];  // output ranges, most steps first
 };
 hipError_t launch_upd_toep(const ToepArgs& a, hipStream_t stream);
 }  // namespace hl

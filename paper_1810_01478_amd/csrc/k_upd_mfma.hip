@@ -53,48 +53,30 @@ __device__ __forceinline__ int mf_col(int l) { return l & 31; }
 // ---------------------------------------------------------------------------
 // Recode the panel factors (two's complement, nl limbs) into balanced digits.
 // src: [16][NT][nl] limbs; dst: [slices][NT][16] bytes, slice = digit + pad.
+// One thread per (limb q, row, panel column): digits 4q .. 4q+3.
 __device__ __forceinline__ void recode_body(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows,
-                                            int nl, int pad, int8_t* __restrict__ dst, int gid) {
-  const int il = gid & 15, row = gid >> 4;
-  if (row >= NT) return;
-  const int S = 4 * nl;
+                                            int nl, int pad, int8_t* __restrict__ dst, size_t gid) {
+  const int il = (int)(gid & 15);
+  const size_t t = gid >> 4;
+  const int row = (int)(t % NT), q = (int)(t / NT);
+  if (q >= nl) return;
   const size_t rstride = (size_t)NT * 16;
-  int8_t* d = dst + (size_t)pad * rstride + (size_t)row * 16 + il;
-  if (il >= npan || row >= nrows) {
-    for (int j = 0; j < S; ++j) d[(size_t)j * rstride] = 0;
-    return;
-  }
-  const u32* x = src + (size_t)il * lds + (size_t)row * nl;
-  int carry = 0;
-  for (int q = 0; q < nl; ++q) {
-    const u32 limb = x[q];
-    for (int b = 0; b < 4; ++b) {
-      const int j = 4 * q + b;
-      int v;
-      if (j == S - 1)
-        v = (int)(int8_t)(limb >> 24) + carry;
-      else
-        v = (int)((limb >> (8 * b)) & 0xffu) + carry;
-      if (j < S - 1 && v >= 128) {
-        v -= 256;
-        carry = 1;
-      } else {
-        carry = 0;
-      }
-      d[(size_t)j * rstride] = (int8_t)v;
-    }
-  }
+  int8_t* d = dst + (size_t)(pad + 4 * q) * rstride + (size_t)row * 16 + il;
+  u32 v = 0;
+  if (il < npan && row < nrows) v = balanced_digits4(src + (size_t)il * lds + (size_t)row * nl, nl, q);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) d[(size_t)b * rstride] = (int8_t)(v >> (8 * b));
 }
 
 __global__ void k_recode(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows, int nl, int pad,
                          int8_t* __restrict__ dst) {
-  recode_body(src, lds, npan, NT, nrows, nl, pad, dst, blockIdx.x * blockDim.x + threadIdx.x);
+  recode_body(src, lds, npan, NT, nrows, nl, pad, dst, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // batch: blockIdx.y is the record
 __global__ void k_recode_b(const RecodeArgs* __restrict__ tab) {
   const RecodeArgs& a = tab[blockIdx.y];
-  recode_body(a.src, a.lds, a.npan, a.NT, a.nrows, a.nl, a.pad, a.dst, blockIdx.x * blockDim.x + threadIdx.x);
+  recode_body(a.src, a.lds, a.npan, a.NT, a.nrows, a.nl, a.pad, a.dst, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
@@ -422,9 +404,9 @@ RangeTab split_ranges(int nl, int S, int want) {
 
 hipError_t launch_recode(const u32* src, size_t lds, int npan, int NT, int nrows, int nl, int pad, int8_t* dst,
                          hipStream_t stream) {
-  const int threads = NT * 16;
-  hipLaunchKernelGGL(k_recode, dim3((threads + 255) / 256), dim3(256), 0, stream, src, lds, npan, NT, nrows, nl,
-                     pad, dst);
+  const size_t threads = (size_t)nl * NT * 16;
+  hipLaunchKernelGGL(k_recode, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, src, lds, npan, NT,
+                     nrows, nl, pad, dst);
   return hipGetLastError();
 }
 
@@ -482,10 +464,10 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   return e;
 }
 
-hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int NT_max, hipStream_t stream) {
+hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int rows_limbs_max, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  const int threads = NT_max * 16;
-  hipLaunchKernelGGL(k_recode_b, dim3((threads + 255) / 256, count), dim3(256), 0, stream, tab);
+  const size_t threads = (size_t)rows_limbs_max * 16;
+  hipLaunchKernelGGL(k_recode_b, dim3((unsigned)((threads + 255) / 256), count), dim3(256), 0, stream, tab);
   return hipGetLastError();
 }
 

@@ -202,22 +202,26 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
   if (h == 0) cb[n] = live ? carry : 0;
 }
 
-// Work items (range rg, row block, column) in range-major order; the workgroups
-// of a launch are dealt to the 8 XCDs in turn, so block b takes item
-// (b % 8) * per_xcd + b / 8 and the waves of one XCD share a limb range.
+// Work items (range, row block, column) in range-major order, the ranges with
+// the most steps first; block b takes item b, so the workgroups dealt to the
+// 8 XCDs in turn give every XCD the same mix of long and short items, and the
+// short ones fill in at the end.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_upd_toep(ToepArgs a, int per_xcd) {
-  const int b = blockIdx.x;
-  const int item = (b & 7) * per_xcd + (b >> 3);
+void k_upd_toep(ToepArgs a) {
+  const int item = blockIdx.x;
   const int per_rg = a.nrb * a.ncols;
   if (item >= a.nrg * per_rg) return;
-  const int rg = item / per_rg, rem = item - rg * per_rg;
+  const int k = item / per_rg, rem = item - k * per_rg;
+  const int rg = a.rg_order[k];  // longest ranges are dealt first
   const int rb = rem / a.ncols, cc = rem - rb * a.ncols;
-  toep_item(a, rg, a.RB_lo + rb, cc, a.carry + (size_t)item * 32);
+  toep_item(a, rg, a.RB_lo + rb, cc, a.carry + ((size_t)rg * per_rg + rem) * 32);
 }
 
 // Add the carry of range w at limb 128 (w + 1) of every entry, w = 0 .. nrg-2
-// (one thread per entry of the target).
+// (one thread per entry of the target).  The ranges' carries go in as 64-bit
+// adds on their own limb pairs, eight ranges at a time with all loads issued
+// together; an add that carries out of its pair is finished afterwards by
+// rippling +-1 upwards (rare).  Additions commute, so the order is free.
 __global__ void k_toep_carry(ToepArgs a) {
   const UpdArgs& g = a.g;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,64 +233,49 @@ __global__ void k_toep_carry(ToepArgs a) {
   if (!(r >= g.r_lo && r < g.r_hi && c < g.c_hi && (!g.tri || r >= c))) return;
   const int nw = g.nw;
   const size_t per_rg = (size_t)a.nrb * a.ncols;
-  for (int w = 0; w + 1 < a.nrg; ++w) {
-    const i64 cv = a.carry[((size_t)w * per_rg + (size_t)rb * a.ncols + cc) * 32 + n];
-    if (cv == 0) continue;
-    int li = (TP_DIGITS / 4) * (w + 1);
-    if (li >= nw) continue;
-    u32* p0 = tp_entry(a, r, c, li);
-    const u64 x0 = ((u64)p0[1] << 32) | p0[0];
-    const u64 s2 = x0 + (u64)cv;
-    const u64 cy = s2 < x0 ? 1 : 0;
-    p0[0] = (u32)s2;
-    p0[1] = (u32)(s2 >> 32);
-    const u64 add = (cv < 0 ? ~0ull : 0ull) + cy;  // 0 (done), 1 (carry) or ~0 (borrow)
-    if (add == 0) continue;
-    for (li += 2; li < nw; li += 2) {
-      u32* p = tp_entry(a, r, c, li);
-      const u64 xv = ((u64)p[1] << 32) | p[0];
-      const u64 y = xv + add;
-      p[0] = (u32)y;
-      p[1] = (u32)(y >> 32);
-      if (add == 1 ? (y != 0) : (xv != 0)) break;
+  const long long* cbase = a.carry + ((size_t)rb * a.ncols + cc) * 32 + n;
+  constexpr int G = 8;
+  for (int w0 = 0; w0 + 1 < a.nrg; w0 += G) {
+    i64 cv[G];
+    u64 xv[G];
+    u32* pp[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int w = w0 + k, li = (TP_DIGITS / 4) * (w + 1);
+      const bool ok = w + 1 < a.nrg && li < nw;
+      cv[k] = ok ? cbase[(size_t)w * per_rg * 32] : 0;
+      pp[k] = tp_entry(a, r, c, ok ? li : 0);
+      xv[k] = ok ? (((u64)pp[k][1] << 32) | pp[k][0]) : 0;
+    }
+    int dir[G];  // what the pair's add passes to the limbs above: 0, +1 or -1
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      dir[k] = 0;
+      if (cv[k] == 0) continue;
+      const u64 s2 = xv[k] + (u64)cv[k];
+      pp[k][0] = (u32)s2;
+      pp[k][1] = (u32)(s2 >> 32);
+      // the sign-extended add of cv: +1 when the unsigned add wrapped, and the
+      // extension of a negative cv contributes -1 above the pair
+      dir[k] = (s2 < xv[k] ? 1 : 0) + (cv[k] < 0 ? -1 : 0);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (dir[k] == 0) continue;
+      const u64 add = dir[k] > 0 ? 1ull : ~0ull;
+      for (int li = (TP_DIGITS / 4) * (w0 + k + 1) + 2; li < nw; li += 2) {
+        u32* p = tp_entry(a, r, c, li);
+        const u64 x = ((u64)p[1] << 32) | p[0];
+        const u64 y = x + add;
+        p[0] = (u32)y;
+        p[1] = (u32)(y >> 32);
+        if (dir[k] > 0 ? (y != 0) : (x != 0)) break;  // the carry or borrow stops here
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Balanced digits 4q .. 4q+3 of the nl-limb two's complement x, packed in a
-// word (digit 4q in the low byte).  Digit j is byte_j + c_j - 256 c_{j+1} with
-// c_{j+1} = [byte_j + c_j >= 128], except the top digit, which keeps the sign.
-// The carry into digit 4q is found by looking down past bytes 0x7f.
-__device__ __forceinline__ u32 tp_digits4(const u32* __restrict__ x, int nl, int q) {
-  int cin = 0;
-  for (int j = 4 * q - 1; j >= 0; --j) {
-    const u32 byte = (x[j >> 2] >> (8 * (j & 3))) & 0xffu;
-    if (byte != 0x7fu) {
-      cin = byte >= 0x80u ? 1 : 0;
-      break;
-    }
-  }
-  const u32 limb = x[q];
-  const int top = 4 * nl - 1;
-  u32 out = 0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int j = 4 * q + b;
-    int v;
-    if (j == top) {
-      v = (int)(int8_t)(limb >> 24) + cin;
-      cin = 0;
-    } else {
-      v = (int)((limb >> (8 * b)) & 0xffu) + cin;
-      cin = v >= 128 ? 1 : 0;
-      if (cin) v -= 256;
-    }
-    out |= (u32)(v & 0xff) << (8 * b);
-  }
-  return out;
-}
-
 // b digits, forward: bd[p][row][j], rows 32 RB_lo .. 32 (RB_lo + nrb) - 1
 // (rows outside [r_lo, r_hi) read as zero), zero for j >= Sb.
 __global__ void k_toep_recode_b(ToepArgs a) {
@@ -302,7 +291,7 @@ __global__ void k_toep_recode_b(ToepArgs a) {
   u32 v = 0;
   if (4 * w < a.Sb && row >= g.r_lo && row < g.r_hi) {
     const size_t rsb = g.rsb ? g.rsb : (size_t)a.nlb;
-    v = tp_digits4(g.Bop + (size_t)p * g.ldb + (size_t)row * rsb, a.nlb, w);
+    v = balanced_digits4(g.Bop + (size_t)p * g.ldb + (size_t)row * rsb, a.nlb, w);
   }
   u32* dst = (u32*)(a.bd + ((size_t)p * a.NT + row) * tp_bstride(a.Sb));
   dst[w] = v;
@@ -322,7 +311,7 @@ __global__ void k_toep_recode_u(ToepArgs a) {
   if (y >= 0 && y < a.Su) {
     // bytes y .. y+3 are digits Su-1-y .. Su-4-y: limb nlu-1-y/4, reversed
     const int c = g.c_lo + cc;
-    v = __builtin_bswap32(tp_digits4(g.Uop + (size_t)p * g.ldu + (size_t)c * a.ucs, a.nlu, a.nlu - 1 - y / 4));
+    v = __builtin_bswap32(balanced_digits4(g.Uop + (size_t)p * g.ldu + (size_t)c * a.ucs, a.nlu, a.nlu - 1 - y / 4));
   }
   u32* dst = (u32*)(a.ud + ((size_t)p * a.ncols + cc) * tp_ustride(a.Su));
   dst[w] = v;
@@ -346,6 +335,24 @@ hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
   a.nrb = (g.r_hi - 1) / 32 + 1 - a.RB_lo;
   a.ncols = g.c_hi - g.c_lo;
   a.nrg = tp_ranges(g.nw);
+  if (a.nrg > TP_MAX_RANGES) return hipErrorInvalidValue;
+  {
+    // steps of each output range (as toep_item counts them), longest first
+    int steps[TP_MAX_RANGES];
+    for (int rg = 0; rg < a.nrg; ++rg) {
+      const int t0 = TP_DIGITS * rg;
+      const int jlo = t0 - (a.Su - 1) > 0 ? t0 - (a.Su - 1) : 0;
+      const int jhi = t0 + TP_DIGITS - 1 < a.Sb - 1 ? t0 + TP_DIGITS - 1 : a.Sb - 1;
+      steps[rg] = jlo <= jhi ? (jhi - (jlo & ~31)) / 32 + 1 : 0;
+      a.rg_order[rg] = (unsigned char)rg;
+    }
+    for (int i = 1; i < a.nrg; ++i)  // stable insertion sort, descending
+      for (int j = i; j > 0 && steps[a.rg_order[j]] > steps[a.rg_order[j - 1]]; --j) {
+        const unsigned char t = a.rg_order[j];
+        a.rg_order[j] = a.rg_order[j - 1];
+        a.rg_order[j - 1] = t;
+      }
+  }
   if ((a.RB_lo + a.nrb) * 32 > a.NT) return hipErrorInvalidValue;
   const size_t rows = (size_t)a.nrb * 32;
   const size_t bneed = ((size_t)(g.npan - 1) * a.NT + (size_t)(a.RB_lo + a.nrb) * 32) * tp_bstride(a.Sb);
@@ -364,8 +371,7 @@ hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int per_xcd = (int)((items + 7) / 8);
-  hipLaunchKernelGGL(k_upd_toep, dim3(8 * per_xcd), dim3(64), 0, stream, a, per_xcd);
+  hipLaunchKernelGGL(k_upd_toep, dim3((unsigned)items), dim3(64), 0, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.nrg < 2) return e;
   const size_t ne = rows * a.ncols;

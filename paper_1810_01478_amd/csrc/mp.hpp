@@ -331,4 +331,38 @@ __device__ __forceinline__ void g_mul(const u32* a, int na, const u32* b, int nb
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Balanced digits 4q .. 4q+3 of the nl-limb two's complement x, packed in a
+// word (digit 4q in the low byte).  Digit j is byte_j + c_j - 256 c_{j+1} with
+// c_{j+1} = [byte_j + c_j >= 128], except the top digit, which keeps the sign.
+// The carry into digit 4q is found by looking down past bytes 0x7f.
+__device__ __forceinline__ u32 balanced_digits4(const u32* __restrict__ x, int nl, int q) {
+  int cin = 0;
+  for (int j = 4 * q - 1; j >= 0; --j) {
+    const u32 byte = (x[j >> 2] >> (8 * (j & 3))) & 0xffu;
+    if (byte != 0x7fu) {
+      cin = byte >= 0x80u ? 1 : 0;
+      break;
+    }
+  }
+  const u32 limb = x[q];
+  const int top = 4 * nl - 1;
+  u32 out = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = 4 * q + b;
+    int v;
+    if (j == top) {
+      v = (int)(int8_t)(limb >> 24) + cin;
+      cin = 0;
+    } else {
+      v = (int)((limb >> (8 * b)) & 0xffu) + cin;
+      cin = v >= 128 ? 1 : 0;
+      if (cin) v -= 256;
+    }
+    out |= (u32)(v & 0xff) << (8 * b);
+  }
+  return out;
+}
+
 }  // namespace hl
