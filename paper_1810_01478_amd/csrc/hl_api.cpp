@@ -139,7 +139,7 @@ Layout make_layout(const Dims& dm) {
     // users: trailing-matrix targets (nw limbs, up to NT rows), the column
     // products (one column of colprod_ld limbs), the block sums (32 rows of b
     // digits of 2 nl + 1 limbs, k columns of blk_nm limbs)
-    const size_t b1 = (size_t)16 * dm.NT * tp_bstride(dm.S);
+    const size_t b1 = (size_t)16 * dm.NT * tp_bstride(4 * (2 * dm.nl + 1));  // b rows up to 2 nl + 1 limbs
     const size_t b2 = (size_t)16 * 32 * tp_bstride(4 * (2 * dm.nl + 1));
     L.toep_b_bytes = b1 > b2 ? b1 : b2;
     L.toep_b = off;
@@ -160,6 +160,11 @@ Layout make_layout(const Dims& dm) {
     off += al((size_t)dm.k * dm.NT * L.blk_ny * 4);
     L.blk_m = off;
     off += al((size_t)dm.k * dm.k * L.blk_nm * 4);
+    L.adj_nr = 3 * dm.nl + 4;
+    L.adj_da = off;
+    off += al((size_t)16 * dm.N * dm.nw * 4);
+    L.adj_r = off;
+    off += al((size_t)dm.N * L.adj_nr * 4);
   }
   L.total = off;
   return L;
@@ -817,7 +822,43 @@ extern "C" hl_status hl_lambda_grad(hl_ctx* ctx, const hl_shape* sh, const hl_fa
       }
     }
   }
-  HIPCHK(launch_adj_contract(dmu, dmu_exp, (const int*)dmu_neg, w, dm, f->s, wp, Z, part, col, tot, dst, st));
+  if (sh->form == HL_FORM_MFMA8) {
+    // R_i = sum_j da_ij z_j as Toeplitz MFMA GEMMs of rank 16 over j
+    u32* DA = (u32*)(base + L.adj_da);
+    u32* R = (u32*)(base + L.adj_r);
+    HIPCHK(launch_adj_wprime(dmu, dmu_exp, w, dm, f->s, wp, st));
+    HIPCHK(launch_fill(R, (size_t)dm.N * L.adj_nr, 0u, st));
+    for (int j0 = 0; j0 < dm.N; j0 += 16) {
+      const int npan = dm.N - j0 < 16 ? dm.N - j0 : 16;
+      HIPCHK(launch_adj_da(dmu, dmu_exp, (const int*)dmu_neg, w, dm, f->s, wp, j0, npan, DA, dm.nw, dst, st));
+      UpdArgs g{};
+      g.A = R;
+      g.nw = L.adj_nr;
+      g.nl = dm.nl;
+      g.Bop = DA;
+      g.ldb = (size_t)dm.N * dm.nw;
+      g.rsb = (size_t)dm.nw;
+      g.Uop = Z + (size_t)j0 * nlz;
+      g.ldu = nlz;
+      g.npan = npan;
+      g.r_lo = 0;
+      g.r_hi = dm.N;
+      g.c_lo = 0;
+      g.c_hi = 1;
+      g.st = dst;
+      ToepArgs ta2 = toep_args(g, L, base, dm);
+      ta2.nlb = dm.nw;  // |da| < 2^(2P-3)
+      ta2.nlu = dm.nl;
+      ta2.plain = 1;
+      ta2.ldr = (size_t)L.adj_nr;
+      ta2.ldc = 0;
+      ta2.add = 1;
+      HIPCHK(launch_upd_toep(ta2, st));
+    }
+    HIPCHK(launch_adj_finish(R, L.adj_nr, Z, dm, part, col, tot, dst, st));
+  } else {
+    HIPCHK(launch_adj_contract(dmu, dmu_exp, (const int*)dmu_neg, w, dm, f->s, wp, Z, part, col, tot, dst, st));
+  }
   if (z) HIPCHK(hipMemcpyAsync(z, Z, (size_t)dm.N * nlz * 4, hipMemcpyDeviceToDevice, st));
   ta.end();
   if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;

@@ -23,6 +23,8 @@ struct Layout {
   int colprod_ld;
   size_t blk_y, blk_m;  // MFMA block sums: y_rb = x_rb w_r ([k][NT][blk_ny]), M ([k][k][blk_nm])
   int blk_ny, blk_nm;
+  size_t adj_da, adj_r;  // MFMA adjoint contraction: da for 16 columns ([16][N][nw]), R ([N][adj_nr])
+  int adj_nr;
   int omega_stride;
   int digit_slices;
   int blk_stride;

@@ -167,6 +167,13 @@ hipError_t launch_adj_row(const u32* ACC, const Dims& dm, int i, const i32* h, u
 hipError_t launch_adj_contract(const u32* dmu, const i64* dexp, const int* dneg, int w, const Dims& dm, const i32* s,
                                i64* wprime, const u32* Z, u32* part, unsigned long long* col, u32* tot,
                                DevStatus* st, hipStream_t stream);
+// MFMA form of the contraction (see k_adj_da, k_adj_part)
+hipError_t launch_adj_wprime(const u32* dmu, const i64* dexp, int w, const Dims& dm, const i32* s, i64* wprime,
+                             hipStream_t stream);
+hipError_t launch_adj_da(const u32* dmu, const i64* dexp, const int* dneg, int w, const Dims& dm, const i32* s,
+                         const i64* wprime, int j0, int npan, u32* DA, int lda, DevStatus* st, hipStream_t stream);
+hipError_t launch_adj_finish(const u32* R, int nr, const u32* Z, const Dims& dm, u32* part, unsigned long long* col,
+                             u32* tot, DevStatus* st, hipStream_t stream);
 }  // namespace hl
 
 namespace hl {

@@ -301,6 +301,53 @@ __global__ __launch_bounds__(ADJ_WAVES * 64) void k_adj_contract(
   }
 }
 
+// MFMA form of the contraction: the sums R_i = sum_j da_ij z_j run as
+// Toeplitz-form int8 GEMMs of rank 16 over j.  k_adj_da writes da_ij for the 16
+// columns j0 .. j0+15 of a launch as two's complement (nw limbs, da[p][i]);
+// k_adj_part then forms part_i = z_i R_i.
+__global__ __launch_bounds__(64) void k_adj_da(const u32* __restrict__ dmu, const i64* __restrict__ dexp,
+                                               const int* __restrict__ dneg, int w, Dims dm,
+                                               const i32* __restrict__ s, const i64* __restrict__ wprime, int j0,
+                                               u32* __restrict__ DA, int lda, DevStatus* st) {
+  if (has_error(st)) return;
+  const int i = blockIdx.x, p = blockIdx.y, j = j0 + p;
+  const int nw = dm.nw, m = i + j;
+  u32* da = DA + ((size_t)p * dm.N + i) * lda;
+  const u32* M = dmu + (size_t)m * w;
+  // |da_ij| = rnd(|dmu_m| 2^(e_m + W' - s_i - s_j)) over nw limbs, as k_adj_contract
+  const long sh = dexp[m] + wprime[0] - s[i] - s[j];
+  u32 carry = sh < 0 ? get_bit(M, w, -sh - 1) : 0u;
+  for (int base = 0; base < nw; base += WAVE) {
+    const int q = base + lane_id();
+    u64 v = 0;
+    if (q < nw) v = sh >= 0 ? limb_shl(M, w, sh, q) : limb_shr(M, w, -sh, q);
+    const u32 limb = w_resolve(v, carry);
+    if (q < nw) da[q] = limb;
+  }
+  wsync();
+  if (dneg[m]) w_neg(da, nw);
+}
+
+__global__ __launch_bounds__(64) void k_adj_part(const u32* __restrict__ R, int nr, const u32* __restrict__ Z, Dims dm,
+                                                 u32* __restrict__ part, DevStatus* st) {
+  if (has_error(st)) return;
+  const int i = blockIdx.x, nl = dm.nl;
+  const int ns = 4 * nl + 4;
+  extern __shared__ u32 lds[];
+  u32* acc = lds;       // nr
+  u32* zj = acc + nr;   // nl
+  w_copy(R + (size_t)i * nr, acc, nr);
+  w_copy(Z + (size_t)i * nl, zj, nl);
+  wsync();
+  const bool nR = (acc[nr - 1] >> 31) != 0, nz = (zj[nl - 1] >> 31) != 0;
+  if (nR) w_neg(acc, nr);
+  if (nz) w_neg(zj, nl);
+  u32* out = part + (size_t)i * ns;
+  for (int q = lane_id(); q < ns; q += WAVE) out[q] = 0;
+  wsync();
+  w_mac(out, ns, acc, nr, zj, nl, nR != nz);
+}
+
 // column sums of the parts (each limb position summed over rows as u64), then
 // one wave resolves the carries: the sum of two's complement numbers mod 2^(32 ns)
 __global__ __launch_bounds__(256) void k_adj_colsum(const u32* __restrict__ part, int N, int ns,
@@ -363,6 +410,39 @@ hipError_t launch_adj_row(const u32* ACC, const Dims& dm, int i, const i32* h, u
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_adj_row, dim3(1), dim3(64), lds, stream, ACC, dm, i, h, Z, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_wprime(const u32* dmu, const i64* dexp, int w, const Dims& dm, const i32* s, i64* wprime,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_adj_wprime, dim3(1), dim3(256), 0, stream, dmu, dexp, w, dm, s, wprime);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_da(const u32* dmu, const i64* dexp, const int* dneg, int w, const Dims& dm, const i32* s,
+                         const i64* wprime, int j0, int npan, u32* DA, int lda, DevStatus* st, hipStream_t stream) {
+  if (npan <= 0) return hipSuccess;
+  if (lda < dm.nw) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_adj_da, dim3(dm.N, npan), dim3(64), 0, stream, dmu, dexp, dneg, w, dm, s, wprime, j0, DA, lda,
+                     st);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_finish(const u32* R, int nr, const u32* Z, const Dims& dm, u32* part, unsigned long long* col,
+                             u32* tot, DevStatus* st, hipStream_t stream) {
+  const size_t lds = (size_t)(nr + dm.nl) * 4;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_adj_part, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adj_part, dim3(dm.N), dim3(64), lds, stream, R, nr, Z, dm, part, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ns = 4 * dm.nl + 4;
+  hipLaunchKernelGGL(k_adj_colsum, dim3((ns + 255) / 256), dim3(256), 0, stream, part, dm.N, ns, col);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_resolve, dim3(1), dim3(64), 0, stream, col, ns, tot);
   return hipGetLastError();
 }
 
