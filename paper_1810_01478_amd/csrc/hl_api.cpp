@@ -173,7 +173,7 @@ Layout make_layout(const Dims& dm) {
 }  // namespace hl
 
 // Toeplitz-form update over the workspace's digit and carry regions
-static ToepArgs toep_args(const UpdArgs& g, const Layout& L, char* base, const Dims& dm) {
+ToepArgs hl::toep_args(const UpdArgs& g, const Layout& L, char* base, const Dims& dm) {
   ToepArgs a{};
   a.g = g;
   a.bd = (int8_t*)(base + L.toep_b);

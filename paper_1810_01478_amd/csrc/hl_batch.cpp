@@ -66,7 +66,7 @@ struct Inst {
 // One recorded launch; offsets point into the plan buffer.
 struct Op {
   enum Kind {
-    FILL, SCALES, LOAD, PIVOT, COL, VALU, RECODE, MFMA, CARRY, TRSM_ROW, BLOCK, EIG
+    FILL, SCALES, LOAD, PIVOT, COL, VALU, RECODE, MFMA, CARRY, TRSM_ROW, BLOCK, EIG, COLU, COLFIN, TOEP
   } kind;
   int inst = -1;           // FILL, SCALES, LOAD, BLOCK: the instance
   size_t off = 0;          // table offset
@@ -75,7 +75,33 @@ struct Op {
   int a = 0, b = 0, c = 0, d = 0;  // launch extents (see issue())
   u32* fp = nullptr;       // FILL target
   size_t fn = 0;           // FILL words
+  size_t x[4] = {0, 0, 0, 0};  // TOEP: recode threads (b, u), work items, entries
 };
+
+// one batched Toeplitz-form launch set over prepared records
+void put_toep(Blob& blob, std::vector<Op>& ops, const std::vector<ToepArgs>& v) {
+  if (v.empty()) return;
+  Op o;
+  o.kind = Op::TOEP;
+  for (const ToepArgs& a : v) {
+    size_t e[4];
+    toep_extents(a, &e[0], &e[1], &e[2], &e[3]);
+    for (int q = 0; q < 4; ++q) o.x[q] = std::max(o.x[q], e[q]);
+    o.a = std::max(o.a, a.nrg);
+  }
+  o.off = blob.put(v);
+  o.count = (int)v.size();
+  ops.push_back(o);
+}
+
+// prepare a record and keep it if it has work
+hl_status add_toep(std::vector<ToepArgs>& v, ToepArgs a) {
+  bool empty = false;
+  const hipError_t e = toep_prepare(a, &empty);
+  if (e != hipSuccess) return fail(HL_EHIP, "Toeplitz update record: %s", hipGetErrorString(e));
+  if (!empty) v.push_back(a);
+  return HL_OK;
+}
 
 // cost of one work item of range rg of an MFMA entry, in MFMA steps
 double item_cost(const RangeTab& rt, int rg, int S) {
@@ -106,6 +132,7 @@ struct hl_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int steps = 0;  // panel steps recorded (for partial plans of the autotuner)
+  int nl_max = 0;
 };
 
 namespace {
@@ -327,18 +354,50 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
     for (int il = 0; il < 16; ++il) {
       const int c = i0 + il;
       std::vector<PivotArgs> pv;
-      std::vector<ColArgs> cl;
+      std::vector<ColArgs> cl, cu;      // VALU-form column step; MFMA form: u_r
+      std::vector<ColFinArgs> cf;       // MFMA form: rounding of the products
+      std::vector<ToepArgs> tprod, tin; // MFMA form: column products, in-panel updates
       std::vector<UpdArgs> ip;
-      int nlm = 0, rows = 0, nr = 0, nc = 0, nwm = 0;
+      int nlm = 0, rows = 0, nr = 0, nc = 0, nwm = 0, ldpm = 0;
+      hl_status hs;
       for (int i = 0; i < n; ++i) {
         Inst& I = B->inst[i];
         if (c >= I.dm.N) continue;
         const int npan = std::min(16, I.dm.N - i0);
         pv.push_back(PivotArgs{I.A, I.dm, c, I.in.f.d, I.in.f.h, I.omega, I.L.omega_stride, I.st});
-        cl.push_back(ColArgs{I.A, I.dm, c, i0, I.in.f.h, I.omega, I.L.omega_stride, I.up + (size_t)il * I.ldb,
-                             I.in.f.l + (size_t)c * I.ldb, I.st});
+        const ColArgs ca{I.A, I.dm, c, i0, I.in.f.h, I.omega, I.L.omega_stride, I.up + (size_t)il * I.ldb,
+                         I.in.f.l + (size_t)c * I.ldb, I.st};
         nlm = std::max(nlm, I.dm.nl);
         rows = std::max(rows, I.dm.NT - i0);
+        if (I.form == HL_FORM_MFMA8) {
+          // column step as in hl_factor: u_r, then P_r = u_r w_c as a Toeplitz
+          // GEMM, then b_r = rnd(P_r / 2^P)
+          u32* Pp = (u32*)(I.base + I.L.colprod);
+          cu.push_back(ca);
+          cf.push_back(ColFinArgs{ca, Pp, I.L.colprod_ld});
+          ldpm = std::max(ldpm, I.L.colprod_ld);
+          UpdArgs gp{};
+          gp.A = Pp;
+          gp.nw = I.L.colprod_ld;
+          gp.nl = I.dm.nl;
+          gp.Bop = ca.u_out;
+          gp.Uop = I.omega + (size_t)c * I.L.omega_stride;
+          gp.npan = 1;
+          gp.r_lo = c + 1;
+          gp.r_hi = I.dm.N;
+          gp.c_lo = 0;
+          gp.c_hi = 1;
+          gp.st = I.st;
+          ToepArgs tp = toep_args(gp, I.L, I.base, I.dm);
+          tp.nlb = I.dm.nl;
+          tp.nlu = I.dm.nl + 1;
+          tp.plain = 1;
+          tp.ldr = (size_t)I.L.colprod_ld;
+          tp.add = 2;
+          if ((hs = add_toep(tprod, tp)) != HL_OK) return hs;
+        } else {
+          cl.push_back(ca);
+        }
         if (il + 1 < npan) {
           UpdArgs g{};
           g.A = I.A;
@@ -355,6 +414,10 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
           g.c_lo = c + 1;
           g.c_hi = i0 + npan;
           g.st = I.st;
+          if (I.form == HL_FORM_MFMA8) {
+            if ((hs = add_toep(tin, toep_args(g, I.L, I.base, I.dm))) != HL_OK) return hs;
+            continue;
+          }
           ip.push_back(g);
           nr = std::max(nr, g.r_hi - g.r_lo);
           nc = std::max(nc, g.c_hi - g.c_lo);
@@ -368,11 +431,29 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
       o.count = (int)pv.size();
       o.d = nlm;
       B->ops.push_back(o);
-      o.kind = Op::COL;
-      o.off = blob.put(cl);
-      o.count = (int)cl.size();
-      o.a = rows;
-      B->ops.push_back(o);
+      if (!cl.empty()) {
+        o.kind = Op::COL;
+        o.off = blob.put(cl);
+        o.count = (int)cl.size();
+        o.a = rows;
+        B->ops.push_back(o);
+      }
+      if (!cu.empty()) {
+        o.kind = Op::COLU;
+        o.off = blob.put(cu);
+        o.count = (int)cu.size();
+        o.a = rows;
+        B->ops.push_back(o);
+        put_toep(blob, B->ops, tprod);
+        Op f2;
+        f2.kind = Op::COLFIN;
+        f2.off = blob.put(cf);
+        f2.count = (int)cf.size();
+        f2.a = rows;
+        f2.b = ldpm;
+        B->ops.push_back(f2);
+      }
+      put_toep(blob, B->ops, tin);
       if (!ip.empty()) {
         Op v;
         v.kind = Op::VALU;
@@ -445,7 +526,9 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
       const int r = R0 + j;
       std::vector<TrsmRowArgs> tr;
       std::vector<UpdArgs> ib;
+      std::vector<ToepArgs> tib;
       int km = 0, nlm = 0, nr = 0, nc = 0, nwm = 0;
+      hl_status hs;
       for (int i = 0; i < n; ++i) {
         Inst& I = B->inst[i];
         if (r >= I.dm.N) continue;
@@ -470,6 +553,10 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
           g.c_lo = 0;
           g.c_hi = I.dm.k;
           g.st = I.st;
+          if (I.form == HL_FORM_MFMA8) {
+            if ((hs = add_toep(tib, toep_args(g, I.L, I.base, I.dm))) != HL_OK) return hs;
+            continue;
+          }
           ib.push_back(g);
           nr = std::max(nr, g.r_hi - g.r_lo);
           nc = std::max(nc, g.c_hi - g.c_lo);
@@ -484,6 +571,7 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
       o.a = km;
       o.d = nlm;
       B->ops.push_back(o);
+      put_toep(blob, B->ops, tib);
       if (!ib.empty()) {
         Op v;
         v.kind = Op::VALU;
@@ -496,6 +584,8 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
         B->ops.push_back(v);
       }
     }
+    std::vector<ToepArgs> ttr;
+    hl_status hs2;
     std::vector<StepUpd> ups;
     for (int i = 0; i < n; ++i) {
       Inst& I = B->inst[i];
@@ -528,8 +618,14 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
       u.nrow = I.dm.nt - u.C_lo;
       u.ncol = 1;
       u.ntiles = u.nrow;
+      if (I.form == HL_FORM_MFMA8) {
+        // k <= 32 target columns: the Toeplitz form keeps every MFMA column busy
+        if ((hs2 = add_toep(ttr, toep_args(u.g, I.L, I.base, I.dm))) != HL_OK) return hs2;
+        continue;
+      }
       ups.push_back(u);
     }
+    put_toep(blob, B->ops, ttr);
     if (!ups.empty()) record_update_step(B, blob, ups);
   }
   // --- blocks (per instance) and eigen-steps (one launch)
@@ -603,6 +699,15 @@ hl_status issue(hl_batch* B, hipStream_t st) {
       case Op::EIG:
         HIPCHK(launch_eig_batch((const EigArgs*)(P + o.off), o.count, o.d, st));
         break;
+      case Op::COLU:
+        HIPCHK(launch_col_u_batch((const ColArgs*)(P + o.off), o.count, o.a, B->nl_max, st));
+        break;
+      case Op::COLFIN:
+        HIPCHK(launch_col_fin_batch((const ColFinArgs*)(P + o.off), o.count, o.a, o.b, st));
+        break;
+      case Op::TOEP:
+        HIPCHK(launch_upd_toep_batch((const ToepArgs*)(P + o.off), o.count, o.x[0], o.x[1], o.x[2], o.x[3], o.a, st));
+        break;
     }
   }
   return HL_OK;
@@ -657,6 +762,7 @@ hl_status init_batch(hl_ctx* ctx, int32_t count, const hl_instance* inst, const 
     Inst& I = B->inst[i];
     I.form = I.in.shape.form;
     if (I.dm.P < B->tune.valu_below_bits) I.form = HL_FORM_VALU;
+    B->nl_max = std::max(B->nl_max, I.dm.nl);
   }
   return HL_OK;
 }

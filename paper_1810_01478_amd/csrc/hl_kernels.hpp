@@ -48,6 +48,14 @@ struct ColArgs {
   DevStatus* st;
 };
 hipError_t launch_pivot_batch(const PivotArgs* tab, int count, int nl_max, hipStream_t stream);
+// batched split column step (one record per instance)
+struct ColFinArgs {
+  ColArgs c;
+  const u32* P;  // products u_r w_i, rows ldp limbs apart
+  int ldp;
+};
+hipError_t launch_col_u_batch(const ColArgs* tab, int count, int rows_max, int nl_max, hipStream_t stream);
+hipError_t launch_col_fin_batch(const ColFinArgs* tab, int count, int rows_max, int ldp_max, hipStream_t stream);
 hipError_t launch_col_batch(const ColArgs* tab, int count, int rows_max, int nl_max, hipStream_t stream);
 hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout,
                             hipStream_t stream);
@@ -210,4 +218,10 @@ struct ToepArgs {
   unsigned char rg_order[TP_MAX_RANGES];  // output ranges, most steps first
 };
 hipError_t launch_upd_toep(const ToepArgs& a, hipStream_t stream);
+// batched form: prepare each record on the host (derived fields, checks), then
+// one set of launches over a device table (grid.y = record; npan <= 0 skips)
+hipError_t toep_prepare(ToepArgs& a, bool* empty);
+void toep_extents(const ToepArgs& a, size_t* nb, size_t* nu, size_t* items, size_t* entries);
+hipError_t launch_upd_toep_batch(const ToepArgs* tab, int count, size_t nb_max, size_t nu_max, size_t items_max,
+                                size_t entries_max, int nrg_max, hipStream_t stream);
 }  // namespace hl

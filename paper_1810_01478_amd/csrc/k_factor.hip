@@ -402,9 +402,9 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_b(const ColArgs* __restrict
 // signed u_r, the product P_r = u_r w_i runs as an int8 MFMA GEMM (Toeplitz
 // form, all rows against the one w_i), and k_col_fin rounds
 // b_r = sign(P_r) ((|P_r| + 2^(P-1)) >> P).  Same bits as k_col.  One wave per row.
-__global__ __launch_bounds__(64) void k_col_u(ColArgs a) {
+__device__ __forceinline__ void col_u_body(const ColArgs& a, int bx) {
   const Dims dm = a.dm;
-  const int i = a.i, r = a.r0 + blockIdx.x;
+  const int i = a.i, r = a.r0 + bx;
   DevStatus* st = a.st;
   if (has_error(st) || r >= dm.NT) return;
   const int nl = dm.nl, nw = dm.nw;
@@ -436,10 +436,15 @@ __global__ __launch_bounds__(64) void k_col_u(ColArgs a) {
   for (int l = lane_id(); l < nl; l += WAVE) uo[l] = Us[l];
 }
 
+__global__ __launch_bounds__(64) void k_col_u(ColArgs a) { col_u_body(a, blockIdx.x); }
+
+// batch: blockIdx.y is the instance
+__global__ __launch_bounds__(64) void k_col_u_b(const ColArgs* __restrict__ tab) { col_u_body(tab[blockIdx.y], blockIdx.x); }
+
 // P: row r at P + r ldp (ldp >= 2 nl + 1 limbs, two's complement)
-__global__ __launch_bounds__(64) void k_col_fin(ColArgs a, const u32* __restrict__ P, int ldp) {
+__device__ __forceinline__ void col_fin_body(const ColArgs& a, const u32* __restrict__ P, int ldp, int bx) {
   const Dims dm = a.dm;
-  const int i = a.i, r = a.r0 + blockIdx.x;
+  const int i = a.i, r = a.r0 + bx;
   DevStatus* st = a.st;
   if (has_error(st) || r >= dm.NT) return;
   const int nl = dm.nl;
@@ -466,6 +471,15 @@ __global__ __launch_bounds__(64) void k_col_fin(ColArgs a, const u32* __restrict
   if (neg) w_neg(Ps + nl, nl);
   wsync();
   for (int l = lane_id(); l < nl; l += WAVE) bo[l] = Ps[nl + l];
+}
+
+__global__ __launch_bounds__(64) void k_col_fin(ColArgs a, const u32* __restrict__ P, int ldp) {
+  col_fin_body(a, P, ldp, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_col_fin_b(const ColFinArgs* __restrict__ tab) {
+  const ColFinArgs& f = tab[blockIdx.y];
+  col_fin_body(f.c, f.P, f.ldp, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -574,6 +588,24 @@ hipError_t launch_col_fin(const Dims& dm, int i, int r0, const u32* P, int ldp, 
   hipError_t e = allow_lds((const void*)k_col_fin, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_col_fin, dim3(nrows), dim3(64), lds, stream, a, P, ldp);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_u_batch(const ColArgs* tab, int count, int rows_max, int nl_max, hipStream_t stream) {
+  if (count <= 0 || rows_max <= 0) return hipSuccess;
+  const size_t lds = (size_t)(3 * nl_max + 1) * 4;  // nw + nl + 1 words
+  hipError_t e = allow_lds((const void*)k_col_u_b, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_u_b, dim3(rows_max, count), dim3(64), lds, stream, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_fin_batch(const ColFinArgs* tab, int count, int rows_max, int ldp_max, hipStream_t stream) {
+  if (count <= 0 || rows_max <= 0) return hipSuccess;
+  const size_t lds = (size_t)ldp_max * 4;
+  hipError_t e = allow_lds((const void*)k_col_fin_b, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_fin_b, dim3(rows_max, count), dim3(64), lds, stream, tab);
   return hipGetLastError();
 }
 

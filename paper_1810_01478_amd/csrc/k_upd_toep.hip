@@ -217,14 +217,27 @@ void k_upd_toep(ToepArgs a) {
   toep_item(a, rg, a.RB_lo + rb, cc, a.carry + ((size_t)rg * per_rg + rem) * 32);
 }
 
+// batch: blockIdx.y is the record (npan <= 0 skips it)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_upd_toep_b(const ToepArgs* __restrict__ tab) {
+  const ToepArgs& a = tab[blockIdx.y];
+  if (a.g.npan <= 0) return;
+  const int item = blockIdx.x;
+  const int per_rg = a.nrb * a.ncols;
+  if (item >= a.nrg * per_rg) return;
+  const int k = item / per_rg, rem = item - k * per_rg;
+  const int rg = a.rg_order[k];
+  const int rb = rem / a.ncols, cc = rem - rb * a.ncols;
+  toep_item(a, rg, a.RB_lo + rb, cc, a.carry + ((size_t)rg * per_rg + rem) * 32);
+}
+
 // Add the carry of range w at limb 128 (w + 1) of every entry, w = 0 .. nrg-2
 // (one thread per entry of the target).  The ranges' carries go in as 64-bit
 // adds on their own limb pairs, eight ranges at a time with all loads issued
 // together; an add that carries out of its pair is finished afterwards by
 // rippling +-1 upwards (rare).  Additions commute, so the order is free.
-__global__ void k_toep_carry(ToepArgs a) {
+__device__ __forceinline__ void toep_carry_body(const ToepArgs& a, int e) {
   const UpdArgs& g = a.g;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.nrb * 32 * a.ncols) return;
   if (has_error(g.st)) return;
   const int rr = e / a.ncols, cc = e - rr * a.ncols;
@@ -276,12 +289,19 @@ __global__ void k_toep_carry(ToepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+
+__global__ void k_toep_carry(ToepArgs a) { toep_carry_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
+
+__global__ void k_toep_carry_b(const ToepArgs* __restrict__ tab) {
+  const ToepArgs& a = tab[blockIdx.y];
+  if (a.g.npan > 0 && a.nrg > 1) toep_carry_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // b digits, forward: bd[p][row][j], rows 32 RB_lo .. 32 (RB_lo + nrb) - 1
 // (rows outside [r_lo, r_hi) read as zero), zero for j >= Sb.
-__global__ void k_toep_recode_b(ToepArgs a) {
+__device__ __forceinline__ void toep_recode_b_body(const ToepArgs& a, size_t gid) {
   const UpdArgs& g = a.g;
   const int BS4 = tp_bstride(a.Sb) / 4;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t rows = (size_t)a.nrb * 32;
   if (gid >= (size_t)g.npan * rows * BS4) return;
   const int w = (int)(gid % BS4);
@@ -298,10 +318,9 @@ __global__ void k_toep_recode_b(ToepArgs a) {
 }
 
 // u digits, reversed: ud[p][cc][TP_PADU_LO + y] = digit Su-1-y of u_(c_lo+cc), zero padded
-__global__ void k_toep_recode_u(ToepArgs a) {
+__device__ __forceinline__ void toep_recode_u_body(const ToepArgs& a, size_t gid) {
   const UpdArgs& g = a.g;
   const int US4 = tp_ustride(a.Su) / 4;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (size_t)g.npan * a.ncols * US4) return;
   const int w = (int)(gid % US4);
   const size_t pc = gid / US4;
@@ -317,10 +336,23 @@ __global__ void k_toep_recode_u(ToepArgs a) {
   dst[w] = v;
 }
 
-hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
-  const UpdArgs& g = a0.g;
-  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
-  ToepArgs a = a0;
+__global__ void k_toep_recode_b(ToepArgs a) { toep_recode_b_body(a, (size_t)blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ void k_toep_recode_u(ToepArgs a) { toep_recode_u_body(a, (size_t)blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ void k_toep_recode_b_b(const ToepArgs* __restrict__ tab) {
+  const ToepArgs& a = tab[blockIdx.y];
+  if (a.g.npan > 0) toep_recode_b_body(a, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void k_toep_recode_u_b(const ToepArgs* __restrict__ tab) {
+  const ToepArgs& a = tab[blockIdx.y];
+  if (a.g.npan > 0) toep_recode_u_body(a, (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Host: fill in the derived fields of a (launch extents, range order) and check
+// the capacities.  *empty when there is nothing to update.
+hipError_t toep_prepare(ToepArgs& a, bool* empty) {
+  const UpdArgs& g = a.g;
+  *empty = g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0;
+  if (*empty) return hipSuccess;
   if (a.nlb <= 0) a.nlb = g.nl;
   if (a.nlu <= 0) a.nlu = g.nl;
   if (a.ucs == 0) a.ucs = (size_t)a.nlu;
@@ -359,6 +391,27 @@ hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
   const size_t uneed = (size_t)g.npan * a.ncols * tp_ustride(a.Su);
   const long items = (long)a.nrg * a.nrb * a.ncols;
   if (bneed > a.bd_bytes || uneed > a.ud_bytes || (size_t)items * 32 > a.carry_words) return hipErrorInvalidValue;
+  (void)rows;
+  return hipSuccess;
+}
+
+// launch extents of a prepared record: recode threads (b, u), work items, entries
+void toep_extents(const ToepArgs& a, size_t* nb, size_t* nu, size_t* items, size_t* entries) {
+  const size_t rows = (size_t)a.nrb * 32;
+  *nb = (size_t)a.g.npan * rows * (tp_bstride(a.Sb) / 4);
+  *nu = (size_t)a.g.npan * a.ncols * (tp_ustride(a.Su) / 4);
+  *items = (size_t)a.nrg * a.nrb * a.ncols;
+  *entries = rows * a.ncols;
+}
+
+hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
+  ToepArgs a = a0;
+  bool empty = false;
+  hipError_t e0 = toep_prepare(a, &empty);
+  if (e0 != hipSuccess || empty) return e0;
+  const UpdArgs& g = a.g;
+  const size_t rows = (size_t)a.nrb * 32;
+  const long items = (long)a.nrg * a.nrb * a.ncols;
   {
     const size_t n = (size_t)g.npan * rows * (tp_bstride(a.Sb) / 4);
     hipLaunchKernelGGL(k_toep_recode_b, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
@@ -376,6 +429,22 @@ hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
   if (e != hipSuccess || a.nrg < 2) return e;
   const size_t ne = rows * a.ncols;
   hipLaunchKernelGGL(k_toep_carry, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_upd_toep_batch(const ToepArgs* tab, int count, size_t nb_max, size_t nu_max, size_t items_max,
+                                size_t entries_max, int nrg_max, hipStream_t stream) {
+  if (count <= 0 || items_max == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_toep_recode_b_b, dim3((unsigned)((nb_max + 255) / 256), count), dim3(256), 0, stream, tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_toep_recode_u_b, dim3((unsigned)((nu_max + 255) / 256), count), dim3(256), 0, stream, tab);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_upd_toep_b, dim3((unsigned)items_max, count), dim3(64), 0, stream, tab);
+  e = hipGetLastError();
+  if (e != hipSuccess || nrg_max < 2) return e;
+  hipLaunchKernelGGL(k_toep_carry_b, dim3((unsigned)((entries_max + 255) / 256), count), dim3(256), 0, stream, tab);
   return hipGetLastError();
 }
 
