@@ -66,7 +66,8 @@ struct Inst {
 // One recorded launch; offsets point into the plan buffer.
 struct Op {
   enum Kind {
-    FILL, SCALES, LOAD, PIVOT, COL, VALU, RECODE, MFMA, CARRY, TRSM_ROW, BLOCK, EIG, COLU, COLFIN, TOEP
+    FILL, SCALES, LOAD, PIVOT, COL, VALU, RECODE, MFMA, CARRY, TRSM_ROW, BLOCK, EIG, COLU, COLFIN, TOEP, BLOCKY,
+    BLOCKSUM
   } kind;
   int inst = -1;           // FILL, SCALES, LOAD, BLOCK: the instance
   size_t off = 0;          // table offset
@@ -628,17 +629,61 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
     put_toep(blob, B->ops, ttr);
     if (!ups.empty()) record_update_step(B, blob, ups);
   }
-  // --- blocks (per instance) and eigen-steps (one launch)
+  // --- blocks and eigen-steps (one launch).  MFMA form as in hl_inv_block:
+  // y = x w per instance, the sums over r as Toeplitz GEMMs of rank 16 in lock
+  // step over all instances, then gather, reduction and rounding per instance
   std::vector<EigArgs> eg;
   int nlm = 0;
   for (int i = 0; i < n; ++i) {
     Op b;
-    b.kind = Op::BLOCK;
+    b.kind = B->inst[i].form == HL_FORM_MFMA8 ? Op::BLOCKY : Op::BLOCK;
     b.inst = i;
     B->ops.push_back(b);
     Inst& I = B->inst[i];
     eg.push_back(eig_args(I.in.blk, I.dm, I.base + I.L.eig, I.st));
     nlm = std::max(nlm, I.dm.nl);
+  }
+  for (int r0 = 0; r0 < Nmax; r0 += 16) {
+    std::vector<ToepArgs> tb;
+    for (int i = 0; i < n; ++i) {
+      Inst& I = B->inst[i];
+      if (I.form != HL_FORM_MFMA8 || r0 >= I.dm.N) continue;
+      UpdArgs g{};
+      g.A = (u32*)(I.base + I.L.blk_m);
+      g.tri = 1;
+      g.nw = I.L.blk_nm;
+      g.nl = I.dm.nl;
+      g.Bop = (u32*)(I.base + I.L.blk_y) + (size_t)r0 * I.L.blk_ny;
+      g.ldb = I.L.blk_ny;
+      g.rsb = (size_t)I.dm.NT * I.L.blk_ny;
+      g.Uop = I.in.x + (size_t)r0 * I.ldx;
+      g.ldu = I.ldx;
+      g.npan = std::min(16, I.dm.N - r0);
+      g.r_lo = 0;
+      g.r_hi = I.dm.k;
+      g.c_lo = 0;
+      g.c_hi = I.dm.k;
+      g.st = I.st;
+      ToepArgs ta = toep_args(g, I.L, I.base, I.dm);
+      ta.NT = 32;
+      ta.nlb = 2 * I.dm.nl + 1;
+      ta.nlu = I.dm.nl;
+      ta.ucs = (size_t)I.dm.nl;
+      ta.plain = 1;
+      ta.ldr = (size_t)I.dm.k * I.L.blk_nm;
+      ta.ldc = (size_t)I.L.blk_nm;
+      ta.add = 1;
+      hl_status hs3 = add_toep(tb, ta);
+      if (hs3 != HL_OK) return hs3;
+    }
+    put_toep(blob, B->ops, tb);
+  }
+  for (int i = 0; i < n; ++i) {
+    if (B->inst[i].form != HL_FORM_MFMA8) continue;
+    Op b;
+    b.kind = Op::BLOCKSUM;
+    b.inst = i;
+    B->ops.push_back(b);
   }
   Op e;
   e.kind = Op::EIG;
@@ -699,6 +744,22 @@ hl_status issue(hl_batch* B, hipStream_t st) {
       case Op::EIG:
         HIPCHK(launch_eig_batch((const EigArgs*)(P + o.off), o.count, o.d, st));
         break;
+      case Op::BLOCKY: {
+        const Inst& I = B->inst[o.inst];
+        HIPCHK(launch_fill((u32*)(I.base + I.L.blk_m), (size_t)I.dm.k * I.dm.k * I.L.blk_nm, 0u, st));
+        HIPCHK(launch_block_y(I.in.x, I.dm, I.omega, I.L.omega_stride, (u32*)(I.base + I.L.blk_y), I.L.blk_ny, I.st,
+                              st));
+        break;
+      }
+      case Op::BLOCKSUM: {
+        const Inst& I = B->inst[o.inst];
+        u32* part = (u32*)(I.base + I.L.blk_part);
+        HIPCHK(launch_block_gather((const u32*)(I.base + I.L.blk_m), I.L.blk_nm, I.dm, part, I.L.blk_stride, I.st,
+                                   st));
+        HIPCHK(launch_block_sums(I.dm, I.in.f.s, part, I.L.blk_stride, 1, (u32*)(I.base + I.L.blk_sum),
+                                 I.L.blk_stride + 64, I.in.blk, I.in.blk_exp, I.st, st));
+        break;
+      }
       case Op::COLU:
         HIPCHK(launch_col_u_batch((const ColArgs*)(P + o.off), o.count, o.a, B->nl_max, st));
         break;
@@ -753,7 +814,7 @@ hl_status init_batch(hl_ctx* ctx, int32_t count, const hl_instance* inst, const 
   B->ctx = ctx;
   B->plan = (char*)plan;
   B->plan_bytes = plan_bytes;
-  B->tune = tune ? *tune : hl_tune_t{4, kMaxRanges, 0, 0};
+  B->tune = tune ? *tune : hl_tune_t{8, kMaxRanges, 0, 0};
   if (B->tune.items_per_simd < 1) B->tune.items_per_simd = 1;
   B->inst.resize(count);
   for (int i = 0; i < count; ++i) {
