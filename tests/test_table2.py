@@ -1,0 +1,51 @@
+"""The paper's Table 2 (beta = 1/2, k = 8) as golden values.
+
+CPU: the fixture reads back whole and keeps the orderings the mathematics fixes
+(lambda_1 < lambda_2 < lambda_3, each decreasing in N; truncation estimates
+negative, by Cauchy interlacing of the k-1 block inside the k block).
+GPU: the whole path (moments -> LDL^T -> first k columns of L^-1 -> block of
+H^-1 -> eigen-step) at N = 500 and N = 1000, k = 8, reproduces the printed
+lambda_1 to the 16 printed digits and the truncation estimate within the
+double-precision error of the paper's own difference; N >= 1500 needs more than this library's
+largest precision (57344 bits) under its scaled fixed-point contract."""
+from fractions import Fraction
+
+import pytest
+
+from golden_table2 import table2
+
+
+def test_fixture_orderings():
+    t = table2()
+    assert sorted(t) == [500, 1000, 1500, 2000, 2500, 3000, 3500, 4000, 4500]
+    prev = None
+    for N in sorted(t):
+        r = t[N]
+        assert 0 < r.lambda1 < r.lambda2 < r.lambda3
+        assert r.trunc1 < 0 and r.trunc2 < 0 and r.trunc3 < 0
+        if prev is not None:
+            assert r.lambda1 < prev.lambda1 and r.lambda2 < prev.lambda2 and r.lambda3 < prev.lambda3
+        prev = r
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("N", [500, 1000])
+def test_lambda1_reproduces_table2(N):
+    from hankel_inputs import moments
+    from hankel_inputs.moments import precision_rule
+    from gpu_util import ctx, say
+    row = table2()[N]
+    beta = Fraction(1, 2)
+    P = precision_rule(beta, N)
+    say("table 2", N, P)
+    mu = moments(beta, 2 * N - 1, P + 64)
+    fac = ctx().factor(mu, N, 8, P, 16, "mfma")
+    res = ctx().lambda_min(fac)
+    say("  lambda1", repr(res["lambda1"]), "paper", row.lambda1, "trunc", res["trunc"], "paper", row.trunc1)
+    # 16 printed digits, computed there in double precision from the block
+    assert abs(res["lambda1"] / row.lambda1 - 1) < 2e-15
+    # the paper's estimate is the difference of two eigenvalues computed in
+    # double precision, each good to about the 2e-15 relative agreement above,
+    # so it carries an absolute error of that order (here it is exact)
+    assert res["trunc"] < 0
+    assert abs(res["trunc"] - row.trunc1) <= 2e-15 * row.lambda1
