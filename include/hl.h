@@ -107,6 +107,17 @@ typedef struct {
   int32_t reserved;
 } hl_lambda_t;
 
+/* One further eigenvalue from hl_lambda_next (host). */
+typedef struct {
+  double lambda;      /* lambda_j ~= 1 / (j-th largest eigenvalue of the k x k block)    */
+  double lambda_km1;  /* the same from the leading (k-1) x (k-1) block                   */
+  double trunc;       /* lambda - lambda_km1 (<= 0 by interlacing), truncation estimate  */
+  int64_t exp;        /* lambda = mant * 2^exp (mant: nl limbs, unsigned)                */
+  int64_t exp_km1;    /* lambda_km1 = mant_km1 * 2^exp_km1                               */
+  int32_t j;          /* 2, 3                                                             */
+  int32_t iterations; /* eigen-step iterations used (both blocks)                        */
+} hl_lambda_j_t;
+
 /* Context: selects the device and holds timers.  Not thread safe. */
 hl_status hl_create(hl_ctx **ctx, int device);
 hl_status hl_destroy(hl_ctx *ctx);
@@ -167,6 +178,25 @@ hl_status hl_inv_block(hl_ctx *ctx, const hl_shape *sh, const hl_factor_t *f, vo
 hl_status hl_lambda_min(hl_ctx *ctx, const hl_shape *sh, const uint32_t *blk, const int64_t *blk_exp,
                         void *ws, size_t ws_bytes, uint32_t *lam_mant, uint32_t *lam_mant_km1,
                         hl_lambda_t *out, void *stream);
+
+/*
+ * hl_lambda_next -- lambda_2 and lambda_3 with their truncation estimates (the
+ * further columns of Table 2; the estimate as in Section 4.5): the j-th
+ * smallest eigenvalue of H_N taken as 1 / (j-th largest eigenvalue of the
+ * block), for the k x k block and its leading (k-1) x (k-1) block.  Each
+ * eigenvalue comes from the block deflated by the eigenpairs found before it,
+ * B - mu y y^T / (y^T y) in the eigen-step's multiprecision floating point, and
+ * the same certified inverse iteration as hl_lambda_min.  Needs hl_lambda_min
+ * on the same workspace first (it uses that call's eigenvectors).  Synchronises
+ * the stream; returns the first device error of the workspace if there is one.
+ *   count            1 (lambda_2) or 2 (lambda_2, lambda_3); EINVAL unless k >= count + 2
+ *   mant, mant_km1   optional device outputs, count x nl limbs each (NULL: skip)
+ *   out              host, count entries (out[j - 2] for lambda_j)
+ * Device errors: HL_ENOCONV (index = 2 (j - 1) for the k x k block, + 1 for the other).
+ */
+hl_status hl_lambda_next(hl_ctx *ctx, const hl_shape *sh, const uint32_t *blk, const int64_t *blk_exp,
+                         void *ws, size_t ws_bytes, int32_t count, uint32_t *mant, uint32_t *mant_km1,
+                         hl_lambda_j_t *out, void *stream);
 
 /*
  * hl_lambda_grad -- the derivative of lambda_1 along a moment direction dmu

@@ -12,9 +12,10 @@ Modules
 contract  the fixed-point contract step by step, in Python integers:
           scales, load, Algorithm 1 with explicit rounding points, Algorithm 4
           for the first k columns of L^-1, eq. ``equ:index`` for the block, and
-          the largest eigenvalue of the block by a dense library eigen-solver.
+          the largest eigenvalue of the block by a dense library eigen-solver,
+          and (``eigen_next``) the next ones, lambda_2 and lambda_3 of Table 2.
 exact     exact rational arithmetic for tiny N: LDL^T, L^-1, H^-1 block, and the
-          characteristic polynomial of H_N for a brute-force smallest eigenvalue.
+          characteristic polynomial of H_N for brute-force eigenvalues.
 adjoint   the derivative of lambda_1 with respect to the moments (the adjoint
           vector mubar) and its contraction with d mu / d beta, from the
           definition, in mpmath.

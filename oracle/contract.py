@@ -351,6 +351,53 @@ def eigen(blk: Block, prec: Optional[int] = None, P: Optional[int] = None) -> La
         return Lambda(lam1=lam1, lam1_km1=lam1m, trunc=lam1 - lam1m, lmax_blk=lk, prec=prec)
 
 
+@dataclass
+class LambdaJ:
+    j: int                        # 2, 3, ...
+    lam: object                   # 1 / (j-th largest eigenvalue of the k x k block)
+    lam_km1: object               # the same from the leading (k-1) x (k-1) block
+    trunc: object                 # lam - lam_km1 (<= 0 by interlacing)
+
+
+def _eigs_desc(mat: List[List[int]], prec: int):
+    import mpmath
+    with mpmath.workprec(prec):
+        n = len(mat)
+        M = mpmath.matrix(n, n)
+        for a in range(n):
+            for b2 in range(n):
+                M[a, b2] = mpmath.mpf(mat[a][b2])
+        ev = mpmath.eigsy(M, eigvals_only=True)
+        return sorted((ev[i] for i in range(n)), reverse=True)
+
+
+def eigen_next(blk: Block, count: int, prec: Optional[int] = None, P: Optional[int] = None) -> List[LambdaJ]:
+    """Table 2 (Section 5) prints lambda_2 and lambda_3 beside lambda_1, each
+    with its truncation estimate.  As for lambda_1 (Section 4.2), the j-th
+    smallest eigenvalue of H_N is taken as 1 / (j-th largest eigenvalue of the
+    k x k block of H^-1), and the estimate (Section 4.5) is that minus the same
+    from the leading (k-1) x (k-1) block; Cauchy interlacing of the smaller
+    block in the larger makes it <= 0.  lambda_j for j = 2 .. count + 1, so the
+    (k-1) block needs count + 1 eigenvalues: k >= count + 2.  All eigenvalues
+    of each integer block from one dense symmetric eigen-solve at ``prec`` bits
+    (default 2P + 64)."""
+    import mpmath
+    if prec is None:
+        prec = 2 * (P or 1024) + 64
+    k = blk.k
+    if count < 1 or k < count + 2:
+        raise ContractError(EINVAL, k, "lambda_%d with its estimate needs k >= %d" % (count + 1, count + 2))
+    with mpmath.workprec(prec):
+        ek = _eigs_desc(blk.blk, prec)
+        ekm1 = _eigs_desc([row[:k - 1] for row in blk.blk[:k - 1]], prec)
+        out = []
+        for j in range(2, count + 2):
+            lam = mpmath.ldexp(1 / ek[j - 1], -blk.blk_exp)
+            lamm = mpmath.ldexp(1 / ekm1[j - 1], -blk.blk_exp)
+            out.append(LambdaJ(j=j, lam=lam, lam_km1=lamm, trunc=lam - lamm))
+        return out
+
+
 def lambda_min(mu: Sequence, N: int, k: int, P: int, E: int = 16, prec: Optional[int] = None):
     """The whole path: factor -> solve -> block -> eigen."""
     f = factor(mu, N, P, E)

@@ -8,11 +8,13 @@ These functions are the plain definitions, with no rounding at all:
 * ``hinv_block``: eq. ``equ:index`` summed exactly over l;
 * ``charpoly``: the characteristic polynomial of H_N, by the Faddeev-LeVerrier
   recurrence in rationals, and ``smallest_root`` which isolates its smallest
-  root by bisection on exact sign changes (the brute-force smallest eigenvalue).
+  root by bisection on exact sign changes (the brute-force smallest eigenvalue);
+  ``kth_root`` the same for the j-th smallest root (lambda_2, lambda_3).
 
 Parity status: pinned by closed forms (beta = 1: D_m = (m!)^2, L_ij = C(i,j) i!/j!,
 det H_N = prod (m!)^2), by H == L D L^T exactly, and by sympy's independent
-characteristic polynomial in tests/test_oracle_exact.py.
+characteristic polynomial in tests/test_oracle_pins.py; ``kth_root`` by a
+polynomial with known rational roots in tests/test_oracle_pins.py.
 """
 
 from __future__ import annotations
@@ -140,6 +142,26 @@ def smallest_root(c: List[Fraction], hi: Fraction, bits: int = 200) -> Fraction:
     for _ in range(bits):
         mid = (lo + up) / 2
         if v0 - _sign_changes(chain, mid) >= 1:
+            up = mid
+        else:
+            lo = mid
+    return (lo + up) / 2
+
+
+def kth_root(c: List[Fraction], j: int, hi: Fraction, bits: int = 200) -> Fraction:
+    """j-th smallest positive root of a polynomial whose roots are real and
+    simple (the characteristic polynomial of a positive definite matrix with
+    distinct eigenvalues): Sturm's theorem counts the roots in (0, x], and the
+    bracket [0, hi] is halved ``bits`` times keeping at least j roots in (0, up]
+    and fewer than j in (0, lo]."""
+    chain = sturm_chain(c)
+    v0 = _sign_changes(chain, Fraction(0))
+    lo, up = Fraction(0), Fraction(hi)
+    if v0 - _sign_changes(chain, up) < j:
+        raise ValueError("fewer than %d roots below hi" % j)
+    for _ in range(bits):
+        mid = (lo + up) / 2
+        if v0 - _sign_changes(chain, mid) >= j:
             up = mid
         else:
             lo = mid

@@ -217,6 +217,28 @@ class Context:
         self.inv_block(fac, stream)
         return self.eigen(fac, stream=stream)
 
+    def lambda_next(self, fac: Factorization, count: int = 2, want_mant=True, stream=None):
+        """lambda_2 (and lambda_3) with their truncation estimates (hl_lambda_next);
+        needs lambda_min(fac) first.  One dict per eigenvalue, j = 2, 3."""
+        nl = fac.nl
+        out = (L.hl_lambda_j_t * count)()
+        m1 = torch.zeros(count * nl, dtype=torch.int32, device=self.device) if want_mant else None
+        m2 = torch.zeros(count * nl, dtype=torch.int32, device=self.device) if want_mant else None
+        L.check(L.lib().hl_lambda_next(self.h, ctypes.byref(fac.shape), _ptr(fac.blk), _ptr(fac.blk_exp),
+                                       _ptr(fac.ws), fac.ws.numel(), count,
+                                       _ptr(m1) if m1 is not None else None,
+                                       _ptr(m2) if m2 is not None else None, out, _stream(stream)))
+        res = []
+        for i in range(count):
+            o = out[i]
+            r = {"j": o.j, "lambda": o.lambda_, "lambda_km1": o.lambda_km1, "trunc": o.trunc, "exp": o.exp,
+                 "exp_km1": o.exp_km1, "iterations": o.iterations}
+            if want_mant:
+                r["mant"] = _ints(m1[i * nl:(i + 1) * nl], nl, signed=False)[0]
+                r["mant_km1"] = _ints(m2[i * nl:(i + 1) * nl], nl, signed=False)[0]
+            res.append(r)
+        return res
+
     def pack_signed(self, vals):
         """Signed dyadics (M, e) as magnitude limbs, exponents and sign flags."""
         mags = [abs(v.M) for v in vals]

@@ -620,6 +620,67 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   return read_lambda(dm, ews, bexp, lam_mant, lam_mant_km1, out);
 }
 
+// one multiprecision result of the eigen-step as a double and (optionally) its
+// top nl limbs on the device; *e_out = exponent of those limbs
+static hl_status read_fp(const Dims& dm, int* hdr, u32* mant, int64_t bexp, double* v_out, int64_t* e_out,
+                         uint32_t* dst) {
+  const int NWM = dm.nl + 4;
+  int h2[2];
+  std::vector<uint32_t> m(NWM);
+  HIPCHK(hipMemcpy(h2, hdr, 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(m.data(), mant, (size_t)NWM * 4, hipMemcpyDeviceToHost));
+  const long e = (long)h2[1] - bexp;
+  *v_out = h2[0] == 2 ? 0.0 : fp_to_double(h2[0], e, m);
+  if (e_out) *e_out = e - 32L * dm.nl;
+  if (dst) HIPCHK(hipMemcpy(dst, m.data() + (NWM - dm.nl), (size_t)dm.nl * 4, hipMemcpyHostToDevice));
+  return HL_OK;
+}
+
+extern "C" hl_status hl_lambda_next(hl_ctx* ctx, const hl_shape* sh, const uint32_t* blk, const int64_t* blk_exp,
+                                    void* ws, size_t ws_bytes, int32_t count, uint32_t* mant, uint32_t* mant_km1,
+                                    hl_lambda_j_t* out, void* stream) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  Dims dm;
+  hl_status s = make_dims(sh, &dm);
+  if (s != HL_OK) return s;
+  if (!blk || !blk_exp || !out) return fail(HL_EINVAL, "null argument");
+  if (count < 1 || count > 2) return fail(HL_EINVAL, "count=%d: 1 or 2 further eigenvalues", count);
+  if (dm.k < count + 2) return fail(HL_EINVAL, "k=%d: lambda_%d with its estimate needs k >= %d", dm.k, count + 1,
+                                    count + 2);
+  Layout L = make_layout(dm);
+  if ((s = check_ws(L, ws, ws_bytes)) != HL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  DevStatus* dst = (DevStatus*)(base + L.status);
+  void* ews = base + L.eig;
+  HIPCHK(launch_eig_next(blk, dm, ews, count, dst, st));
+  int32_t idx = 0;
+  if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;
+  int64_t bexp = 0;
+  HIPCHK(hipMemcpy(&bexp, blk_exp, 8, hipMemcpyDeviceToHost));
+  for (int j = 1; j <= count; ++j) {
+    hl_lambda_j_t& o = out[j - 1];
+    memset(&o, 0, sizeof o);
+    o.j = j + 1;
+    int* hdr = nullptr;
+    u32* m = nullptr;
+    eig_next_refs(dm, ews, 2 * j, false, &hdr, &m);
+    if ((s = read_fp(dm, hdr, m, bexp, &o.lambda, &o.exp, mant ? mant + (size_t)(j - 1) * dm.nl : nullptr)) != HL_OK)
+      return s;
+    eig_next_refs(dm, ews, 2 * j + 1, false, &hdr, &m);
+    if ((s = read_fp(dm, hdr, m, bexp, &o.lambda_km1, &o.exp_km1,
+                     mant_km1 ? mant_km1 + (size_t)(j - 1) * dm.nl : nullptr)) != HL_OK)
+      return s;
+    eig_next_refs(dm, ews, 2 * j, true, &hdr, &m);
+    if ((s = read_fp(dm, hdr, m, bexp, &o.trunc, nullptr, nullptr)) != HL_OK) return s;
+    int it[2];
+    HIPCHK(hipMemcpy(&it[0], eig_iter_ref(ews, 2 * j), 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&it[1], eig_iter_ref(ews, 2 * j + 1), 4, hipMemcpyDeviceToHost));
+    o.iterations = it[0] + it[1];
+  }
+  return HL_OK;
+}
+
 namespace hl {
 // host readback of the eigen-step's results (after the stream has finished)
 hl_status read_lambda(const Dims& dm, void* ews, int64_t bexp, uint32_t* lam_mant, uint32_t* lam_mant_km1,

@@ -120,7 +120,6 @@ hipError_t launch_recode_batch(const RecodeArgs* tab, int count, int rows_limbs_
 hipError_t launch_upd_mfma_batch(const MfmaEntry* tab, const int4* items, int per_xcd, unsigned* heads,
                                  hipStream_t stream);
 hipError_t launch_carry_fix_batch(const MfmaEntry* tab, int count, int nrow_max, int ncol_max, hipStream_t stream);
-size_t eig_ws_bytes_impl(int nl, int k);
 }  // namespace hl
 
 namespace hl {
@@ -162,6 +161,11 @@ hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStat
 hipError_t launch_eig_batch(const EigArgs* tab, int count, int nl_max, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
 void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out);
+// the next eigenvalues by deflation (after launch_eig_host; synchronises)
+hipError_t launch_eig_next(const u32* blk, const Dims& dm, void* eig_ws, int count, DevStatus* st,
+                           hipStream_t stream);
+void eig_next_refs(const Dims& dm, void* eig_ws, int mat, bool diff, int** hdr_out, u32** mant_out);
+int* eig_iter_ref(void* eig_ws, int mat);
 }  // namespace hl
 
 namespace hl {

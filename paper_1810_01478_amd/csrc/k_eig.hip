@@ -29,6 +29,14 @@ constexpr int EIG_WAVES = 8;
 constexpr int EIG_THREADS = EIG_WAVES * WAVE;
 constexpr int EIG_MAXIT = 400;
 constexpr int EIG_NSCAL = 24;
+// matrices of the workspace: 0 the k x k block, 1 its leading (k-1) x (k-1)
+// block; 2 j and 2 j + 1 (j = 1, 2) the same less the eigenpairs found in
+// matrices 2 j - 2 and 2 j - 1 (deflation, for the next eigenvalues)
+constexpr int EIG_MATS = 6;
+// flag words at the head of the workspace: 8 per matrix for matrices 0 and 1,
+// the iteration trace of those two at 16 .. 63, 8 per matrix for the rest from 64
+constexpr int EIG_FLAG_INTS = 64 + 8 * (EIG_MATS - 2);
+__host__ __device__ __forceinline__ int eig_flag_off(int which) { return which < 2 ? 8 * which : 64 + 8 * (which - 2); }
 
 // ---------------------------------------------------------------------------
 // multiprecision floats in global memory: header (sign, exp) + NWM limbs
@@ -829,11 +837,11 @@ __device__ void wg_fp_recip(const WgCtx& g0, FpRef z, const FpRef& x, FpRef t1, 
 
 __device__ __forceinline__ EigMat eig_mat(const EigArgs& ea, int which) {
   EigMat M;
-  M.n = ea.k - which;
+  M.n = ea.k - (which & 1);
   M.NWM = ea.NWM;
   M.hdr = ea.hdr + (size_t)which * ea.nums_per * 2;
   M.mant = ea.mant + (size_t)which * ea.nums_per * ea.NWM;
-  M.flags = ea.flags + which * 8;
+  M.flags = ea.flags + eig_flag_off(which);
   return M;
 }
 
@@ -1083,7 +1091,7 @@ __global__ __launch_bounds__(EIG2_THREADS) void k_e2_rq_final(EigArgs a, int whi
     const int bits = eig_bits(M, g.c);
     if (lane_id() == 0) {
       M.flags[3] = bits;
-      if (it < 24) a.flags[16 + which * 24 + it] = bits * 1000 + nw;
+      if (it < 24 && which < 2) a.flags[16 + which * 24 + it] = bits * 1000 + nw;
     }
   });
 }
@@ -1156,10 +1164,64 @@ __global__ __launch_bounds__(EIG2_THREADS) void k_e2_finish(EigArgs a, int which
   wg_fp_recip(g, num(M, ix_s(n, S_ONE)), num(M, ix_s(n, S_RES)), num(M, ix_w(n, 0, 1)), num(M, ix_w(n, 0, 2)));
 }
 
+// ---------------------------------------------------------------------------
+// The next eigenvalues (lambda_2, lambda_3 of Table 2) by deflation: matrix
+// `which` (2 or more) is matrix which - 2 less its converged eigenpair,
+// B' = B - mu y y^T / (y^T y).  For symmetric B this keeps every other eigenpair
+// and sends mu to 0, so the largest eigenvalue of B' is the next one of B; an
+// error e in the eigenvector y moves it by O(mu e^2) only.  Step 1 (one
+// workgroup): g_a = (mu / y^T y) y_a, into the destination's vector t.
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_defl_vec(EigArgs a, int which) {
+  const EigMat S = eig_mat(a, which - 2), D = eig_mat(a, which);
+  const int n = D.n;
+  const WgCtx g = wg_ctx(a.NWM, a.NWM - 1);
+  for (int ia = 0; ia < n; ++ia) wg_fp_mul(g, num(D, ix_T(n, ia, 0)), num(S, ix_y(n, ia)), num(S, ix_y(n, ia)));
+  FpRef den = num(D, ix_s(n, S_DEN)), inv = num(D, ix_s(n, S_T1)), f = num(D, ix_s(n, S_T2));
+  WG_WAVE0({
+    fp_set_zero(g.c, den);
+    wsync();
+    for (int ia = 0; ia < n; ++ia) fp_add(g.c, den, den, num(D, ix_T(n, ia, 0)), false);
+  });
+  wg_fp_recip(g, inv, den, num(D, ix_w(n, 0, 1)), num(D, ix_w(n, 0, 2)));
+  wg_fp_mul(g, f, num(S, ix_s(n, S_RES)), inv);
+  for (int ia = 0; ia < n; ++ia) wg_fp_mul(g, num(D, ix_t(n, ia)), f, num(S, ix_y(n, ia)));
+}
+
+// Step 2 (one workgroup per pair a >= b): B'_ab = B_ab - g_a y_b, copied to
+// B'_ba so that B' stays exactly symmetric
+__global__ __launch_bounds__(EIG2_THREADS) void k_e2_defl_mat(EigArgs a, int which) {
+  const EigMat S = eig_mat(a, which - 2), D = eig_mat(a, which);
+  const int n = D.n, p = blockIdx.x;
+  int ia = 0;
+  while ((ia + 1) * (ia + 2) / 2 <= p) ++ia;
+  const int ib = p - ia * (ia + 1) / 2;
+  if (ia >= n) return;
+  const WgCtx g = wg_ctx(a.NWM, a.NWM - 1);
+  FpRef T = num(D, ix_T(n, ia, ib));
+  wg_fp_mul(g, T, num(D, ix_t(n, ia)), num(S, ix_y(n, ib)));
+  WG_WAVE0({
+    fp_add(g.c, num(D, ix_B(n, ia, ib)), num(S, ix_B(n, ia, ib)), T, true);
+    wsync();
+    if (ia != ib) fp_copy(g.c, num(D, ix_B(n, ib, ia)), num(D, ix_B(n, ia, ib)));
+  });
+}
+
+// trunc_j = 1 / mu_j(k) - 1 / mu_j(k - 1) into the scalar T3 of matrix `which` (even)
+__global__ __launch_bounds__(64) void k_e2_diff(EigArgs a, int which) {
+  const EigMat A = eig_mat(a, which), B = eig_mat(a, which + 1);
+  extern __shared__ u32 lds2[];
+  FpCtx c;
+  c.NWM = a.NWM;
+  c.nw = a.NWM - 1;
+  c.la = lds2;
+  c.lb = lds2 + a.NWM + 8;
+  fp_add(c, num(A, ix_s(A.n, S_T3)), num(A, ix_s(A.n, S_ONE)), num(B, ix_s(B.n, S_ONE)), true);
+}
+
 namespace {
 int read_flag(const EigArgs& a, int which, int slot, hipStream_t st, hipError_t* err) {
   int v = 0;
-  *err = hipMemcpyAsync(&v, a.flags + which * 8 + slot, 4, hipMemcpyDeviceToHost, st);
+  *err = hipMemcpyAsync(&v, a.flags + eig_flag_off(which) + slot, 4, hipMemcpyDeviceToHost, st);
   if (*err == hipSuccess) *err = hipStreamSynchronize(st);
   return v;
 }
@@ -1173,12 +1235,14 @@ int read_flag(const EigArgs& a, int which, int slot, hipStream_t st, hipError_t*
 
 // one block (which = 0: k x k, 1: (k-1) x (k-1)); *conv = 0 if it did not converge
 static hipError_t eig2_block(const EigArgs& a, int which, hipStream_t st, int* conv) {
-  const int n = a.k - which, NWM = a.NWM, NWF = NWM - 1;
+  const int n = a.k - (which & 1), NWM = a.NWM, NWF = NWM - 1;
   const size_t lw = (size_t)2 * (NWM + 8) * 4;   // one wave's scratch
   const size_t lg = eig2_lds_bytes(NWM);
   *conv = 1;
-  hipLaunchKernelGGL(k_e2_init_b, dim3(n * n), dim3(64), lw, st, a, which);
-  E2CHK(hipGetLastError());
+  if (which < 2) {  // deflated matrices are written by k_e2_defl_mat
+    hipLaunchKernelGGL(k_e2_init_b, dim3(n * n), dim3(64), lw, st, a, which);
+    E2CHK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_e2_init, dim3(1), dim3(64), lw, st, a, which);
   E2CHK(hipGetLastError());
   if (n > 1) {
@@ -1270,38 +1334,80 @@ static hipError_t eig2_block(const EigArgs& a, int which, hipStream_t st, int* c
   return hipGetLastError();
 }
 
-// Host-driven eigen-step of both blocks; ENOCONV goes to the status word.
-hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream) {
-  const EigArgs a = eig_args(blk, dm, eig_ws, st);
-  const size_t lg = eig2_lds_bytes(a.NWM);
-  const void* big[] = {(const void*)k_e2_pivot, (const void*)k_e2_lcol, (const void*)k_e2_update,
-                       (const void*)k_e2_sweep, (const void*)k_e2_scale, (const void*)k_e2_rq_prod,
-                       (const void*)k_e2_rq_final, (const void*)k_e2_trial, (const void*)k_e2_finish};
+// dynamic LDS above the default for the workgroup kernels
+static hipError_t eig2_attrs(size_t lg) {
+  const void* big[] = {(const void*)k_e2_pivot,   (const void*)k_e2_lcol,     (const void*)k_e2_update,
+                       (const void*)k_e2_sweep,   (const void*)k_e2_scale,    (const void*)k_e2_rq_prod,
+                       (const void*)k_e2_rq_final, (const void*)k_e2_trial,   (const void*)k_e2_finish,
+                       (const void*)k_e2_defl_vec, (const void*)k_e2_defl_mat};
   if (lg > 65536)
     for (const void* f : big) E2CHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lg));
-  // a device error from an earlier stage stops here
+  return hipSuccess;
+}
+
+// *stop = the status word holds a device error from an earlier stage
+static hipError_t eig2_status(DevStatus* st, hipStream_t stream, bool* stop) {
   unsigned long long sw = 0;
   E2CHK(hipMemcpyAsync(&sw, st, 8, hipMemcpyDeviceToHost, stream));
   E2CHK(hipStreamSynchronize(stream));
-  if (sw) return hipSuccess;
+  *stop = sw != 0;
+  return hipSuccess;
+}
+
+static hipError_t eig2_noconv(DevStatus* st, int which, hipStream_t stream) {
+  const unsigned long long v = ((unsigned long long)HL_ENOCONV << 32) | (unsigned)which;
+  E2CHK(hipMemcpyAsync(st, &v, 8, hipMemcpyHostToDevice, stream));
+  return hipStreamSynchronize(stream);
+}
+
+// Host-driven eigen-step of both blocks; ENOCONV goes to the status word.
+hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream) {
+  const EigArgs a = eig_args(blk, dm, eig_ws, st);
+  E2CHK(eig2_attrs(eig2_lds_bytes(a.NWM)));
+  bool stop = false;
+  E2CHK(eig2_status(st, stream, &stop));
+  if (stop) return hipSuccess;
   for (int which = 0; which < (dm.k >= 2 ? 2 : 1); ++which) {
     int conv = 1;
     E2CHK(eig2_block(a, which, stream, &conv));
-    if (!conv) {
-      const unsigned long long v = ((unsigned long long)HL_ENOCONV << 32) | (unsigned)which;
-      E2CHK(hipMemcpyAsync(st, &v, 8, hipMemcpyHostToDevice, stream));
-      E2CHK(hipStreamSynchronize(stream));
-      return hipSuccess;
-    }
+    if (!conv) return eig2_noconv(st, which, stream);
   }
   hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (a.NWM + 8) * 4, stream, a);
   return hipGetLastError();
 }
 
+// The next `count` eigenvalues of both blocks by deflation (matrices 2 .. 2 count
+// + 1), after launch_eig_host on the same workspace; needs k >= count + 2 and
+// count <= EIG_MATS / 2 - 1 (checked by the caller).
+hipError_t launch_eig_next(const u32* blk, const Dims& dm, void* eig_ws, int count, DevStatus* st,
+                           hipStream_t stream) {
+  const EigArgs a = eig_args(blk, dm, eig_ws, st);
+  const size_t lg = eig2_lds_bytes(a.NWM);
+  E2CHK(eig2_attrs(lg));
+  bool stop = false;
+  E2CHK(eig2_status(st, stream, &stop));
+  if (stop) return hipSuccess;
+  for (int j = 1; j <= count; ++j) {
+    for (int h = 0; h < 2; ++h) {
+      const int which = 2 * j + h, n = dm.k - h;
+      hipLaunchKernelGGL(k_e2_defl_vec, dim3(1), dim3(EIG2_THREADS), lg, stream, a, which);
+      E2CHK(hipGetLastError());
+      hipLaunchKernelGGL(k_e2_defl_mat, dim3(n * (n + 1) / 2), dim3(EIG2_THREADS), lg, stream, a, which);
+      E2CHK(hipGetLastError());
+      int conv = 1;
+      E2CHK(eig2_block(a, which, stream, &conv));
+      if (!conv) return eig2_noconv(st, which, stream);
+    }
+    hipLaunchKernelGGL(k_e2_diff, dim3(1), dim3(64), (size_t)2 * (a.NWM + 8) * 4, stream, a, 2 * j);
+    E2CHK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
 size_t eig_ws_bytes(const Dims& dm) {
   const int NWM = dm.nl + 4;
   const size_t per = (size_t)eig_numbers(dm.k);
-  return 2 * per * (2 * 4 + (size_t)NWM * 4) + 256;
+  return EIG_MATS * per * (2 * 4 + (size_t)NWM * 4) + EIG_FLAG_INTS * 4;
 }
 
 // host: run the eigen-step on both blocks and read back the results
@@ -1314,8 +1420,8 @@ EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st) {
   a.NWM = dm.nl + 4;
   a.nums_per = (size_t)eig_numbers(dm.k);
   a.flags = (int*)eig_ws;
-  a.hdr = a.flags + 64;
-  a.mant = (u32*)(a.hdr + 2 * 2 * a.nums_per);
+  a.hdr = a.flags + EIG_FLAG_INTS;
+  a.mant = (u32*)(a.hdr + 2 * EIG_MATS * a.nums_per);
   a.st = st;
   return a;
 }
@@ -1356,8 +1462,8 @@ void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out
   const int NWM = dm.nl + 4;
   const size_t per = (size_t)eig_numbers(dm.k);
   int* flags = (int*)eig_ws;
-  int* hdr = flags + 64;
-  u32* mant = (u32*)(hdr + 2 * 2 * per);
+  int* hdr = flags + EIG_FLAG_INTS;
+  u32* mant = (u32*)(hdr + 2 * EIG_MATS * per);
   *hdr_out = hdr + 2 * ix_y(dm.k, 0);
   *mant_out = mant + (size_t)ix_y(dm.k, 0) * NWM;
 }
@@ -1367,8 +1473,8 @@ void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32
   const int NWM = dm.nl + 4;
   const size_t per = (size_t)eig_numbers(dm.k);
   int* flags = (int*)eig_ws;
-  int* hdr = flags + 64;
-  u32* mant = (u32*)(hdr + 2 * 2 * per);
+  int* hdr = flags + EIG_FLAG_INTS;
+  u32* mant = (u32*)(hdr + 2 * EIG_MATS * per);
   // which: 0 -> 1/lambda_max(k), 1 -> 1/lambda_max(k-1), 2 -> difference, 3 -> iteration flags
   const int n = which == 1 ? dm.k - 1 : dm.k;
   const int blkidx = which == 1 ? 1 : 0;
@@ -1376,5 +1482,22 @@ void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32
   *hdr_out = hdr + (size_t)blkidx * per * 2 + 2 * idx;
   *mant_out = mant + ((size_t)blkidx * per + idx) * NWM;
 }
+
+// results of the deflated matrices: 1 / mu of matrix `mat`, or (diff, even
+// mat) the difference left by k_e2_diff
+void eig_next_refs(const Dims& dm, void* eig_ws, int mat, bool diff, int** hdr_out, u32** mant_out) {
+  const int NWM = dm.nl + 4;
+  const size_t per = (size_t)eig_numbers(dm.k);
+  int* flags = (int*)eig_ws;
+  int* hdr = flags + EIG_FLAG_INTS;
+  u32* mant = (u32*)(hdr + 2 * EIG_MATS * per);
+  const int n = dm.k - (mat & 1);
+  const int idx = diff ? ix_s(n, S_T3) : ix_s(n, S_ONE);
+  *hdr_out = hdr + (size_t)mat * per * 2 + 2 * idx;
+  *mant_out = mant + ((size_t)mat * per + idx) * NWM;
+}
+
+// iterations used on matrix `mat`
+int* eig_iter_ref(void* eig_ws, int mat) { return (int*)eig_ws + eig_flag_off(mat) + 1; }
 
 }  // namespace hl

@@ -5,7 +5,8 @@
 * exact rational LDL^T for tiny N (beta = 1/2, irrational-free but with
   non-integer factors), within the contract's rounding bound;
 * the brute-force characteristic polynomial for N <= 8 (sympy's independent
-  routine and the Sturm-isolated smallest root);
+  routine and the Sturm-isolated smallest root, and the second and third
+  roots for lambda_2 and lambda_3);
 * the values printed in Table 2 at N = 500;
 * agreement at doubled precision;
 * interlacing (trunc <= 0), positivity of pivots, the error paths.
@@ -120,6 +121,81 @@ def test_lambda1_against_characteristic_polynomial(beta, N):
         assert abs(ev.lam1 / ref - 1) < mpmath.mpf(10) ** -90
 
 
+def _polymul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def test_kth_root_known_roots():
+    roots = [Fraction(1, 3), Fraction(2), Fraction(7, 2), Fraction(10)]
+    c = [Fraction(1)]
+    for r in roots:
+        c = _polymul(c, [-r, Fraction(1)])   # coefficients low to high
+    for j, r in enumerate(roots, start=1):
+        got = X.kth_root(c, j, Fraction(16), bits=200)
+        assert abs(got - r) <= Fraction(16, 2 ** 199)
+    assert X.kth_root(c, 1, Fraction(16), bits=200) == X.smallest_root(c, Fraction(16), bits=200)
+    with pytest.raises(ValueError):
+        X.kth_root(c, 4, Fraction(5))
+
+
+@pytest.mark.parametrize("beta", [Fraction(1, 2), Fraction(1), Fraction(1, 3)])
+@pytest.mark.parametrize("N", [4, 8])
+def test_next_eigenvalues_against_characteristic_polynomial(beta, N):
+    # k = N: the block is all of H^-1, so lambda_2 and lambda_3 are the second
+    # and third roots of the characteristic polynomial, isolated exactly
+    mu = _mu(beta, N)
+    H = X.hankel([m.to_fraction() for m in mu], N)
+    c = X.charpoly(H)
+    tr = sum(H[i][i] for i in range(N))
+    P = 1024
+    f, sv, bl, ev = C.lambda_min(mu, N, N, P, E=1)
+    nxt = C.eigen_next(bl, 2, P=P)
+    assert [r.j for r in nxt] == [2, 3]
+    with mpmath.workprec(600):
+        for r in nxt:
+            root = X.kth_root(c, r.j, tr, bits=400 + int(tr).bit_length())
+            ref = mpmath.mpf(root.numerator) / root.denominator
+            assert abs(r.lam / ref - 1) < mpmath.mpf(10) ** -90
+            assert r.trunc <= 0
+        assert ev.lam1 < nxt[0].lam < nxt[1].lam
+
+
+@pytest.mark.parametrize("mutation", ["ascending", "off_by_one"])
+def test_planted_eigen_next_mistakes_are_caught(monkeypatch, mutation):
+    # the real _eigs_desc passes the characteristic-polynomial pin; an ordering
+    # or index mistake in it must not
+    N, P = 6, 1024
+    mu = _mu(Fraction(1, 2), N)
+    H = X.hankel([m.to_fraction() for m in mu], N)
+    c = X.charpoly(H)
+    tr = sum(H[i][i] for i in range(N))
+    root = X.kth_root(c, 2, tr, bits=400 + int(tr).bit_length())
+    _, _, bl, _ = C.lambda_min(mu, N, N, P, E=1)
+    real = C._eigs_desc
+    if mutation == "ascending":
+        monkeypatch.setattr(C, "_eigs_desc", lambda m, p: real(m, p)[::-1])
+    else:
+        monkeypatch.setattr(C, "_eigs_desc", lambda m, p: real(m, p)[1:] + real(m, p)[:1])
+    lam2 = C.eigen_next(bl, 1, P=P)[0].lam
+    with mpmath.workprec(600):
+        ref = mpmath.mpf(root.numerator) / root.denominator
+        assert abs(lam2 / ref - 1) > mpmath.mpf(10) ** -10
+
+
+def test_next_eigenvalues_bad_count():
+    mu = _mu(Fraction(1, 2), 16)
+    _, _, bl, _ = C.lambda_min(mu, 16, 3, 1024, 16)
+    C.eigen_next(bl, 1, P=1024)
+    with pytest.raises(C.ContractError):
+        C.eigen_next(bl, 2, P=1024)       # the 2 x 2 leading block has no third eigenvalue
+    with pytest.raises(C.ContractError):
+        C.eigen_next(bl, 0, P=1024)
+
+
 # ------------------------------------------------------------------ doubled precision, full-matrix eigenvalues
 
 def test_doubled_precision_agreement_c1():
@@ -151,6 +227,32 @@ def test_truncation_against_full_matrix_eigenvalue():
         assert err8 < abs(ev8.trunc) * 10     # the k-1 difference bounds the k error
 
 
+def test_next_truncation_against_full_matrix_eigenvalues():
+    # lambda_2, lambda_3 of H_32 by a dense eigen-solver on the exact matrix:
+    # k = N reproduces them; k = 8 can only raise them (Poincare separation:
+    # the j-th eigenvalue of a compression of H^-1 is at most that of H^-1)
+    N = 32
+    mu = _mu(Fraction(1, 2), N)
+    with mpmath.workprec(1500):
+        M = mpmath.matrix(N, N)
+        for i in range(N):
+            for j in range(N):
+                M[i, j] = mpmath.mpf(mu[i + j].M)
+        full = sorted(mpmath.eigsy(M, eigvals_only=True)[i] for i in range(N))
+    _, _, bl_full, _ = C.lambda_min(mu, N, N, 2048, 16)
+    _, _, bl8, _ = C.lambda_min(mu, N, 8, 2048, 16)
+    nf = C.eigen_next(bl_full, 2, P=2048)
+    n8 = C.eigen_next(bl8, 2, P=2048)
+    with mpmath.workprec(1500):
+        for r_full, r8 in zip(nf, n8):
+            ref = full[r_full.j - 1]
+            assert abs(r_full.lam / ref - 1) < mpmath.mpf(10) ** -100
+            err = r8.lam - ref
+            assert err >= 0
+            assert r8.trunc <= 0
+            assert err < abs(r8.trunc) * 10
+
+
 # ------------------------------------------------------------------ Table 2
 
 @pytest.mark.slow
@@ -159,9 +261,18 @@ def test_table2_n500():
     # truncation error -6.52e-16 (k = 8; the paper reports 16 digits from a
     # double-precision eigen-solve, so 1e-15 relative is the comparison bar).
     mu = _mu(Fraction(1, 2), 500)
-    _, _, _, ev = C.lambda_min(mu, 500, 8, 1280, E=1)
+    _, _, bl, ev = C.lambda_min(mu, 500, 8, 1280, E=1)
     assert abs(float(ev.lam1) / 0.1204653471966412 - 1) < 1e-15
     assert -7.5e-16 < float(ev.trunc) < -5.5e-16
+    # lambda_2 and lambda_3 (Table 2's other columns) within the error of the
+    # paper's double-precision eigen-solve (tests/golden_table2.paper_error)
+    from golden_table2 import paper_error, table2
+    row = table2()[500]
+    for r in C.eigen_next(bl, 2, P=1280):
+        e_lam, e_tr = paper_error(row, r.j)
+        assert abs(float(r.lam) - (row.lambda2, row.lambda3)[r.j - 2]) <= e_lam
+        assert float(r.trunc) < 0
+        assert abs(float(r.trunc) - (row.trunc2, row.trunc3)[r.j - 2]) <= e_tr
 
 
 # ------------------------------------------------------------------ invariants and error paths

@@ -6,13 +6,15 @@ negative, by Cauchy interlacing of the k-1 block inside the k block).
 GPU: the whole path (moments -> LDL^T -> first k columns of L^-1 -> block of
 H^-1 -> eigen-step) at N = 500 and N = 1000, k = 8, reproduces the printed
 lambda_1 to the 16 printed digits and the truncation estimate within the
-double-precision error of the paper's own difference; N >= 1500 needs more than this library's
+double-precision error of the paper's own difference, and lambda_2, lambda_3
+with their estimates within the error of the paper's double-precision
+eigen-solve (golden_table2.paper_error); N >= 1500 needs more than this library's
 largest precision (57344 bits) under its scaled fixed-point contract."""
 from fractions import Fraction
 
 import pytest
 
-from golden_table2 import table2
+from golden_table2 import paper_error, table2
 
 
 def test_fixture_orderings():
@@ -49,3 +51,11 @@ def test_lambda1_reproduces_table2(N):
     # so it carries an absolute error of that order (here it is exact)
     assert res["trunc"] < 0
     assert abs(res["trunc"] - row.trunc1) <= 2e-15 * row.lambda1
+    for g in ctx().lambda_next(fac, 2, want_mant=False):
+        e_lam, e_tr = paper_error(row, g["j"])
+        lam_p = (row.lambda2, row.lambda3)[g["j"] - 2]
+        tr_p = (row.trunc2, row.trunc3)[g["j"] - 2]
+        say("  lambda%d" % g["j"], repr(g["lambda"]), "paper", lam_p, "trunc", g["trunc"], "paper", tr_p)
+        assert abs(g["lambda"] - lam_p) <= e_lam
+        assert g["trunc"] < 0
+        assert abs(g["trunc"] - tr_p) <= e_tr
