@@ -16,6 +16,8 @@ contract  the fixed-point contract step by step, in Python integers:
           and (``eigen_next``) the next ones, lambda_2 and lambda_3 of Table 2.
 exact     exact rational arithmetic for tiny N: LDL^T, L^-1, H^-1 block, and the
           characteristic polynomial of H_N for brute-force eigenvalues.
+fit       the weighted straight-line fit of Section 6 (leading exponent) from its
+          closed form, with Student-t intervals.
 adjoint   the derivative of lambda_1 with respect to the moments (the adjoint
           vector mubar) and its contraction with d mu / d beta, from the
           definition, in mpmath.

@@ -65,7 +65,7 @@ def run_at(ctx: Context, beta, N: int, k: int, P: int, E: int = 1, form: str = "
         r1 = ctx.eigen(fac, want_mant=False)
         t_eig = ctx.timing()["ms"][4]
         te = time.perf_counter()
-        nxt = ctx.lambda_next(fac, count, want_mant=False)
+        nxt = ctx.lambda_next(fac, count, want_mant=False) if count > 0 else []
         torch.cuda.synchronize()
         t_next = time.perf_counter() - te
     except L.HLError as e:
@@ -124,7 +124,7 @@ def main(argv: Optional[List[str]] = None) -> int:
     ap.add_argument("--N", type=int, nargs="+", default=[500, 1000, 1500, 2000, 2500, 3000, 3500, 4000, 4500])
     ap.add_argument("--beta", default="1/2")
     ap.add_argument("--k", type=int, default=8)
-    ap.add_argument("--count", type=int, default=2, help="further eigenvalues beyond lambda_1 (1 or 2)")
+    ap.add_argument("--count", type=int, default=2, help="further eigenvalues beyond lambda_1 (0, 1 or 2)")
     ap.add_argument("--P-start", type=int, default=1024,
                     help="first precision of the first N; each later N starts one step below the previous result")
     ap.add_argument("--step", type=int, default=1024)
