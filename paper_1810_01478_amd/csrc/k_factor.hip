@@ -171,8 +171,11 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   long p = 30;
   int ny = 1;
   while (p < pf) {
-    long pn = 2 * p - 12;
-    if (pn > pf) pn = pf;
+    // precisions planned back from pf, each step at most doubling (less 12
+    // guard bits): pn is the smallest of pf, c(pf), c(c(pf)), ... above p,
+    // c(t) = ceil((t + 12) / 2), so the last step starts near pf / 2
+    long pn = pf;
+    while ((pn + 13) / 2 > p) pn = (pn + 13) / 2;
     const long q = pn + 8;
     const int nq = (int)(q / 32) + 2;
     // dq = floor(D * 2^(q - LD))

@@ -108,26 +108,52 @@ __device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, 
   __syncthreads();
   // the MFMA row of this lane's Toeplitz operand and its output digit
   const int tm = 16 * ((n >> 2) & 1) + 4 * (n >> 3) + (n & 3);
+  // a digits 32 J + tm - 16 h - x, x = 0..15, are the reversed bytes y0 .. y0 + 15
+  // with y0 = yb - 32 J: the 16-byte alignment offset is the same for every J
+  const int yb = WM_PAD + SA - 1 - tm + 16 * h;
+  const int abase = yb & ~15, aw = (yb & 15) >> 2, ab = yb & 3;
+  const wm_v4i zero4 = (wm_v4i){0, 0, 0, 0};
   for (int set = w; set < nsets; set += nwv) {
     const int O = 32 * set;
-    wm_v16i acc = (wm_v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     // window J holds a digits 32 J - 31 .. 32 J + 31, so J runs to nJa
     int J0 = O - nJb + 1;
     if (J0 < 0) J0 = 0;
     int J1 = O + 31;
     if (J1 > nJa) J1 = nJa;
-    for (int J = J0; J <= J1; ++J) {
-      // a digits 32 J + tm - 16 h - x, x = 0..15: reversed bytes y0 .. y0 + 15
-      const int y0 = WM_PAD + SA - 1 - 32 * J - tm + 16 * h;
-      const int base = y0 & ~15, off = y0 & 15;
-      const wm_v4i lo = *(const wm_v4i*)(ar + base);
-      const wm_v4i hi = *(const wm_v4i*)(ar + base + 16);
-      const wm_v4i av = wm_window(lo, hi, off >> 2, off & 3);
+    // raw operands of window J: the two 16-byte pieces of a's reversed digits
+    // and b's chunk (zero outside b).  Beyond J1 they are never used, so the a
+    // pieces are read at J1 and only the b predicate keeps its true index.
+    auto load = [&](int J, wm_v4i& lo, wm_v4i& hi, wm_v4i& bv) {
+      const int Ja = J <= J1 ? J : J1;
+      lo = *(const wm_v4i*)(ar + abase - 32 * Ja);
+      hi = *(const wm_v4i*)(ar + abase - 32 * Ja + 16);
       const int c = O + n - J;
-      wm_v4i bv = (wm_v4i){0, 0, 0, 0};
+      bv = zero4;
       if (c >= 0 && c < nJb) bv = *(const wm_v4i*)(bf + 32 * c + 16 * h);
-      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc, 0, 0, 0);
+    };
+    // two windows per half-step into two accumulators; two register sets (A, B)
+    // take turns, so the next pair's operands load while this pair's MFMAs
+    // issue.  acc0 + acc1 is the same exact sum as one accumulator.
+    wm_v16i acc0 = (wm_v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    wm_v16i acc1 = acc0;
+    wm_v4i la0, ha0, ba0, la1, ha1, ba1;  // set A: windows J, J + 1
+    wm_v4i lb0, hb0, bb0, lb1, hb1, bb1;  // set B: windows J + 2, J + 3
+    load(J0, la0, ha0, ba0);
+    load(J0 + 1, la1, ha1, ba1);
+    for (int J = J0; J <= J1; J += 4) {
+      load(J + 2, lb0, hb0, bb0);
+      load(J + 3, lb1, hb1, bb1);
+      acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wm_window(la0, ha0, aw, ab), ba0, acc0, 0, 0, 0);
+      if (J + 1 <= J1)
+        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wm_window(la1, ha1, aw, ab), ba1, acc1, 0, 0, 0);
+      if (J + 2 > J1) break;
+      load(J + 4, la0, ha0, ba0);
+      load(J + 5, la1, ha1, ba1);
+      acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wm_window(lb0, hb0, aw, ab), bb0, acc0, 0, 0, 0);
+      if (J + 3 <= J1)
+        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wm_window(lb1, hb1, aw, ab), bb1, acc1, 0, 0, 0);
     }
+    const wm_v16i acc = acc0 + acc1;
     // lane: output block O + n, digits 16 h .. 16 h + 15 = chunk 2 (O + n) + h
     i64 dd[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -144,9 +170,9 @@ __device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, 
   // positive carries plus the complement of the negative ones, plus one
   if (w == 0) {
     const int nch = 64 * nsets;
-    u32 carry = 0;
-    for (int base = 0; base < nout; base += WAVE) {
-      const int p = base + l;
+    // position value of limb p (reads the scratch only, never out, so the next
+    // round's value is formed before this round's limb is stored)
+    auto value = [&](int p) -> u64 {
       u64 v = 0;
       if (p < nout) {
         v = p < 4 * nch ? olo[p] : 0u;
@@ -161,6 +187,14 @@ __device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, 
         v += (u64)pos + (u64)(~neg);
         if (p == 0) v += 1;
       }
+      return v;
+    };
+    u32 carry = 0;
+    u64 vn = value(l);
+    for (int base = 0; base < nout; base += WAVE) {
+      const int p = base + l;
+      const u64 v = vn;
+      vn = value(p + WAVE);
       const u32 limb = w_resolve(v, carry);
       if (p < nout) out[p] = limb;
     }
