@@ -94,33 +94,20 @@ struct PivotOut {
   int ok;
 };
 
-__device__ void sub_from_pow2(long e, const u32* T, int nT, u32* out, int n) {
-  // out = 2^e - T (mod 2^(32n)), T zero-extended from nT
-  u32 carry = 1;
-  for (int base = 0; base < n; base += WAVE) {
-    const int p = base + lane_id();
-    u64 v = 0;
-    if (p < n) {
-      u32 tp = p < nT ? T[p] : 0u;
-      v = (u64)(~tp);
-      if ((long)p == (e >> 5)) v += (u64)1 << (e & 31);
-    }
-    const u32 limb = w_resolve(v, carry);
-    if (p < n) out[p] = limb;
-  }
+// out = 2^e - T (mod 2^(32n)), T zero-extended from nT; out may be T.  All
+// threads of the workgroup; rip as for wg_resolve.
+__device__ void wg_sub_from_pow2(long e, const u32* T, int nT, u32* out, int n, u32* rip) {
+  wg_resolve(n, [=](int p) -> u64 {
+    u64 v = (u64)(~(p < nT ? T[p] : 0u)) + (p == 0 ? 1u : 0u);
+    if ((long)p == (e >> 5)) v += (u64)1 << (e & 31);
+    return v;
+  }, out, rip);
 }
 
 // x += d (two's complement add of a sign-extended small signed value), n limbs
-__device__ void add_i32(u32* x, int n, int d) {
-  u32 carry = 0;
+__device__ void wg_add_i32(u32* x, int n, int d, u32* rip) {
   const u32 ext = d < 0 ? 0xffffffffu : 0u;
-  for (int base = 0; base < n; base += WAVE) {
-    const int p = base + lane_id();
-    u64 v = 0;
-    if (p < n) v = (u64)x[p] + (p == 0 ? (u32)d : ext);
-    const u32 limb = w_resolve(v, carry);
-    if (p < n) x[p] = limb;
-  }
+  wg_resolve(n, [=](int p) -> u64 { return (u64)x[p] + (p == 0 ? (u32)d : ext); }, x, rip);
 }
 
 // Product for the reciprocal's steps (non-negative operands): the one-workgroup
@@ -136,9 +123,8 @@ __device__ __forceinline__ void pv_mul(const u32* a, int na, const u32* b, int n
 
 __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_omega, u32* lds,
                                 int nl) {
-  // every thread of the block calls this: the products use all waves, the
-  // other steps run on wave 0 between barriers
-  const bool w0 = wave_id() == 0;
+  // every thread of the block calls this and every step runs on all waves:
+  // the products, the shifts, and the carry chains (wg_resolve)
   PivotOut res{0, 1};
   const int NB = nl + 8;
   u32* D = lds;            // d~
@@ -148,20 +134,20 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   u32* Z = dq + NB;
   u32* T = Z + NB;         // 2 NB
   u32* T2 = T + 2 * NB;    // 2 NB
-  u32* colbuf = T2 + 2 * NB;  // 6 NB: scratch of the products
+  u32* colbuf = T2 + 2 * NB;  // 6 NB: scratch of the products, and between them of the carry chains
+  u32* rip = colbuf;
   const size_t cap = (size_t)6 * NB * 4;
   const int Ld = w_bitlen(d, nw);
   const int h = Ld / 2;
   res.h = h;
   const long m = Ld - (long)P - 64 > 0 ? Ld - (long)P - 64 : 0;
   const int nd = nl + 2;
-  if (w0) w_shift_right(d, nw, m, D, nd);
-  __syncthreads();
+  wg_shift_right(d, nw, m, D, nd);
   const int LD = w_bitlen(D, nd);
   const long e = 2L * h + P - m;
   const long pf = e - LD + 40;   // final precision of y
   // initial 30-bit estimate from the top 32 bits of D
-  if (w0) {
+  if (wave_id() == 0) {
     const u32 dtop = LD >= 32 ? limb_shr(D, nd, LD - 32, 0) : limb_shl(D, nd, 32 - LD, 0);
     const u64 y0 = ((u64)1 << 62) / (u64)dtop;
     if (lane_id() == 0) Y[0] = (u32)y0;
@@ -179,19 +165,16 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
     const long q = pn + 8;
     const int nq = (int)(q / 32) + 2;
     // dq = floor(D * 2^(q - LD))
-    if (w0) w_shift_right(D, nd, LD - q, dq, nq);
-    __syncthreads();
+    wg_shift_right(D, nd, LD - q, dq, nq);
     // T = dq * Y
     const int nT = nq + ny;
     pv_mul(dq, nq, Y, ny, T, nT, colbuf, cap);
     // E = 2^(p+q) - T  (two's complement over nT + 1 limbs)
     const int nE = nT + 1;
-    if (w0) sub_from_pow2(p + q, T, nT, T, nE);
-    __syncthreads();
+    wg_sub_from_pow2(p + q, T, nT, T, nE, rip);
     const bool neg = (T[nE - 1] >> 31) != 0;
     __syncthreads();
-    if (w0 && neg) w_neg(T, nE);
-    __syncthreads();
+    if (neg) wg_neg(T, nE, rip);
     // T2 = Y * |E|, then shifted
     int ne = (w_bitlen(T, nE) + 31) / 32;
     if (ne < 1) ne = 1;
@@ -203,35 +186,27 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
     pv_mul(Y, ny, T, ne, T2, nT2, colbuf, cap);
     const int nyn = (int)((pn + 2) / 32) + 2;
     // Yn = Y << (pn - p);   Z = T2 >> (2p + q - pn)
-    if (w0) {
-      w_shift_right(Y, ny, -(pn - p), Yn, nyn);
-      w_shift_right(T2, nT2, 2 * p + q - pn, Z, nyn);
+    wg_shift_right(Y, ny, -(pn - p), Yn, nyn);
+    wg_shift_right(T2, nT2, 2 * p + q - pn, Z, nyn);
+    if (neg) {
+      wg_sub(Yn, Z, Y, nyn, rip);
+    } else {
+      wg_add(Yn, nyn, Z, nyn, Y, nyn, rip);
     }
-    __syncthreads();
-    if (w0) {
-      if (neg) {
-        w_sub(Yn, Z, Y, nyn);
-      } else {
-        w_add(Yn, nyn, Z, nyn, Y, nyn);
-      }
-      for (int j = nyn + lane_id(); j < NB; j += WAVE) Y[j] = 0;
-    }
+    for (int j = nyn + threadIdx.x; j < NB; j += blockDim.x) Y[j] = 0;
     __syncthreads();
     ny = nyn;
     p = pn;
   }
   // Z = Y >> (pf - (e - LD))  ~ 2^e / D
   const int nz = nl + 3;
-  if (w0) w_shift_right(Y, ny, pf - (e - LD), Z, nz);
-  __syncthreads();
+  wg_shift_right(Y, ny, pf - (e - LD), Z, nz);
   // R = 2^e - Z D, exact, over nR limbs
   const int nR = (int)(e / 32) + 3;
   pv_mul(Z, nz, D, nd, T, nR, colbuf, cap);
-  if (w0) {
-    sub_from_pow2(e, T, nR, T, nR);
-    // T2 = D zero-extended to nR (and zero up to NB for the comparison below)
-    for (int j = lane_id(); j < (nR > NB ? nR : NB); j += WAVE) T2[j] = j < nd ? D[j] : 0u;
-  }
+  wg_sub_from_pow2(e, T, nR, T, nR, rip);
+  // T2 = D zero-extended to nR (and zero up to NB for the comparison below)
+  for (int j = threadIdx.x; j < (nR > NB ? nR : NB); j += blockDim.x) T2[j] = j < nd ? D[j] : 0u;
   __syncthreads();
   int guard = 0;
   while (true) {
@@ -239,33 +214,25 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
     const int cmp = rneg ? 0 : w_cmp(T, T2, nR);
     __syncthreads();
     if (rneg) {
-      if (w0) {
-        add_i32(Z, nz, -1);
-        w_add(T, nR, T2, nR, T, nR);
-      }
+      wg_add_i32(Z, nz, -1, rip);
+      wg_add(T, nR, T2, nR, T, nR, rip);
     } else if (cmp >= 0) {
-      if (w0) {
-        add_i32(Z, nz, 1);
-        w_sub(T, T2, T, nR);
-      }
+      wg_add_i32(Z, nz, 1, rip);
+      wg_sub(T, T2, T, nR, rip);
     } else {
       break;
     }
-    __syncthreads();
     if (++guard > 16) {
       res.ok = 0;
       break;
     }
   }
   // omega = Z + [2R >= D]
-  if (w0) w_shift_right(T, nR, -1, Yn, nR > NB ? NB : nR);  // 2R fits: R < D < 2^(P+64)
-  __syncthreads();
+  wg_shift_right(T, nR, -1, Yn, nR > NB ? NB : nR);  // 2R fits: R < D < 2^(P+64)
   const bool up = w_cmp(Yn, T2, nd + 1) >= 0;
   __syncthreads();
-  if (w0) {
-    if (up) add_i32(Z, nz, 1);
-    for (int j = lane_id(); j < n_omega; j += WAVE) omega[j] = j < nz ? Z[j] : 0u;
-  }
+  if (up) wg_add_i32(Z, nz, 1, rip);
+  for (int j = threadIdx.x; j < n_omega; j += blockDim.x) omega[j] = j < nz ? Z[j] : 0u;
   __syncthreads();
   return res;
 }

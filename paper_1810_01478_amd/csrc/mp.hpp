@@ -228,6 +228,80 @@ __device__ __forceinline__ void w_add_word(u32* x, int n, int pos, u32 v) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Carry resolution by a whole workgroup.  out[p] = limb p of
+// sum_{p < n} v(p) 2^(32 p) mod 2^(32 n), every v(p) < 2^64.  Limb p receives
+// the low word of v(p), the high word of v(p - 1) and a one-bit ripple from
+// below; only the ripple crosses a 64-limb chunk, so the chunks are spread over
+// the waves: pass 1 records each chunk's carry-out for a ripple-in of 0 and of 1
+// and the high word entering it, pass 2 (wave 0) chains the ripples with one
+// ballot per 64 chunks, pass 3 writes the limbs.  v(p) may read out[p] (each
+// chunk reads its own limbs before writing them) but no other limb of out.
+// rip: 2 ceil(n / 64) words of LDS.  All threads call it; it ends with a barrier.
+template <class V>
+__device__ __forceinline__ void wg_resolve(int n, V value, u32* out, u32* rip) {
+  const int l = lane_id(), w = wave_id(), nwv = blockDim.x / WAVE;
+  const int nq = (n + WAVE - 1) / WAVE;
+  // the generate and propagate masks of chunk k (ripple in excluded)
+  auto masks = [&](int k, u32 hin, u64& A, u64& G, u64& s2) {
+    const int p = WAVE * k + l;
+    const u64 v = p < n ? value(p) : 0ull;
+    u32 cprev = shfl_up_u32((u32)(v >> 32), 1);
+    if (l == 0) cprev = hin;
+    s2 = (u64)(u32)v + cprev;
+    G = ballot64((s2 >> 32) != 0);
+    A = G | ballot64((u32)s2 == 0xffffffffu);
+  };
+  for (int k = w; k < nq; k += nwv) {
+    u32 hin = 0;
+    if (l == 0 && k > 0) hin = (u32)(value(WAVE * k - 1) >> 32);
+    hin = shfl_u32(hin, 0);
+    u64 A, G, s2;
+    masks(k, hin, A, G, s2);
+    const u64 S1 = A + G;
+    const u32 g = S1 < A ? 1u : 0u;                  // carry out with ripple 0
+    const u32 t = (g || S1 == ~0ull) ? 1u : 0u;      // with ripple 1
+    if (l == 0) {
+      rip[2 * k] = g | (t << 1);
+      rip[2 * k + 1] = hin;
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    u32 cg = 0;
+    for (int base = 0; base < nq; base += WAVE) {
+      const int k = base + l;
+      const u32 f = k < nq ? rip[2 * k] : 0u;
+      const u64 G2 = ballot64(f & 1u), A2 = ballot64((f >> 1) & 1u);
+      const u64 S1 = A2 + G2, S = S1 + cg;
+      const u64 cv = S ^ A2 ^ G2;   // ripple into each chunk
+      if (k < nq) rip[2 * k] = f | ((u32)((cv >> l) & 1ull) << 2);
+      cg = (S1 < A2 || (cg && S == 0)) ? 1u : 0u;
+    }
+  }
+  __syncthreads();
+  for (int k = w; k < nq; k += nwv) {
+    const u32 c = (rip[2 * k] >> 2) & 1u;
+    u64 A, G, s2;
+    masks(k, rip[2 * k + 1], A, G, s2);
+    const u64 cin = (A + G + c) ^ A ^ G;
+    const int p = WAVE * k + l;
+    if (p < n) out[p] = (u32)s2 + (u32)((cin >> l) & 1ull);
+  }
+  __syncthreads();
+}
+
+// workgroup forms of the carry loops above (same results); rip as for wg_resolve
+__device__ __forceinline__ void wg_add(const u32* a, int na, const u32* b, int nb, u32* out, int n, u32* rip) {
+  wg_resolve(n, [=](int p) -> u64 { return (u64)(p < na ? a[p] : 0u) + (u64)(p < nb ? b[p] : 0u); }, out, rip);
+}
+__device__ __forceinline__ void wg_sub(const u32* a, const u32* b, u32* out, int n, u32* rip) {
+  wg_resolve(n, [=](int p) -> u64 { return (u64)a[p] + (u64)(~b[p]) + (p == 0 ? 1u : 0u); }, out, rip);
+}
+__device__ __forceinline__ void wg_neg(u32* x, int n, u32* rip) {
+  wg_resolve(n, [=](int p) -> u64 { return (u64)(~x[p]) + (p == 0 ? 1u : 0u); }, x, rip);
+}
+
 // Limb j of (x >> s) for x of nx limbs (logical shift, zero fill), s >= 0.
 __device__ __forceinline__ u32 limb_shr(const u32* x, int nx, long s, int j) {
   const long q = s >> 5;
@@ -253,6 +327,12 @@ __device__ __forceinline__ u32 limb_shl(const u32* x, int nx, long s, int j) {
 __device__ __forceinline__ void w_shift_right(const u32* src, int ns, long s, u32* dst, int nd) {
   for (int j = lane_id(); j < nd; j += WAVE)
     dst[j] = s >= 0 ? limb_shr(src, ns, s, j) : limb_shl(src, ns, -s, j);
+}
+// the same by every thread of the workgroup; ends with a barrier
+__device__ __forceinline__ void wg_shift_right(const u32* src, int ns, long s, u32* dst, int nd) {
+  for (int j = threadIdx.x; j < nd; j += blockDim.x)
+    dst[j] = s >= 0 ? limb_shr(src, ns, s, j) : limb_shl(src, ns, -s, j);
+  __syncthreads();
 }
 
 // number of significant bits of x (0 for x == 0)

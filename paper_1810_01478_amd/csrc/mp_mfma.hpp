@@ -168,33 +168,34 @@ __device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, 
   __syncthreads();
   // out = sum_ch (olo_ch + ocw_ch 2^128) 2^(128 ch): the chunk limbs plus the
   // positive carries plus the complement of the negative ones, plus one
+  const int nch = 64 * nsets;
+  auto value = [=](int p) -> u64 {
+    u64 v = p < 4 * nch ? olo[p] : 0u;
+    u32 pos = 0, neg = 0;
+    const int c = (p >> 2) - 1, j = p & 3;
+    if (c >= 0 && c < nch && j < 2) {
+      const i64 cw = ocw[c];
+      const u64 m = cw < 0 ? (u64)(-cw) : (u64)cw;
+      const u32 word = (u32)(m >> (32 * j));
+      if (cw < 0) neg = word; else pos = word;
+    }
+    v += (u64)pos + (u64)(~neg);
+    if (p == 0) v += 1;
+    return v;
+  };
+  // resolved by the whole workgroup, the digit strings (no longer needed) holding
+  // the ripple table; one wave if they are too short for it
+  if ((size_t)8 * ((nout + WAVE - 1) / WAVE) <= (size_t)2 * WM_PAD + 32 * (nJa + nJb)) {
+    wg_resolve(nout, value, out, (u32*)ar);
+    return;
+  }
   if (w == 0) {
-    const int nch = 64 * nsets;
-    // position value of limb p (reads the scratch only, never out, so the next
-    // round's value is formed before this round's limb is stored)
-    auto value = [&](int p) -> u64 {
-      u64 v = 0;
-      if (p < nout) {
-        v = p < 4 * nch ? olo[p] : 0u;
-        u32 pos = 0, neg = 0;
-        const int c = (p >> 2) - 1, j = p & 3;
-        if (c >= 0 && c < nch && j < 2) {
-          const i64 cw = ocw[c];
-          const u64 m = cw < 0 ? (u64)(-cw) : (u64)cw;
-          const u32 word = (u32)(m >> (32 * j));
-          if (cw < 0) neg = word; else pos = word;
-        }
-        v += (u64)pos + (u64)(~neg);
-        if (p == 0) v += 1;
-      }
-      return v;
-    };
     u32 carry = 0;
     u64 vn = value(l);
     for (int base = 0; base < nout; base += WAVE) {
       const int p = base + l;
       const u64 v = vn;
-      vn = value(p + WAVE);
+      vn = p + WAVE < nout ? value(p + WAVE) : 0ull;
       const u32 limb = w_resolve(v, carry);
       if (p < nout) out[p] = limb;
     }
