@@ -48,12 +48,12 @@ def schur_limb_macs(N, nl):
     return (N - 1) * N * (N + 1) / 6 * nl * nl
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, kernel="k_upd_mfma"):
     """HBM traffic per trailing-update launch from the rocprofv3 counter runs
     recorded under profiles/, if they were taken on this workload and on the
     kernel source as it is now; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_upd_mfma_c4_traffic.json")
+    path = os.path.join(ROOT, "profiles", kernel + "_c4_traffic.json")
     try:
         rec = json.load(open(path))
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (d lambda_1 / d beta)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance workload")
+    ap.add_argument("--karatsuba", default="auto", choices=["auto", "on", "off"],
+                    help="Schur-update form of the MFMA path: one Karatsuba level or the plain digit product")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--progress", action="store_true",
                     help="factor in pieces of 128 columns, printing a line after each (profiler runs)")
@@ -115,6 +117,7 @@ def main():
     nl = P // 32
     log = lambda *x: print("[bench]", *x, file=sys.stderr, flush=True)
     ctx = Context(0)
+    ctx.set_karatsuba({"auto": -1, "on": 1, "off": 0}[a.karatsuba])
     mu = moments(beta, 2 * N - 1)
     packed = ctx.pack_moments(mu)
     sh = ctx.shape(N, k, P, E, a.form)
@@ -197,12 +200,25 @@ def main():
         "schur": {"limb_macs_algorithmic": macs, "limb_macs_in_updates": stages["schur_limb_macs"],
                   "kernel_limb_mac_per_s": stages["schur_limb_macs"] / (ms[0] * 1e-3) if ms[0] else None},
     }
+    kara = a.form == "mfma" and stages["launches"][2] > 0
+    if a.form == "mfma":
+        out["config"]["schur_form"] = "karatsuba" if kara else "digit product"
+    if kara:
+        out["stages_ms"]["kara_combine"] = ms[9]
     if a.form == "mfma" and ms[6] > 0:
-        achieved = 32.0 * stages["schur_limb_macs"] / (ms[6] * 1e-3) / 1e12  # int8 ops: 16 MACs x 2
+        # int8 ops the GEMMs need per entry and panel column: the digit product
+        # multiplies S^2 digit pairs (S = P/8, 16 per limb-MAC), one Karatsuba
+        # level three products of S/2 + 1 digits; 2 ops per multiply-add
+        S = P // 8
+        units = stages["schur_limb_macs"] / (nl * nl)   # entry x panel-column updates
+        ops = units * (3 * (S // 2 + 1) ** 2 if kara else S * S) * 2
+        achieved = ops / (ms[6] * 1e-3) / 1e12
+        kname = "k_upd_kara" if kara else "k_upd_mfma"
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_INT8_PEAK_TOPS,
                            "unit": "TFLOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
-                           "traffic": measured_traffic(workload),
-                           "kernel": "k_upd_mfma (int8 ops)", "launches": stages["launches"][1],
+                           "traffic": measured_traffic(workload, kname),
+                           "kernel": kname + " (int8 ops of the algorithm, padding excluded)",
+                           "launches": stages["launches"][1],
                            "avg_launch_ms": ms[6] / max(1, stages["launches"][1])}
 
     # adjoint on the same factorisation: d lambda_1 / d beta (after the timed steps)

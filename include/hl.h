@@ -155,6 +155,21 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
                          int32_t col_begin, int32_t col_end, void *stream);
 
 /*
+ * hl_set_karatsuba -- form of the exact Schur update of hl_factor for
+ * HL_FORM_MFMA8 shapes whose P is a multiple of 256 (other shapes always use
+ * the digit product).  The update of Algorithm 1's inner loops is exact, so both
+ * forms give the same bits; they differ in speed only.
+ *   mode  0: one int8 digit-product GEMM of the P-bit factors (S = P/8 digits);
+ *         1: one Karatsuba level: the factors split at digit S/2, three GEMMs of
+ *            (S/2 + 1)-digit operands (3/4 of the int8 multiply-adds), their exact
+ *            sums combined per entry with exact carries;
+ *        -1 (default): 1 from P = 4096 on, else 0.
+ * Applies to later hl_factor / hl_factor_cols calls on this context (the two
+ * may be mixed within one factorisation).  HL_EINVAL for another mode.
+ */
+hl_status hl_set_karatsuba(hl_ctx *ctx, int32_t mode);
+
+/*
  * hl_inv_block -- first k columns of L^-1 (Algorithm 4, Section 4.4) and the
  * top-left k x k block of H^-1 (eq. equ:index, Section 4.5).
  *   x        device, NT x k x nl limbs: x_rm at x + (r*k + m)*nl, the scaled
@@ -310,8 +325,9 @@ hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
  * ms[0] Schur update (all its kernels), ms[1] panel (pivots, factor columns,
  * in-panel updates), ms[2] triangular solve, ms[3] block, ms[4] eigen-step,
  * ms[5] load, ms[6] the int8 MFMA GEMM kernel alone, ms[7] whole hl_factor,
- * ms[8] hl_lambda_grad; launches[0] Schur updates, launches[1] MFMA GEMM
- * launches. */
+ * ms[8] hl_lambda_grad, ms[9] the Karatsuba combination kernel alone;
+ * launches[0] Schur updates, launches[1] MFMA GEMM launches, launches[2] those
+ * of them in the Karatsuba form. */
 typedef struct {
   double ms[12];
   int64_t launches[4];

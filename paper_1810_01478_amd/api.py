@@ -274,6 +274,11 @@ class Context:
     def set_timing(self, on: bool):
         L.check(L.lib().hl_set_timing(self.h, 1 if on else 0))
 
+    def set_karatsuba(self, mode: int):
+        """Schur-update form of later factorisations of MFMA shapes with P % 256 == 0:
+        0 digit product, 1 one Karatsuba level, -1 by precision (the default)."""
+        L.check(L.lib().hl_set_karatsuba(self.h, int(mode)))
+
     def timing(self):
         t = L.hl_timing_t()
         L.check(L.lib().hl_get_timing(self.h, ctypes.byref(t)))

@@ -18,6 +18,7 @@ using namespace hl;
 struct hl_ctx {
   int device = 0;
   int timing = 0;
+  int karatsuba = -1;  // Schur update form for MFMA shapes: -1 by precision, 0 digit product, 1 Karatsuba
   hl_timing_t t{};
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -67,6 +68,7 @@ hl_status make_dims(const hl_shape* sh, Dims* dm) {
   dm->E = sh->exp_block;
   dm->k = sh->k;
   dm->W = 2 * sh->prec_bits - 4;
+  dm->kara = (sh->form == HL_FORM_MFMA8 && sh->prec_bits % 256 == 0) ? 1 : 0;
   return HL_OK;
 }
 
@@ -99,6 +101,13 @@ Layout make_layout(const Dims& dm) {
     const size_t tiles = tri > rect ? tri : rect;
     const size_t useful = tiles * (size_t)(kMaxRanges < dm.nl / 2 ? kMaxRanges : dm.nl / 2);
     L.carry_tiles = 16384 + tiles < useful ? 16384 + tiles : useful;
+    if (dm.kara) {
+      // the Karatsuba form has three products per tile
+      const size_t ntbp = (size_t)kara_nwp(dm.S) / 4;
+      const size_t kuse = 3 * tri * (kMaxRanges < ntbp ? kMaxRanges : ntbp);
+      const size_t kt = 16384 + 3 * tri < kuse ? 16384 + 3 * tri : kuse;
+      if (kt > L.carry_tiles) L.carry_tiles = kt;
+    }
     off += al(L.carry_tiles * 1024 * 8);
   }
   // block: per pair and row chunk partial sums of 3nl + 8 limbs
@@ -166,6 +175,16 @@ Layout make_layout(const Dims& dm) {
     L.adj_r = off;
     off += al((size_t)dm.N * L.adj_nr * 4);
   }
+  if (dm.kara) {
+    L.kara_slices = dm.S / 2 + 1 + 2 * kDigitPad;
+    L.kara_dig_bytes = al((size_t)L.kara_slices * dm.NT * 16);
+    L.kara_dig = off;
+    off += 6 * L.kara_dig_bytes;
+    L.kara_nwp = kara_nwp(dm.S);
+    L.kara_tiles = (size_t)dm.nt * (dm.nt + 1) / 2;
+    L.kara_prod = off;
+    off += al(3 * L.kara_tiles * tile_words(L.kara_nwp) * 4);
+  }
   L.total = off;
   return L;
 }
@@ -229,6 +248,13 @@ extern "C" hl_status hl_destroy(hl_ctx* ctx) {
 extern "C" hl_status hl_set_timing(hl_ctx* ctx, int enable) {
   if (!ctx) return fail(HL_EINVAL, "null ctx");
   ctx->timing = enable;
+  return HL_OK;
+}
+
+extern "C" hl_status hl_set_karatsuba(hl_ctx* ctx, int32_t mode) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  if (mode < -1 || mode > 1) return fail(HL_EINVAL, "karatsuba mode %d not in {-1, 0, 1}", mode);
+  ctx->karatsuba = mode;
   return HL_OK;
 }
 
@@ -303,6 +329,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   u32* up = (u32*)(base + L.upanel);
   u32* omega = (u32*)(base + L.omega);
   ctx->t = hl_timing_t{};
+  const bool use_kara = dm.kara && (ctx->karatsuba == 1 || (ctx->karatsuba < 0 && dm.P >= kKaraMinPrec));
 
   Stamp total(ctx, st, 7);
   if (col_begin == 0) {
@@ -313,6 +340,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
     // zero digit slices (the padding outside [0, S) must read as zero)
     HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
     HIPCHK(launch_fill((u32*)(base + L.udig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
+    if (dm.kara) HIPCHK(launch_fill((u32*)(base + L.kara_dig), 6 * L.kara_dig_bytes / 4, 0u, st));
   }
   HIPCHK(launch_scales(mu, mu_exp, w, dm.N, dm.E, out->s, dst, st));
   HIPCHK(launch_load(mu, mu_exp, w, out->s, dm, A, dst, st));
@@ -412,7 +440,19 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         m.carry_tiles = L.carry_tiles;
         m.timing = ctx->timing ? &ctx->t : nullptr;
         m.u_rows = dm.NT;
-        e = launch_upd_mfma(m, st);
+        if (use_kara) {
+          KaraArgs ka{};
+          ka.m = m;
+          for (int q = 0; q < 6; ++q) ka.dig[q] = (int8_t*)(base + L.kara_dig + q * L.kara_dig_bytes);
+          ka.Sk = dm.S / 2 + 1;
+          ka.kslices = L.kara_slices;
+          ka.prod = (u32*)(base + L.kara_prod);
+          ka.nwp = L.kara_nwp;
+          ka.prod_tiles = L.kara_tiles;
+          e = launch_upd_kara(ka, st);
+        } else {
+          e = launch_upd_mfma(m, st);
+        }
       } else {
         e = launch_upd_valu(g, st);
       }

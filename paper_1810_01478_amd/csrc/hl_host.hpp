@@ -9,6 +9,7 @@ constexpr int kMaxPrec = 57344;   // pivot kernel keeps ~9 (P/32 + 8) words in L
 constexpr int kDigitPad = 64;     // zero digit slices below 0 and above S-1
 constexpr int kMaxRanges = 64;    // output-limb ranges per tile in the MFMA updates
 constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
+constexpr int kKaraMinPrec = 4096; // Karatsuba form of the Schur update from this precision on (by default)
 
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
@@ -29,6 +30,11 @@ struct Layout {
   int digit_slices;
   int blk_stride;
   int blk_chunks;
+  // Karatsuba form of the Schur update: six half-length digit panels
+  // (kara_slices slices each, kara_dig_bytes apart) and the three products
+  // (kara_tiles tiles of kara_nwp limbs per entry each)
+  size_t kara_dig, kara_dig_bytes, kara_prod, kara_tiles;
+  int kara_slices, kara_nwp;
 };
 
 hl_status fail(hl_status s, const char* fmt, ...);

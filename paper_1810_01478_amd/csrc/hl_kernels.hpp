@@ -97,8 +97,34 @@ struct RangeTab {
 };
 RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items);
 RangeTab split_ranges(int nl, int S, int n);
+// the same for ntb output blocks of a product of S-digit operands, with units
+// work items per range (tiles x products)
+RangeTab make_ranges_ntb(int ntb, int S, long units, int max_ranges, size_t max_items);
+RangeTab split_ranges_ntb(int ntb, int S, int n);
 double block_work(int tb, int S);  // digit pairs multiplied for output block tb
 constexpr int MF_BLOCK_DIGITS = 16;
+
+// Karatsuba form of the Schur update (one level).  With X = 256^h, h = S/2, each
+// factor splits into its balanced digits below and above h: b = b_lo + X b_hi,
+// and b_mid = b_lo + b_hi is recoded into h + 1 balanced digits.  Then
+//   sum_i b_ri u_ci = LL + X (MM - LL - HH) + X^2 HH,
+// LL = sum_i b_lo u_lo, HH = sum_i b_hi u_hi, MM = sum_i b_mid u_mid: three
+// digit-sum GEMMs of (h + 1)-digit operands (3/4 of the int8 MACs of the
+// S-digit product) whose exact sums are stored per entry, then one pass per
+// entry subtracts the combination from the trailing matrix with exact carries.
+constexpr int KA_LL = 0, KA_HH = 1, KA_MM = 2;
+struct KaraArgs {
+  MfmaArgs m;          // target, pad, NT, S, carry slots (3 x tiles x ranges), timing; bdig/udig unused
+  int8_t* dig[6];      // digit panels b_lo, b_hi, b_mid, u_lo, u_hi, u_mid: [kslices][NT][16]
+  int Sk;              // digits per half operand: h + 1
+  int kslices;         // Sk + 2 pad
+  u32* prod;           // products LL, HH, MM: [3][prod_tiles] tiles of nwp limbs per entry
+  int nwp;             // limbs per product entry: 4 x output blocks of a (2 Sk - 1)-digit product
+  size_t prod_tiles;   // tiles per product
+};
+hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream);
+// limbs per product entry and digit panel size of the Karatsuba form for S digits
+__host__ __device__ __forceinline__ int kara_nwp(int S) { return 4 * ((2 * (S / 2 + 1) - 1 + 15) / 16); }
 
 // Batched form: one entry per instance and step, work items (entry, tile index
 // of the entry's launch, range) in 8 per-XCD queues of per_xcd items (x < 0:

@@ -100,25 +100,31 @@ __device__ __forceinline__ size_t launch_tile_index(const UpdArgs& g, int R, int
   return (size_t)(R - C_lo) * g.ntc + C;
 }
 
-// The update of tile (R, C) over output blocks [tb0, tb1); the carry out of the
-// range goes to cb (1024 entries).
-__device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int tb0, int tb1, long long* cb) {
-  const UpdArgs& g = m.g;
-  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
+// The digit-sum GEMM of tile (R, C) over output blocks [tb0, tb1) of the
+// product of the digit panels bdig (rows) and udig (columns), S digits each,
+// slices = S + 2 pad slices of NT x 16 bytes.  STORE = false: the sums are
+// subtracted from the trailing-matrix tile Out (limb 4 tb of an entry receives
+// block tb).  STORE = true: the exact sums themselves are written to the tile
+// Out, block tb as limbs 4 tb .. 4 tb + 3 of the entry.  Either way the carry
+// out of the range goes to cb (1024 entries).
+template <bool STORE>
+__device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig, const int8_t* udig, int slices,
+                                            int S, int pad, int NT, int R, int C, int tb0, int tb1, long long* cb,
+                                            u32* Out) {
   if (has_error(g.st)) return;
   __shared__ i64 carry_s[16 * WAVE];  // carry of each of the lane's 16 entries
   const int l = lane_id(), h = l >> 5, mm = l & 31;
-  const int S = m.S, NT = m.NT, pad = m.pad;
   const int sst = NT * 16;  // bytes per digit slice
   // A operand (b digits of tile rows), B operand (u digits of tile columns),
   // read through buffer descriptors: a 32-bit lane offset plus a wave-uniform
   // slice offset stepped in scalar registers, so no load in flight holds a
   // per-lane 64-bit address
-  const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(m.bdig, 0, m.slices * sst, kRawBufferWord3);
-  const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(m.udig, 0, m.slices * sst, kRawBufferWord3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(bdig), 0, slices * sst, kRawBufferWord3);
+  const __amdgpu_buffer_rsrc_t ru =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(udig), 0, slices * sst, kRawBufferWord3);
   const int aoff = h * sst + R * 512 + mm * 16;
   const int uoff = (1 - h) * sst + C * 512 + mm * 16;
-  u32* At = g.A + tix * tile_words(g.nw);
   unsigned live = 0;  // entries of the trailing matrix proper (r >= c, inside the target)
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -183,15 +189,20 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int t
     for (int v = 0; v < 16; ++v) {
       if (!((live >> v) & 1u)) continue;
       const int r = mf_row(l, v), c = mf_col(l);
-      uint4* p = (uint4*)(At + in_tile(r, c, MF_LPB * tb));
-      const uint4 x = *p;
+      uint4* p = (uint4*)(Out + in_tile(r, c, MF_LPB * tb));
       i64 d[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < MF_T; ++q) d[q >> 2] += (i64)acc[q][v] << (8 * (q & 3));
-      const __int128 X = (__int128)(((u64)x.y << 32) | x.x) - (__int128)d[0] - ((__int128)d[1] << 32) +
-                         (__int128)carry_s[v * WAVE + l];
-      const __int128 Y = (__int128)(((u64)x.w << 32) | x.z) - (__int128)d[2] - ((__int128)d[3] << 32) +
-                         (__int128)(i64)(X >> 64);
+      __int128 X, Y;
+      if (STORE) {
+        X = (__int128)d[0] + ((__int128)d[1] << 32) + (__int128)carry_s[v * WAVE + l];
+        Y = (__int128)d[2] + ((__int128)d[3] << 32) + (__int128)(i64)(X >> 64);
+      } else {
+        const uint4 x = *p;
+        X = (__int128)(((u64)x.y << 32) | x.x) - (__int128)d[0] - ((__int128)d[1] << 32) +
+            (__int128)carry_s[v * WAVE + l];
+        Y = (__int128)(((u64)x.w << 32) | x.z) - (__int128)d[2] - ((__int128)d[3] << 32) + (__int128)(i64)(X >> 64);
+      }
       const u64 lo = (u64)X, hi = (u64)Y;
       *p = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
       carry_s[v * WAVE + l] = (i64)(Y >> 64);
@@ -200,6 +211,14 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int t
   // carries out of this range
 #pragma unroll
   for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry_s[v * WAVE + l];
+}
+
+// the Schur update of tile (R, C) of the trailing matrix (see mfma_tile_t)
+__device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int tb0, int tb1, long long* cb) {
+  const UpdArgs& g = m.g;
+  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
+  mfma_tile_t<false>(g, m.bdig, m.udig, m.slices, m.S, m.pad, m.NT, R, C, tb0, tb1, cb,
+                     g.A + tix * tile_words(g.nw));
 }
 
 // tile (R, C) of work item lt of an entry's launch (see k_upd_mfma)
@@ -312,6 +331,156 @@ __global__ void k_carry_fix_b(const MfmaEntry* __restrict__ tab) {
 }
 
 // ---------------------------------------------------------------------------
+// Karatsuba form (see KaraArgs).
+//
+// Digits of the halves: limb q of a factor holds its balanced digits 4q..4q+3;
+// those below h = 4 hq go to the lo panel, the others to the hi panel at digit
+// 4q - h.  One thread per (limb, row, panel column), as recode_body.
+__global__ void k_recode_kara(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows, int nl, int pad,
+                              int hq, int8_t* __restrict__ lo, int8_t* __restrict__ hi) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int il = (int)(gid & 15);
+  const size_t t = gid >> 4;
+  const int row = (int)(t % NT), q = (int)(t / NT);
+  if (q >= nl) return;
+  const size_t rstride = (size_t)NT * 16;
+  const int qq = q < hq ? q : q - hq;
+  int8_t* d = (q < hq ? lo : hi) + (size_t)(pad + 4 * qq) * rstride + (size_t)row * 16 + il;
+  u32 v = 0;
+  if (il < npan && row < nrows) v = balanced_digits4(src + (size_t)il * lds + (size_t)row * nl, nl, q);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) d[(size_t)b * rstride] = (int8_t)(v >> (8 * b));
+}
+
+// floor((x + 128) / 256) for -512 <= x + 128: the balanced carry out of a
+// digit position holding x
+__device__ __forceinline__ int bal_carry(int x) { return (x + 640) / 256 - 2; }
+
+// mid = lo + hi recoded into h + 1 balanced digits: sigma_j = lo_j + hi_j in
+// [-256, 254], digit_j = sigma_j + c_j - 256 c_{j+1}, c_{j+1} = bal_carry(sigma_j
+// + c_j) in {-1, 0, 1}, c_0 = 0; the top digit h is c_h.  One thread per (group
+// of digits 4g..4g+3, row, panel column), g = 0..h/4; the carry into 4g is found
+// by looking down to the nearest position whose carry out does not depend on
+// the carry in, then carrying up from there.
+__global__ void k_kara_mid(const int8_t* __restrict__ lo, const int8_t* __restrict__ hi, int NT, int pad, int h,
+                           int8_t* __restrict__ mid) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int il = (int)(gid & 15);
+  const size_t t = gid >> 4;
+  const int row = (int)(t % NT), g = (int)(t / NT);
+  if (g > h / 4) return;
+  const size_t rs = (size_t)NT * 16, off = (size_t)row * 16 + il;
+  auto sig = [&](int j) -> int {
+    return j < h ? (int)lo[(size_t)(pad + j) * rs + off] + (int)hi[(size_t)(pad + j) * rs + off] : 0;
+  };
+  const int j0 = 4 * g;
+  int js = j0 - 1;
+  while (js >= 0) {
+    const int sj = sig(js);
+    if (bal_carry(sj - 1) == bal_carry(sj + 1)) break;
+    --js;
+  }
+  int c = js >= 0 ? bal_carry(sig(js)) : 0;  // carry into js + 1
+  for (int j = js + 1; j < j0; ++j) c = bal_carry(sig(j) + c);
+  int8_t* d = mid + (size_t)(pad + j0) * rs + off;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int x = sig(j0 + b) + c;
+    const int cn = bal_carry(x);
+    d[(size_t)b * rs] = (int8_t)(x - 256 * cn);
+    c = cn;
+  }
+}
+
+// The three digit-sum GEMMs: work items (range rg, product p, tile lt) in that
+// order, dealt to the XCDs as in k_upd_mfma, so the waves of one XCD share a
+// range and a product and hold neighbouring tiles.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_upd_kara(KaraArgs k, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
+  const UpdArgs& g = k.m.g;
+  const int b = blockIdx.x;
+  const int item = (b & 7) * per_xcd + (b >> 3);
+  if (item >= 3 * ntiles * rt.n) return;
+  const int rg = item / (3 * ntiles), rem = item - rg * 3 * ntiles;
+  const int p = rem / ntiles, lt = rem - p * ntiles;
+  int R, C;
+  item_tile(g, C_lo, lt, &R, &C);
+  if (R * 32 >= k.m.NT) return;
+  const int8_t* bd = p == KA_LL ? k.dig[0] : (p == KA_HH ? k.dig[1] : k.dig[2]);
+  const int8_t* ud = p == KA_LL ? k.dig[3] : (p == KA_HH ? k.dig[4] : k.dig[5]);
+  mfma_tile_t<true>(g, bd, ud, k.kslices, k.Sk, k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
+                    k.m.carry + (((size_t)p * ntiles + lt) * rt.n + rg) * 1024,
+                    k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp));
+}
+
+// a -= LL + X (MM - LL - HH) + X^2 HH for every live entry of the launch, with
+// X = 2^(32 H) (H = h/4 limbs, O = H/4 slabs): one thread per entry walks the
+// entry's slabs from the bottom with one signed running carry.  Each stored
+// product is exact only with the carries out of its ranges, which enter at the
+// first slab of the next range (the last one at the slab past the product: its
+// sign extension).
+__global__ __launch_bounds__(256) void k_kara_comb(KaraArgs k, RangeTab rt, int C_lo, int ntiles) {
+  __shared__ int tbs[MF_MAX_RANGES + 1];
+  for (int i = threadIdx.x; i <= rt.n; i += blockDim.x) tbs[i] = rt.tb[i];
+  __syncthreads();
+  const UpdArgs& g = k.m.g;
+  const int lt = blockIdx.x >> 2, e = (blockIdx.x & 3) * 256 + threadIdx.x;
+  int R, C;
+  item_tile(g, C_lo, lt, &R, &C);
+  if (R * 32 >= k.m.NT) return;
+  const int r = e >> 5, c = e & 31;
+  {
+    const int rg = R * 32 + r, cg = C * 32 + c;
+    if (!((!g.tri || rg >= cg) && rg >= g.r_lo && rg < g.r_hi && cg >= g.c_lo && cg < g.c_hi)) return;
+  }
+  if (has_error(g.st)) return;
+  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
+  u32* At = g.A + tix * tile_words(g.nw);
+  const size_t tw = tile_words(k.nwp);
+  const u32* QL = k.prod + ((size_t)KA_LL * k.prod_tiles + lt) * tw;
+  const u32* QH = k.prod + ((size_t)KA_HH * k.prod_tiles + lt) * tw;
+  const u32* QM = k.prod + ((size_t)KA_MM * k.prod_tiles + lt) * tw;
+  const long long* cL = k.m.carry + ((size_t)KA_LL * ntiles + lt) * rt.n * 1024 + e;
+  const long long* cH = k.m.carry + ((size_t)KA_HH * ntiles + lt) * rt.n * 1024 + e;
+  const long long* cM = k.m.carry + ((size_t)KA_MM * ntiles + lt) * rt.n * 1024 + e;
+  const int O = k.m.S / 32;  // h / 16
+  const int nsl = g.nw / 4, nq = k.nwp / 4, nr = rt.n;
+  int w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0;
+  i64 cy = 0;
+  for (int j = 0; j < nsl; ++j) {
+    const uint4 a = *(const uint4*)(At + in_tile(r, c, 4 * j));
+    i64 s0 = a.x, s1 = a.y, s2 = a.z, s3 = a.w;
+    auto term = [&](const u32* Q, const long long* cq, int off, bool add, int& w) {
+      const int q = j - off;
+      if (q >= 0 && q < nq) {
+        const uint4 v = *(const uint4*)(Q + in_tile(r, c, 4 * q));
+        if (add) {
+          s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
+        } else {
+          s0 -= v.x; s1 -= v.y; s2 -= v.z; s3 -= v.w;
+        }
+      }
+      if (w < nr && q == tbs[w + 1]) {
+        const i64 cv = cq[(size_t)w * 1024];
+        s0 += add ? cv : -cv;
+        ++w;
+      }
+    };
+    term(QL, cL, 0, false, w0);
+    term(QM, cM, O, false, w1);
+    term(QL, cL, O, true, w2);
+    term(QH, cH, O, true, w3);
+    term(QH, cH, 2 * O, false, w4);
+    s0 += cy;
+    s1 += s0 >> 32;
+    s2 += s1 >> 32;
+    s3 += s2 >> 32;
+    cy = s3 >> 32;
+    *(uint4*)(At + in_tile(r, c, 4 * j)) = make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // MFMA output layout probe (test hook): out[v * 64 + l] for two operand patterns.
 __global__ __launch_bounds__(64) void k_mfma_probe(int* out) {
   const int l = lane_id();
@@ -356,14 +525,17 @@ double block_work(int tb, int S) {
 // (8 XCDs x 128) and c = 0.2% of a tile is the cost of one more work item (its
 // first block's operand fetch and its carry slot).
 RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items) {
-  const int ntb = 8 * nl / MF_T;
+  return make_ranges_ntb(8 * nl / MF_T, S, ntiles, max_ranges, max_items);
+}
+
+RangeTab make_ranges_ntb(int ntb, int S, long units, int max_ranges, size_t max_items) {
   int cap = max_ranges < MF_MAX_RANGES ? max_ranges : MF_MAX_RANGES;
   if (cap > ntb) cap = ntb;
   if (cap < 1) cap = 1;
   int want = 1;
   double best = 1e300;
   for (int n = 1; n <= cap; ++n) {
-    const long total = (long)ntiles * n;
+    const long total = units * n;
     if (n > 1 && (size_t)total > max_items) break;
     const long per = (total + 7) / 8;
     const long rounds = (per + 127) / 128;
@@ -373,12 +545,13 @@ RangeTab make_ranges(int nl, int S, int ntiles, int max_ranges, size_t max_items
       want = n;
     }
   }
-  return split_ranges(nl, S, want);
+  return split_ranges_ntb(ntb, S, want);
 }
 
 // n ranges of about equal work
-RangeTab split_ranges(int nl, int S, int want) {
-  const int ntb = 8 * nl / MF_T;
+RangeTab split_ranges(int nl, int S, int want) { return split_ranges_ntb(8 * nl / MF_T, S, want); }
+
+RangeTab split_ranges_ntb(int ntb, int S, int want) {
   RangeTab rt{};
   if (want < 1) want = 1;
   if (want > MF_MAX_RANGES) want = MF_MAX_RANGES;
@@ -460,6 +633,69 @@ hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream) {
   if (rt.n > 1) {
     hipLaunchKernelGGL(k_carry_fix, dim3(nrow, ncol), dim3(1024), 0, stream, m, rt, C_lo);
     e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
+  const MfmaArgs& m = k.m;
+  const UpdArgs& g = m.g;
+  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  if (!g.tri || (g.rsb != 0 && g.rsb != (size_t)g.nl)) return hipErrorInvalidValue;
+  const int h = m.S / 2;
+  if (m.S % 32 || m.S != 4 * g.nl || k.Sk != h + 1 || k.nwp != kara_nwp(m.S) || m.pad < MF_PAD_MIN ||
+      k.kslices != k.Sk + 2 * m.pad || (size_t)k.kslices * m.NT * 16 > 0x7fffffffu)
+    return hipErrorInvalidValue;  // halves of whole 4-limb slabs, padding, 32-bit buffer offsets
+  const size_t rthreads = (size_t)g.nl * m.NT * 16;
+  const unsigned rblocks = (unsigned)((rthreads + 255) / 256);
+  hipLaunchKernelGGL(k_recode_kara, dim3(rblocks), dim3(256), 0, stream, g.Bop, g.ldb, g.npan, m.NT, m.NT, g.nl,
+                     m.pad, h / 4, k.dig[0], k.dig[1]);
+  hipLaunchKernelGGL(k_recode_kara, dim3(rblocks), dim3(256), 0, stream, g.Uop, g.ldu, g.npan, m.NT, m.u_rows,
+                     g.nl, m.pad, h / 4, k.dig[3], k.dig[4]);
+  const size_t mthreads = (size_t)(h / 4 + 1) * m.NT * 16;
+  const unsigned mblocks = (unsigned)((mthreads + 255) / 256);
+  hipLaunchKernelGGL(k_kara_mid, dim3(mblocks), dim3(256), 0, stream, k.dig[0], k.dig[1], m.NT, m.pad, h, k.dig[2]);
+  hipLaunchKernelGGL(k_kara_mid, dim3(mblocks), dim3(256), 0, stream, k.dig[3], k.dig[4], m.NT, m.pad, h, k.dig[5]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nt = m.NT / 32;
+  const int C_lo = g.c_lo / 32;
+  const int ncol = nt - C_lo;
+  const int ntiles = ncol * (ncol + 1) / 2;
+  if ((size_t)ntiles > k.prod_tiles) return hipErrorInvalidValue;
+  const RangeTab rt = make_ranges_ntb(k.nwp / 4, k.Sk, 3L * ntiles, m.max_ranges, m.carry_tiles);
+  if ((size_t)3 * ntiles * rt.n > m.carry_tiles) return hipErrorInvalidValue;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (m.timing) {
+    (void)hipEventCreate(&ev0);
+    (void)hipEventCreate(&ev1);
+    (void)hipEventRecord(ev0, stream);
+  }
+  const long items = 3L * ntiles * rt.n;
+  const int per_xcd = (int)((items + 7) / 8);
+  hipLaunchKernelGGL(k_upd_kara, dim3(8 * per_xcd), dim3(64), 0, stream, k, rt, C_lo, ntiles, per_xcd);
+  e = hipGetLastError();
+  if (m.timing) {
+    (void)hipEventRecord(ev1, stream);
+    (void)hipEventSynchronize(ev1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    m.timing->ms[6] += ms;
+    m.timing->launches[1] += 1;
+    m.timing->launches[2] += 1;
+    (void)hipEventRecord(ev0, stream);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_kara_comb, dim3(4 * ntiles), dim3(256), 0, stream, k, rt, C_lo, ntiles);
+  e = hipGetLastError();
+  if (m.timing) {
+    (void)hipEventRecord(ev1, stream);
+    (void)hipEventSynchronize(ev1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    m.timing->ms[9] += ms;
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
   }
   return e;
 }

@@ -52,3 +52,4 @@ def test_sizes_and_argument_checks_on_host():
         assert L.hl_get_sizes(ctypes.byref(s), ctypes.byref(out)) == _lib.HL_EINVAL, bad
         assert L.hl_last_error()
     assert L.hl_factor(None, ctypes.byref(sh), None, None, 1, None, 0, None, None) == _lib.HL_EINVAL
+    assert L.hl_set_karatsuba(None, 0) == _lib.HL_EINVAL

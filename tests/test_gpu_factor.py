@@ -164,3 +164,60 @@ def test_mfma_equals_valu_bitwise_c2b_shape():
     ctx().sync(fb)
     import torch
     assert torch.equal(fa.d, fb.d) and torch.equal(fa.l, fb.l) and torch.equal(fa.h, fb.h)
+
+
+@pytest.mark.parametrize("beta,N,P,E", [
+    (Fraction(1, 2), 64, 2048, 16),
+    (Fraction(1, 2), 80, 1024, 7),    # ragged last tile
+    (Fraction(1, 3), 45, 1536, 1),
+    (Fraction(1, 2), 100, 4096, 16),
+    (Fraction(1, 3), 20, 256, 1),     # shortest halves: 16 digits, one slab
+    (1, 97, 3072, 4),
+])
+def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E):
+    # the Karatsuba form of the trailing update is exact: same bits as the oracle
+    say("factor karatsuba", beta, N, P, E)
+    mu = moments(beta, 2 * N - 1)
+    f = C.factor(mu, N, P, E)
+    c = ctx()
+    c.set_karatsuba(1)
+    try:
+        fac = c.factor(mu, N, 8, P, E, "mfma")
+        c.sync(fac)
+    finally:
+        c.set_karatsuba(-1)
+    _check_factor(fac, f, N)
+
+
+def test_karatsuba_equals_digit_product_c2b_shape():
+    # beta = 1/2, N = 256 at 8192 bits, and a continuation in pieces that
+    # switches form between pieces: all give the same bits
+    import torch
+    N, P = 256, 8192
+    say("karatsuba vs digit product", N, P)
+    mu = moments(Fraction(1, 2), 2 * N - 1)
+    c = ctx()
+    try:
+        c.set_karatsuba(0)
+        fa = c.factor(mu, N, 8, P, 16, "mfma")
+        c.sync(fa)
+        c.set_karatsuba(1)
+        fb = c.factor(mu, N, 8, P, 16, "mfma")
+        c.sync(fb)
+        fc = c.factor_cols(mu, N, 8, P, 16, "mfma", 0, 96)
+        c.set_karatsuba(0)
+        c.factor_cols(mu, N, 8, P, 16, "mfma", 96, 160, fac=fc)
+        c.set_karatsuba(1)
+        c.factor_cols(mu, N, 8, P, 16, "mfma", 160, N, fac=fc)
+        c.sync(fc)
+    finally:
+        c.set_karatsuba(-1)
+    for f in (fb, fc):
+        assert torch.equal(fa.d, f.d) and torch.equal(fa.l, f.l) and torch.equal(fa.h, f.h)
+
+
+def test_set_karatsuba_rejects_bad_mode():
+    from paper_1810_01478_amd._lib import HLError, HL_EINVAL
+    with pytest.raises(HLError) as e:
+        ctx().set_karatsuba(2)
+    assert e.value.code == HL_EINVAL
