@@ -86,8 +86,8 @@ def main():
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (d lambda_1 / d beta)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance workload")
-    ap.add_argument("--karatsuba", default="auto", choices=["auto", "on", "off"],
-                    help="Schur-update form of the MFMA path: one Karatsuba level or the plain digit product")
+    ap.add_argument("--karatsuba", default="auto", choices=["auto", "0", "1", "2"],
+                    help="Schur-update form of the MFMA path: Karatsuba levels (0: the plain digit product)")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--progress", action="store_true",
                     help="factor in pieces of 128 columns, printing a line after each (profiler runs)")
@@ -117,7 +117,7 @@ def main():
     nl = P // 32
     log = lambda *x: print("[bench]", *x, file=sys.stderr, flush=True)
     ctx = Context(0)
-    ctx.set_karatsuba({"auto": -1, "on": 1, "off": 0}[a.karatsuba])
+    ctx.set_karatsuba(-1 if a.karatsuba == "auto" else int(a.karatsuba))
     mu = moments(beta, 2 * N - 1)
     packed = ctx.pack_moments(mu)
     sh = ctx.shape(N, k, P, E, a.form)
@@ -200,18 +200,23 @@ def main():
         "schur": {"limb_macs_algorithmic": macs, "limb_macs_in_updates": stages["schur_limb_macs"],
                   "kernel_limb_mac_per_s": stages["schur_limb_macs"] / (ms[0] * 1e-3) if ms[0] else None},
     }
-    kara = a.form == "mfma" and stages["launches"][2] > 0
+    lv = 0
+    if a.form == "mfma" and stages["launches"][2] > 0:
+        lv = 2 if stages["launches"][3] > 0 else 1
+    kara = lv > 0
     if a.form == "mfma":
-        out["config"]["schur_form"] = "karatsuba" if kara else "digit product"
+        out["config"]["schur_form"] = "karatsuba x%d" % lv if kara else "digit product"
     if kara:
         out["stages_ms"]["kara_combine"] = ms[9]
     if a.form == "mfma" and ms[6] > 0:
         # int8 ops the GEMMs need per entry and panel column: the digit product
         # multiplies S^2 digit pairs (S = P/8, 16 per limb-MAC), one Karatsuba
-        # level three products of S/2 + 1 digits; 2 ops per multiply-add
+        # level three products of S/2 + 1 digits, two levels nine of S/4 + 2;
+        # 2 ops per multiply-add
         S = P // 8
         units = stages["schur_limb_macs"] / (nl * nl)   # entry x panel-column updates
-        ops = units * (3 * (S // 2 + 1) ** 2 if kara else S * S) * 2
+        pairs = {0: S * S, 1: 3 * (S // 2 + 1) ** 2, 2: 9 * (S // 4 + 2) ** 2}[lv]
+        ops = units * pairs * 2
         achieved = ops / (ms[6] * 1e-3) / 1e12
         kname = "k_upd_kara" if kara else "k_upd_mfma"
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_INT8_PEAK_TOPS,

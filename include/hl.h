@@ -156,16 +156,19 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
 
 /*
  * hl_set_karatsuba -- form of the exact Schur update of hl_factor for
- * HL_FORM_MFMA8 shapes whose P is a multiple of 256 (other shapes always use
- * the digit product).  The update of Algorithm 1's inner loops is exact, so both
- * forms give the same bits; they differ in speed only.
+ * HL_FORM_MFMA8 shapes.  The update of Algorithm 1's inner loops is exact, so
+ * every form gives the same bits; they differ in speed only.
  *   mode  0: one int8 digit-product GEMM of the P-bit factors (S = P/8 digits);
- *         1: one Karatsuba level: the factors split at digit S/2, three GEMMs of
- *            (S/2 + 1)-digit operands (3/4 of the int8 multiply-adds), their exact
- *            sums combined per entry with exact carries;
- *        -1 (default): 1 from P = 4096 on, else 0.
- * Applies to later hl_factor / hl_factor_cols calls on this context (the two
- * may be mixed within one factorisation).  HL_EINVAL for another mode.
+ *         1: one Karatsuba level (P a multiple of 256): the factors split at
+ *            digit S/2, three GEMMs of (S/2 + 1)-digit operands (3/4 of the int8
+ *            multiply-adds), their exact sums combined per entry with exact
+ *            carries;
+ *         2: two levels (P a multiple of 512): nine GEMMs of (S/4 + 2)-digit
+ *            operands (9/16 of the multiply-adds);
+ *        -1 (default): 2 from P = 24576 on, 1 from P = 8192 on, else 0.
+ * A mode beyond what P allows runs the deepest allowed one.  Applies to later
+ * hl_factor / hl_factor_cols calls on this context (modes may be mixed within
+ * one factorisation).  HL_EINVAL for another mode.
  */
 hl_status hl_set_karatsuba(hl_ctx *ctx, int32_t mode);
 
@@ -327,7 +330,7 @@ hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
  * ms[5] load, ms[6] the int8 MFMA GEMM kernel alone, ms[7] whole hl_factor,
  * ms[8] hl_lambda_grad, ms[9] the Karatsuba combination kernel alone;
  * launches[0] Schur updates, launches[1] MFMA GEMM launches, launches[2] those
- * of them in the Karatsuba form. */
+ * of them in a Karatsuba form, launches[3] those with two levels. */
 typedef struct {
   double ms[12];
   int64_t launches[4];

@@ -275,8 +275,9 @@ class Context:
         L.check(L.lib().hl_set_timing(self.h, 1 if on else 0))
 
     def set_karatsuba(self, mode: int):
-        """Schur-update form of later factorisations of MFMA shapes with P % 256 == 0:
-        0 digit product, 1 one Karatsuba level, -1 by precision (the default)."""
+        """Schur-update form of later factorisations of MFMA shapes: 0 digit
+        product, 1 or 2 Karatsuba levels (P % 256 == 0, P % 512 == 0), -1 by
+        precision (the default)."""
         L.check(L.lib().hl_set_karatsuba(self.h, int(mode)))
 
     def timing(self):

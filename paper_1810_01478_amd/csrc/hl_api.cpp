@@ -18,7 +18,7 @@ using namespace hl;
 struct hl_ctx {
   int device = 0;
   int timing = 0;
-  int karatsuba = -1;  // Schur update form for MFMA shapes: -1 by precision, 0 digit product, 1 Karatsuba
+  int karatsuba = -1;  // Schur update form for MFMA shapes: -1 by precision, else Karatsuba levels (0 = digit product)
   hl_timing_t t{};
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -68,7 +68,7 @@ hl_status make_dims(const hl_shape* sh, Dims* dm) {
   dm->E = sh->exp_block;
   dm->k = sh->k;
   dm->W = 2 * sh->prec_bits - 4;
-  dm->kara = (sh->form == HL_FORM_MFMA8 && sh->prec_bits % 256 == 0) ? 1 : 0;
+  dm->kara = sh->form != HL_FORM_MFMA8 ? 0 : sh->prec_bits % 512 == 0 ? 2 : sh->prec_bits % 256 == 0 ? 1 : 0;
   return HL_OK;
 }
 
@@ -101,11 +101,12 @@ Layout make_layout(const Dims& dm) {
     const size_t tiles = tri > rect ? tri : rect;
     const size_t useful = tiles * (size_t)(kMaxRanges < dm.nl / 2 ? kMaxRanges : dm.nl / 2);
     L.carry_tiles = 16384 + tiles < useful ? 16384 + tiles : useful;
-    if (dm.kara) {
-      // the Karatsuba form has three products per tile
-      const size_t ntbp = (size_t)kara_nwp(dm.S) / 4;
-      const size_t kuse = 3 * tri * (kMaxRanges < ntbp ? kMaxRanges : ntbp);
-      const size_t kt = 16384 + 3 * tri < kuse ? 16384 + 3 * tri : kuse;
+    for (int lv = 1; lv <= dm.kara; ++lv) {
+      // the Karatsuba forms have 3 or 9 products per tile
+      const size_t np = lv == 1 ? 3 : 9;
+      const size_t ntbp = (size_t)kara_nwp(dm.S, lv) / 4;
+      const size_t kuse = np * tri * (kMaxRanges < ntbp ? kMaxRanges : ntbp);
+      const size_t kt = 16384 + np * tri < kuse ? 16384 + np * tri : kuse;
       if (kt > L.carry_tiles) L.carry_tiles = kt;
     }
     off += al(L.carry_tiles * 1024 * 8);
@@ -180,10 +181,20 @@ Layout make_layout(const Dims& dm) {
     L.kara_dig_bytes = al((size_t)L.kara_slices * dm.NT * 16);
     L.kara_dig = off;
     off += 6 * L.kara_dig_bytes;
-    L.kara_nwp = kara_nwp(dm.S);
+    if (dm.kara >= 2) {
+      L.kara_leaf_slices = kara_leaf_digits(dm.S, 2) + 2 * kDigitPad;
+      L.kara_leaf_bytes = al((size_t)L.kara_leaf_slices * dm.NT * 16);
+      L.kara_leaf = off;
+      off += 18 * L.kara_leaf_bytes;
+    }
     L.kara_tiles = (size_t)dm.nt * (dm.nt + 1) / 2;
     L.kara_prod = off;
-    off += al(3 * L.kara_tiles * tile_words(L.kara_nwp) * 4);
+    size_t words = 3 * L.kara_tiles * tile_words(kara_nwp(dm.S, 1));
+    if (dm.kara >= 2) {
+      const size_t w2 = 9 * L.kara_tiles * tile_words(kara_nwp(dm.S, 2));
+      if (w2 > words) words = w2;
+    }
+    off += al(words * 4);
   }
   L.total = off;
   return L;
@@ -253,7 +264,7 @@ extern "C" hl_status hl_set_timing(hl_ctx* ctx, int enable) {
 
 extern "C" hl_status hl_set_karatsuba(hl_ctx* ctx, int32_t mode) {
   if (!ctx) return fail(HL_EINVAL, "null ctx");
-  if (mode < -1 || mode > 1) return fail(HL_EINVAL, "karatsuba mode %d not in {-1, 0, 1}", mode);
+  if (mode < -1 || mode > 2) return fail(HL_EINVAL, "karatsuba mode %d not in {-1, 0, 1, 2}", mode);
   ctx->karatsuba = mode;
   return HL_OK;
 }
@@ -329,7 +340,8 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   u32* up = (u32*)(base + L.upanel);
   u32* omega = (u32*)(base + L.omega);
   ctx->t = hl_timing_t{};
-  const bool use_kara = dm.kara && (ctx->karatsuba == 1 || (ctx->karatsuba < 0 && dm.P >= kKaraMinPrec));
+  int kara_lv = ctx->karatsuba >= 0 ? ctx->karatsuba : (dm.P >= kKara2MinPrec ? 2 : dm.P >= kKaraMinPrec ? 1 : 0);
+  if (kara_lv > dm.kara) kara_lv = dm.kara;
 
   Stamp total(ctx, st, 7);
   if (col_begin == 0) {
@@ -341,6 +353,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
     HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
     HIPCHK(launch_fill((u32*)(base + L.udig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
     if (dm.kara) HIPCHK(launch_fill((u32*)(base + L.kara_dig), 6 * L.kara_dig_bytes / 4, 0u, st));
+    if (dm.kara >= 2) HIPCHK(launch_fill((u32*)(base + L.kara_leaf), 18 * L.kara_leaf_bytes / 4, 0u, st));
   }
   HIPCHK(launch_scales(mu, mu_exp, w, dm.N, dm.E, out->s, dst, st));
   HIPCHK(launch_load(mu, mu_exp, w, out->s, dm, A, dst, st));
@@ -440,14 +453,19 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         m.carry_tiles = L.carry_tiles;
         m.timing = ctx->timing ? &ctx->t : nullptr;
         m.u_rows = dm.NT;
-        if (use_kara) {
+        if (kara_lv > 0) {
           KaraArgs ka{};
           ka.m = m;
-          for (int q = 0; q < 6; ++q) ka.dig[q] = (int8_t*)(base + L.kara_dig + q * L.kara_dig_bytes);
-          ka.Sk = dm.S / 2 + 1;
-          ka.kslices = L.kara_slices;
+          ka.levels = kara_lv;
+          ka.l1 = (int8_t*)(base + L.kara_dig);
+          ka.l1_stride = L.kara_dig_bytes;
+          ka.l1_slices = L.kara_slices;
+          ka.leaf = kara_lv == 1 ? ka.l1 : (int8_t*)(base + L.kara_leaf);
+          ka.leaf_stride = kara_lv == 1 ? L.kara_dig_bytes : L.kara_leaf_bytes;
+          ka.Sk = kara_leaf_digits(dm.S, kara_lv);
+          ka.kslices = ka.Sk + 2 * kDigitPad;
           ka.prod = (u32*)(base + L.kara_prod);
-          ka.nwp = L.kara_nwp;
+          ka.nwp = kara_nwp(dm.S, kara_lv);
           ka.prod_tiles = L.kara_tiles;
           e = launch_upd_kara(ka, st);
         } else {

@@ -9,7 +9,8 @@ constexpr int kMaxPrec = 57344;   // pivot kernel keeps ~9 (P/32 + 8) words in L
 constexpr int kDigitPad = 64;     // zero digit slices below 0 and above S-1
 constexpr int kMaxRanges = 64;    // output-limb ranges per tile in the MFMA updates
 constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
-constexpr int kKaraMinPrec = 4096; // Karatsuba form of the Schur update from this precision on (by default)
+constexpr int kKaraMinPrec = 8192;   // by default one Karatsuba level of the Schur update from this precision on
+constexpr int kKara2MinPrec = 24576; // and two levels from this one
 
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
@@ -31,10 +32,11 @@ struct Layout {
   int blk_stride;
   int blk_chunks;
   // Karatsuba form of the Schur update: six half-length digit panels
-  // (kara_slices slices each, kara_dig_bytes apart) and the three products
-  // (kara_tiles tiles of kara_nwp limbs per entry each)
-  size_t kara_dig, kara_dig_bytes, kara_prod, kara_tiles;
-  int kara_slices, kara_nwp;
+  // (kara_slices slices each, kara_dig_bytes apart), with two levels eighteen
+  // quarter-length ones (kara_leaf_slices, kara_leaf_bytes apart), and the
+  // products (3 or 9 x kara_tiles tiles)
+  size_t kara_dig, kara_dig_bytes, kara_leaf, kara_leaf_bytes, kara_prod, kara_tiles;
+  int kara_slices, kara_leaf_slices;
 };
 
 hl_status fail(hl_status s, const char* fmt, ...);

@@ -34,7 +34,7 @@ struct Dims {
   int E;         // exponent block
   int k;
   int W;         // 2P - 4
-  int kara;      // the Karatsuba form of the Schur update is available (MFMA form, P % 256 == 0)
+  int kara;      // Karatsuba levels of the Schur update available: 0, 1 (MFMA form, P % 256 == 0), 2 (P % 512 == 0)
 };
 
 // Trailing matrix: 32 x 32 tiles (R >= C) packed row by row; inside a tile the

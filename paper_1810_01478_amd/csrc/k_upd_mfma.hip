@@ -392,92 +392,173 @@ __global__ void k_kara_mid(const int8_t* __restrict__ lo, const int8_t* __restri
   }
 }
 
-// The three digit-sum GEMMs: work items (range rg, product p, tile lt) in that
-// order, dealt to the XCDs as in k_upd_mfma, so the waves of one XCD share a
-// range and a product and hold neighbouring tiles.
+// Slices [0, n) of the digit panel src (slice = digit + pad) go to lo below s
+// and to hi from s on (hi digit j - s); one thread per 16 bytes of a slice.
+__global__ void k_digit_split(const int8_t* __restrict__ src, int n, int s, int pad, int NT, int8_t* __restrict__ lo,
+                              int8_t* __restrict__ hi) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = (int)(gid / NT), row = (int)(gid % NT);
+  if (j >= n) return;
+  const size_t rs = (size_t)NT * 16;
+  const uint4 v = *(const uint4*)(src + (size_t)(pad + j) * rs + (size_t)row * 16);
+  int8_t* d = j < s ? lo + (size_t)(pad + j) * rs : hi + (size_t)(pad + j - s) * rs;
+  *(uint4*)(d + (size_t)row * 16) = v;
+}
+
+// The digit-sum GEMMs of the products: work items (range rg, product p, tile
+// lt) in that order, dealt to the XCDs as in k_upd_mfma, so the waves of one
+// XCD share a range and a product and hold neighbouring tiles.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_upd_kara(KaraArgs k, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   const UpdArgs& g = k.m.g;
+  const int np = k.levels == 1 ? 3 : 9;
   const int b = blockIdx.x;
   const int item = (b & 7) * per_xcd + (b >> 3);
-  if (item >= 3 * ntiles * rt.n) return;
-  const int rg = item / (3 * ntiles), rem = item - rg * 3 * ntiles;
+  if (item >= np * ntiles * rt.n) return;
+  const int rg = item / (np * ntiles), rem = item - rg * np * ntiles;
   const int p = rem / ntiles, lt = rem - p * ntiles;
   int R, C;
   item_tile(g, C_lo, lt, &R, &C);
   if (R * 32 >= k.m.NT) return;
-  const int8_t* bd = p == KA_LL ? k.dig[0] : (p == KA_HH ? k.dig[1] : k.dig[2]);
-  const int8_t* ud = p == KA_LL ? k.dig[3] : (p == KA_HH ? k.dig[4] : k.dig[5]);
-  mfma_tile_t<true>(g, bd, ud, k.kslices, k.Sk, k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
+  mfma_tile_t<true>(g, k.leaf + (size_t)p * k.leaf_stride, k.leaf + (size_t)(np + p) * k.leaf_stride, k.kslices,
+                    k.Sk, k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
                     k.m.carry + (((size_t)p * ntiles + lt) * rt.n + rg) * 1024,
                     k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp));
 }
 
-// a -= LL + X (MM - LL - HH) + X^2 HH for every live entry of the launch, with
-// X = 2^(32 H) (H = h/4 limbs, O = H/4 slabs): one thread per entry walks the
-// entry's slabs from the bottom with one signed running carry.  Each stored
-// product is exact only with the carries out of its ranges, which enter at the
-// first slab of the next range (the last one at the slab past the product: its
-// sign extension).
-__global__ __launch_bounds__(256) void k_kara_comb(KaraArgs k, RangeTab rt, int C_lo, int ntiles) {
-  __shared__ int tbs[MF_MAX_RANGES + 1];
-  for (int i = threadIdx.x; i <= rt.n; i += blockDim.x) tbs[i] = rt.tb[i];
-  __syncthreads();
+// The combination: a -= sum_p c_p(Y) P_p, as terms (product p, power of Y,
+// sign of the subtraction).  One level (Y = X): LL (1 - X), HH (X^2 - X), MM X.
+// Two levels: each parent's product c(X = Y^2) times its children's
+// (1 - Y), (Y^2 - Y), Y, products numbered 3 parent + child.
+struct KaTerm {
+  int p, pw, sg;
+};
+__device__ constexpr KaTerm kKaTerms1[5] = {{0, 0, -1}, {0, 1, 1}, {1, 1, 1}, {1, 2, -1}, {2, 1, -1}};
+__device__ constexpr KaTerm kKaTerms2[25] = {
+    // LL parent, c = 1 - Y^2
+    {0, 0, -1}, {0, 1, 1}, {0, 2, 1}, {0, 3, -1},    // LL_L: 1 - Y - Y^2 + Y^3
+    {1, 1, 1}, {1, 2, -1}, {1, 3, -1}, {1, 4, 1},    // LL_H: -Y + Y^2 + Y^3 - Y^4
+    {2, 1, -1}, {2, 3, 1},                           // LL_M: Y - Y^3
+    // HH parent, c = Y^4 - Y^2
+    {3, 2, 1}, {3, 3, -1}, {3, 4, -1}, {3, 5, 1},    // HH_L: -Y^2 + Y^3 + Y^4 - Y^5
+    {4, 3, -1}, {4, 4, 1}, {4, 5, 1}, {4, 6, -1},    // HH_H: Y^3 - Y^4 - Y^5 + Y^6
+    {5, 3, 1}, {5, 5, -1},                           // HH_M: -Y^3 + Y^5
+    // MM parent, c = Y^2
+    {6, 2, -1}, {6, 3, 1},                           // MM_L: Y^2 - Y^3
+    {7, 3, 1}, {7, 4, -1},                           // MM_H: -Y^3 + Y^4
+    {8, 3, -1}};                                     // MM_M: Y^3
+
+// the live entry (r, c) of launch tile lt, or false
+__device__ __forceinline__ bool kara_entry(const KaraArgs& k, int C_lo, int lt, int e, int* R, int* C) {
   const UpdArgs& g = k.m.g;
-  const int lt = blockIdx.x >> 2, e = (blockIdx.x & 3) * 256 + threadIdx.x;
+  item_tile(g, C_lo, lt, R, C);
+  if (*R * 32 >= k.m.NT) return false;
+  const int rg = *R * 32 + (e >> 5), cg = *C * 32 + (e & 31);
+  return (!g.tri || rg >= cg) && rg >= g.r_lo && rg < g.r_hi && cg >= g.c_lo && cg < g.c_hi;
+}
+
+// Add the carries out of all but the last range of product blockIdx.y at the
+// first limb of the next range, for every live entry (one thread each).  The
+// product then holds its exact value modulo 2^(32 nwp); it is far below
+// 2^(32 nwp - 1) in magnitude, so its top slab read as a signed 128-bit
+// number gives the exact value, and the last range's carry (its sign
+// extension) is not needed.
+__global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C_lo, int ntiles) {
+  const int lt = blockIdx.x >> 2, e = (blockIdx.x & 3) * 256 + threadIdx.x, p = blockIdx.y;
   int R, C;
-  item_tile(g, C_lo, lt, &R, &C);
-  if (R * 32 >= k.m.NT) return;
+  if (!kara_entry(k, C_lo, lt, e, &R, &C) || has_error(k.m.g.st)) return;
   const int r = e >> 5, c = e & 31;
-  {
-    const int rg = R * 32 + r, cg = C * 32 + c;
-    if (!((!g.tri || rg >= cg) && rg >= g.r_lo && rg < g.r_hi && cg >= g.c_lo && cg < g.c_hi)) return;
+  u32* Q = k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp);
+  const long long* cb = k.m.carry + ((size_t)p * ntiles + lt) * rt.n * 1024 + e;
+  for (int w = 0; w + 1 < rt.n; ++w) {
+    const i64 cv = cb[(size_t)w * 1024];
+    if (cv == 0) continue;
+    int li = MF_LPB * rt.tb[w + 1];
+    // the sign-extended cv at limb li (two limbs), then the carry or borrow on up
+    u32* p0 = Q + in_tile(r, c, li);
+    const u64 x0 = ((u64)p0[1] << 32) | p0[0];
+    const u64 y0 = x0 + (u64)cv;
+    p0[0] = (u32)y0;
+    p0[1] = (u32)(y0 >> 32);
+    const u64 add = (cv < 0 ? ~0ull : 0ull) + (y0 < x0 ? 1ull : 0ull);  // 0, 1 or ~0
+    if (add == 0) continue;
+    for (li += 2; li < k.nwp; li += 2) {
+      u32* q = Q + in_tile(r, c, li);
+      const u64 x = ((u64)q[1] << 32) | q[0];
+      const u64 y = x + add;
+      q[0] = (u32)y;
+      q[1] = (u32)(y >> 32);
+      if (add == 1 ? (y != 0) : (x != 0)) break;
+    }
   }
-  if (has_error(g.st)) return;
-  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
-  u32* At = g.A + tix * tile_words(g.nw);
-  const size_t tw = tile_words(k.nwp);
-  const u32* QL = k.prod + ((size_t)KA_LL * k.prod_tiles + lt) * tw;
-  const u32* QH = k.prod + ((size_t)KA_HH * k.prod_tiles + lt) * tw;
-  const u32* QM = k.prod + ((size_t)KA_MM * k.prod_tiles + lt) * tw;
-  const long long* cL = k.m.carry + ((size_t)KA_LL * ntiles + lt) * rt.n * 1024 + e;
-  const long long* cH = k.m.carry + ((size_t)KA_HH * ntiles + lt) * rt.n * 1024 + e;
-  const long long* cM = k.m.carry + ((size_t)KA_MM * ntiles + lt) * rt.n * 1024 + e;
-  const int O = k.m.S / 32;  // h / 16
-  const int nsl = g.nw / 4, nq = k.nwp / 4, nr = rt.n;
-  int w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0;
-  i64 cy = 0;
-  for (int j = 0; j < nsl; ++j) {
-    const uint4 a = *(const uint4*)(At + in_tile(r, c, 4 * j));
+}
+
+// Slabs [K O, (K + 1) O) of an entry (segment K; Y is O slabs, every product
+// 2 O + 1 slabs, its top one signed).  Term t adds product slab q = j - pw O:
+// whole for K - pw in {0, 1}, and its top slab (q = 2 O) at the first slab of
+// the segment for K - pw = 2, so the terms of a segment are fixed and all
+// their loads of a slab are in flight together.
+template <int LV, int K>
+__device__ __forceinline__ void kara_comb_seg(u32* At, const u32* Q0, size_t pst, int O, int r, int c, i64& cy) {
+  constexpr int NTERM = LV == 1 ? 5 : 25;
+  for (int jj = 0; jj < O; ++jj) {
+    const int j = K * O + jj;
+    uint4* pa = (uint4*)(At + in_tile(r, c, 4 * j));
+    const uint4 a = *pa;
+    uint4 v[NTERM];
+#pragma unroll
+    for (int t = 0; t < NTERM; ++t) {
+      const KaTerm T = LV == 1 ? kKaTerms1[t] : kKaTerms2[t];
+      const int d = K - T.pw;
+      if (d == 0 || d == 1 || (d == 2 && jj == 0))
+        v[t] = *(const uint4*)(Q0 + (size_t)T.p * pst + (size_t)(j - T.pw * O) * 4096);
+    }
     i64 s0 = a.x, s1 = a.y, s2 = a.z, s3 = a.w;
-    auto term = [&](const u32* Q, const long long* cq, int off, bool add, int& w) {
-      const int q = j - off;
-      if (q >= 0 && q < nq) {
-        const uint4 v = *(const uint4*)(Q + in_tile(r, c, 4 * q));
-        if (add) {
-          s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
+#pragma unroll
+    for (int t = 0; t < NTERM; ++t) {
+      const KaTerm T = LV == 1 ? kKaTerms1[t] : kKaTerms2[t];
+      const int d = K - T.pw;
+      if (d == 0 || d == 1 || (d == 2 && jj == 0)) {
+        const i64 top = d == 2 ? (i64)(int)v[t].w : (i64)v[t].w;
+        if (T.sg > 0) {
+          s0 += v[t].x; s1 += v[t].y; s2 += v[t].z; s3 += top;
         } else {
-          s0 -= v.x; s1 -= v.y; s2 -= v.z; s3 -= v.w;
+          s0 -= v[t].x; s1 -= v[t].y; s2 -= v[t].z; s3 -= top;
         }
       }
-      if (w < nr && q == tbs[w + 1]) {
-        const i64 cv = cq[(size_t)w * 1024];
-        s0 += add ? cv : -cv;
-        ++w;
-      }
-    };
-    term(QL, cL, 0, false, w0);
-    term(QM, cM, O, false, w1);
-    term(QL, cL, O, true, w2);
-    term(QH, cH, O, true, w3);
-    term(QH, cH, 2 * O, false, w4);
+    }
     s0 += cy;
     s1 += s0 >> 32;
     s2 += s1 >> 32;
     s3 += s2 >> 32;
     cy = s3 >> 32;
-    *(uint4*)(At + in_tile(r, c, 4 * j)) = make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
+    *pa = make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
   }
+}
+
+template <int LV, int K>
+__device__ __forceinline__ void kara_comb_segs(u32* At, const u32* Q0, size_t pst, int O, int r, int c, i64& cy) {
+  if constexpr (K < (LV == 1 ? 4 : 8)) {
+    kara_comb_seg<LV, K>(At, Q0, pst, O, r, c, cy);
+    kara_comb_segs<LV, K + 1>(At, Q0, pst, O, r, c, cy);
+  }
+}
+
+// a -= sum_p c_p(Y) P_p for every live entry of the launch: one thread per
+// entry walks the entry's 4 (one level) or 8 (two) segments of O slabs from
+// the bottom with one signed running carry.
+template <int LV>
+__global__ __launch_bounds__(256) void k_kara_comb(KaraArgs k, int C_lo) {
+  const UpdArgs& g = k.m.g;
+  const int lt = blockIdx.x >> 2, e = (blockIdx.x & 3) * 256 + threadIdx.x;
+  int R, C;
+  if (!kara_entry(k, C_lo, lt, e, &R, &C) || has_error(g.st)) return;
+  const int r = e >> 5, c = e & 31;
+  const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
+  const size_t tw = tile_words(k.nwp);
+  i64 cy = 0;
+  kara_comb_segs<LV, 0>(g.A + tix * tile_words(g.nw), k.prod + (size_t)lt * tw + in_tile(r, c, 0),
+                        k.prod_tiles * tw, k.m.S / (LV == 1 ? 32 : 64), r, c, cy);
 }
 
 // ---------------------------------------------------------------------------
@@ -642,20 +723,43 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
   const UpdArgs& g = m.g;
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
   if (!g.tri || (g.rsb != 0 && g.rsb != (size_t)g.nl)) return hipErrorInvalidValue;
-  const int h = m.S / 2;
-  if (m.S % 32 || m.S != 4 * g.nl || k.Sk != h + 1 || k.nwp != kara_nwp(m.S) || m.pad < MF_PAD_MIN ||
-      k.kslices != k.Sk + 2 * m.pad || (size_t)k.kslices * m.NT * 16 > 0x7fffffffu)
-    return hipErrorInvalidValue;  // halves of whole 4-limb slabs, padding, 32-bit buffer offsets
+  const int h = m.S / 2, s2 = m.S / 4;
+  const int np = k.levels == 1 ? 3 : 9;
+  // halves (and quarters) of whole 4-limb slabs, padding, 32-bit buffer offsets
+  if ((k.levels != 1 && k.levels != 2) || m.S % (k.levels == 1 ? 32 : 64) || m.S != 4 * g.nl ||
+      k.Sk != kara_leaf_digits(m.S, k.levels) || k.nwp != kara_nwp(m.S, k.levels) || m.pad < MF_PAD_MIN ||
+      k.kslices != k.Sk + 2 * m.pad || k.l1_slices != h + 1 + 2 * m.pad ||
+      k.nwp / 4 != 2 * (m.S / (k.levels == 1 ? 32 : 64)) + 1 ||
+      (size_t)k.l1_slices * m.NT * 16 > 0x7fffffffu)
+    return hipErrorInvalidValue;
   const size_t rthreads = (size_t)g.nl * m.NT * 16;
   const unsigned rblocks = (unsigned)((rthreads + 255) / 256);
+  int8_t* l1[6];
+  for (int q = 0; q < 6; ++q) l1[q] = k.l1 + (size_t)q * k.l1_stride;
   hipLaunchKernelGGL(k_recode_kara, dim3(rblocks), dim3(256), 0, stream, g.Bop, g.ldb, g.npan, m.NT, m.NT, g.nl,
-                     m.pad, h / 4, k.dig[0], k.dig[1]);
+                     m.pad, h / 4, l1[0], l1[1]);
   hipLaunchKernelGGL(k_recode_kara, dim3(rblocks), dim3(256), 0, stream, g.Uop, g.ldu, g.npan, m.NT, m.u_rows,
-                     g.nl, m.pad, h / 4, k.dig[3], k.dig[4]);
-  const size_t mthreads = (size_t)(h / 4 + 1) * m.NT * 16;
-  const unsigned mblocks = (unsigned)((mthreads + 255) / 256);
-  hipLaunchKernelGGL(k_kara_mid, dim3(mblocks), dim3(256), 0, stream, k.dig[0], k.dig[1], m.NT, m.pad, h, k.dig[2]);
-  hipLaunchKernelGGL(k_kara_mid, dim3(mblocks), dim3(256), 0, stream, k.dig[3], k.dig[4], m.NT, m.pad, h, k.dig[5]);
+                     g.nl, m.pad, h / 4, l1[3], l1[4]);
+  auto mid = [&](const int8_t* lo, const int8_t* hi, int hh, int8_t* out) {
+    const size_t threads = (size_t)(hh / 4 + 1) * m.NT * 16;
+    hipLaunchKernelGGL(k_kara_mid, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, lo, hi, m.NT, m.pad,
+                       hh, out);
+  };
+  mid(l1[0], l1[1], h, l1[2]);
+  mid(l1[3], l1[4], h, l1[5]);
+  if (k.levels == 2) {
+    // each level-1 operand (h digits, h + 1 for the mids) splits at s2
+    for (int x = 0; x < 6; ++x) {
+      const int side = x / 3, par = x % 3;
+      const int n = par == KA_MM ? h + 1 : h;
+      int8_t* lo = k.leaf + (size_t)(side * 9 + 3 * par) * k.leaf_stride;
+      int8_t* hi = lo + k.leaf_stride;
+      const size_t threads = (size_t)n * m.NT;
+      hipLaunchKernelGGL(k_digit_split, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, l1[x], n, s2,
+                         m.pad, m.NT, lo, hi);
+      mid(lo, hi, n - s2, hi + k.leaf_stride);
+    }
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nt = m.NT / 32;
@@ -663,15 +767,15 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
   const int ncol = nt - C_lo;
   const int ntiles = ncol * (ncol + 1) / 2;
   if ((size_t)ntiles > k.prod_tiles) return hipErrorInvalidValue;
-  const RangeTab rt = make_ranges_ntb(k.nwp / 4, k.Sk, 3L * ntiles, m.max_ranges, m.carry_tiles);
-  if ((size_t)3 * ntiles * rt.n > m.carry_tiles) return hipErrorInvalidValue;
+  const RangeTab rt = make_ranges_ntb(k.nwp / 4, k.Sk, (long)np * ntiles, m.max_ranges, m.carry_tiles);
+  if ((size_t)np * ntiles * rt.n > m.carry_tiles) return hipErrorInvalidValue;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (m.timing) {
     (void)hipEventCreate(&ev0);
     (void)hipEventCreate(&ev1);
     (void)hipEventRecord(ev0, stream);
   }
-  const long items = 3L * ntiles * rt.n;
+  const long items = (long)np * ntiles * rt.n;
   const int per_xcd = (int)((items + 7) / 8);
   hipLaunchKernelGGL(k_upd_kara, dim3(8 * per_xcd), dim3(64), 0, stream, k, rt, C_lo, ntiles, per_xcd);
   e = hipGetLastError();
@@ -683,10 +787,15 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
     m.timing->ms[6] += ms;
     m.timing->launches[1] += 1;
     m.timing->launches[2] += 1;
+    if (k.levels == 2) m.timing->launches[3] += 1;
     (void)hipEventRecord(ev0, stream);
   }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_kara_comb, dim3(4 * ntiles), dim3(256), 0, stream, k, rt, C_lo, ntiles);
+  if (rt.n > 1) hipLaunchKernelGGL(k_kara_fix, dim3(4 * ntiles, np), dim3(256), 0, stream, k, rt, C_lo, ntiles);
+  if (k.levels == 1)
+    hipLaunchKernelGGL(k_kara_comb<1>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+  else
+    hipLaunchKernelGGL(k_kara_comb<2>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
   e = hipGetLastError();
   if (m.timing) {
     (void)hipEventRecord(ev1, stream);

@@ -174,13 +174,15 @@ def test_mfma_equals_valu_bitwise_c2b_shape():
     (Fraction(1, 3), 20, 256, 1),     # shortest halves: 16 digits, one slab
     (1, 97, 3072, 4),
 ])
-def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E):
-    # the Karatsuba form of the trailing update is exact: same bits as the oracle
-    say("factor karatsuba", beta, N, P, E)
+@pytest.mark.parametrize("levels", [1, 2])
+def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E, levels):
+    # the Karatsuba forms of the trailing update are exact: same bits as the
+    # oracle (two levels need P % 512 == 0; P = 256 runs one)
+    say("factor karatsuba", beta, N, P, E, levels)
     mu = moments(beta, 2 * N - 1)
     f = C.factor(mu, N, P, E)
     c = ctx()
-    c.set_karatsuba(1)
+    c.set_karatsuba(levels)
     try:
         fac = c.factor(mu, N, 8, P, E, "mfma")
         c.sync(fac)
@@ -190,34 +192,38 @@ def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E):
 
 
 def test_karatsuba_equals_digit_product_c2b_shape():
-    # beta = 1/2, N = 256 at 8192 bits, and a continuation in pieces that
-    # switches form between pieces: all give the same bits
+    # beta = 1/2, N = 256 at 8192 bits: the digit product, one and two Karatsuba
+    # levels, and a continuation in pieces that switches form between pieces,
+    # all give the same bits
     import torch
     N, P = 256, 8192
     say("karatsuba vs digit product", N, P)
     mu = moments(Fraction(1, 2), 2 * N - 1)
     c = ctx()
+    got = []
     try:
         c.set_karatsuba(0)
         fa = c.factor(mu, N, 8, P, 16, "mfma")
         c.sync(fa)
-        c.set_karatsuba(1)
-        fb = c.factor(mu, N, 8, P, 16, "mfma")
-        c.sync(fb)
+        for lv in (1, 2):
+            c.set_karatsuba(lv)
+            fb = c.factor(mu, N, 8, P, 16, "mfma")
+            c.sync(fb)
+            got.append(fb)
         fc = c.factor_cols(mu, N, 8, P, 16, "mfma", 0, 96)
-        c.set_karatsuba(0)
-        c.factor_cols(mu, N, 8, P, 16, "mfma", 96, 160, fac=fc)
-        c.set_karatsuba(1)
-        c.factor_cols(mu, N, 8, P, 16, "mfma", 160, N, fac=fc)
+        for lv, (c0, c1) in zip((0, 1, 2), ((96, 160), (160, 208), (208, N))):
+            c.set_karatsuba(lv)
+            c.factor_cols(mu, N, 8, P, 16, "mfma", c0, c1, fac=fc)
         c.sync(fc)
+        got.append(fc)
     finally:
         c.set_karatsuba(-1)
-    for f in (fb, fc):
+    for f in got:
         assert torch.equal(fa.d, f.d) and torch.equal(fa.l, f.l) and torch.equal(fa.h, f.h)
 
 
 def test_set_karatsuba_rejects_bad_mode():
     from paper_1810_01478_amd._lib import HLError, HL_EINVAL
     with pytest.raises(HLError) as e:
-        ctx().set_karatsuba(2)
+        ctx().set_karatsuba(3)
     assert e.value.code == HL_EINVAL
