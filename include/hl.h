@@ -165,7 +165,7 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
  *            carries;
  *         2: two levels (P a multiple of 512): nine GEMMs of (S/4 + 2)-digit
  *            operands (9/16 of the multiply-adds);
- *        -1 (default): 2 from P = 24576 on, 1 from P = 8192 on, else 0.
+ *        -1 (default): 2 from P = 16384 on, 1 from P = 8192 on, else 0.
  * A mode beyond what P allows runs the deepest allowed one.  Applies to later
  * hl_factor / hl_factor_cols calls on this context (modes may be mixed within
  * one factorisation).  HL_EINVAL for another mode.

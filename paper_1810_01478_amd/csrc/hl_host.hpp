@@ -10,7 +10,7 @@ constexpr int kDigitPad = 64;     // zero digit slices below 0 and above S-1
 constexpr int kMaxRanges = 64;    // output-limb ranges per tile in the MFMA updates
 constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 constexpr int kKaraMinPrec = 8192;   // by default one Karatsuba level of the Schur update from this precision on
-constexpr int kKara2MinPrec = 24576; // and two levels from this one
+constexpr int kKara2MinPrec = 16384; // and two levels from this one
 
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;

@@ -457,6 +457,27 @@ __device__ __forceinline__ bool kara_entry(const KaraArgs& k, int C_lo, int lt, 
   return (!g.tri || rg >= cg) && rg >= g.r_lo && rg < g.r_hi && cg >= g.c_lo && cg < g.c_hi;
 }
 
+// add the sign-extended value cv at limb li (even) of the entry at w (limbs
+// word-addressed by in_tile), the carry or borrow running on up to limb nw
+__device__ __forceinline__ void add_at_limb(u32* w, int r, int c, int li, int nw, i64 cv) {
+  if (cv == 0 || li >= nw) return;
+  u32* p0 = w + in_tile(r, c, li);
+  const u64 x0 = ((u64)p0[1] << 32) | p0[0];
+  const u64 y0 = x0 + (u64)cv;
+  p0[0] = (u32)y0;
+  p0[1] = (u32)(y0 >> 32);
+  const u64 add = (cv < 0 ? ~0ull : 0ull) + (y0 < x0 ? 1ull : 0ull);  // 0, 1 or ~0
+  if (add == 0) return;
+  for (li += 2; li < nw; li += 2) {
+    u32* q = w + in_tile(r, c, li);
+    const u64 x = ((u64)q[1] << 32) | q[0];
+    const u64 y = x + add;
+    q[0] = (u32)y;
+    q[1] = (u32)(y >> 32);
+    if (add == 1 ? (y != 0) : (x != 0)) break;
+  }
+}
+
 // Add the carries out of all but the last range of product blockIdx.y at the
 // first limb of the next range, for every live entry (one thread each).  The
 // product then holds its exact value modulo 2^(32 nwp); it is far below
@@ -470,95 +491,73 @@ __global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C
   const int r = e >> 5, c = e & 31;
   u32* Q = k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp);
   const long long* cb = k.m.carry + ((size_t)p * ntiles + lt) * rt.n * 1024 + e;
-  for (int w = 0; w + 1 < rt.n; ++w) {
-    const i64 cv = cb[(size_t)w * 1024];
-    if (cv == 0) continue;
-    int li = MF_LPB * rt.tb[w + 1];
-    // the sign-extended cv at limb li (two limbs), then the carry or borrow on up
-    u32* p0 = Q + in_tile(r, c, li);
-    const u64 x0 = ((u64)p0[1] << 32) | p0[0];
-    const u64 y0 = x0 + (u64)cv;
-    p0[0] = (u32)y0;
-    p0[1] = (u32)(y0 >> 32);
-    const u64 add = (cv < 0 ? ~0ull : 0ull) + (y0 < x0 ? 1ull : 0ull);  // 0, 1 or ~0
-    if (add == 0) continue;
-    for (li += 2; li < k.nwp; li += 2) {
-      u32* q = Q + in_tile(r, c, li);
-      const u64 x = ((u64)q[1] << 32) | q[0];
-      const u64 y = x + add;
-      q[0] = (u32)y;
-      q[1] = (u32)(y >> 32);
-      if (add == 1 ? (y != 0) : (x != 0)) break;
-    }
-  }
+  for (int w = 0; w + 1 < rt.n; ++w) add_at_limb(Q, r, c, MF_LPB * rt.tb[w + 1], k.nwp, cb[(size_t)w * 1024]);
 }
 
-// Slabs [K O, (K + 1) O) of an entry (segment K; Y is O slabs, every product
-// 2 O + 1 slabs, its top one signed).  Term t adds product slab q = j - pw O:
-// whole for K - pw in {0, 1}, and its top slab (q = 2 O) at the first slab of
-// the segment for K - pw = 2, so the terms of a segment are fixed and all
-// their loads of a slab are in flight together.
-template <int LV, int K>
-__device__ __forceinline__ void kara_comb_seg(u32* At, const u32* Q0, size_t pst, int O, int r, int c, i64& cy) {
-  constexpr int NTERM = LV == 1 ? 5 : 25;
-  for (int jj = 0; jj < O; ++jj) {
-    const int j = K * O + jj;
-    uint4* pa = (uint4*)(At + in_tile(r, c, 4 * j));
-    const uint4 a = *pa;
-    uint4 v[NTERM];
-#pragma unroll
-    for (int t = 0; t < NTERM; ++t) {
-      const KaTerm T = LV == 1 ? kKaTerms1[t] : kKaTerms2[t];
-      const int d = K - T.pw;
-      if (d == 0 || d == 1 || (d == 2 && jj == 0))
-        v[t] = *(const uint4*)(Q0 + (size_t)T.p * pst + (size_t)(j - T.pw * O) * 4096);
-    }
-    i64 s0 = a.x, s1 = a.y, s2 = a.z, s3 = a.w;
-#pragma unroll
-    for (int t = 0; t < NTERM; ++t) {
-      const KaTerm T = LV == 1 ? kKaTerms1[t] : kKaTerms2[t];
-      const int d = K - T.pw;
-      if (d == 0 || d == 1 || (d == 2 && jj == 0)) {
-        const i64 top = d == 2 ? (i64)(int)v[t].w : (i64)v[t].w;
-        if (T.sg > 0) {
-          s0 += v[t].x; s1 += v[t].y; s2 += v[t].z; s3 += top;
-        } else {
-          s0 -= v[t].x; s1 -= v[t].y; s2 -= v[t].z; s3 -= top;
-        }
-      }
-    }
-    s0 += cy;
-    s1 += s0 >> 32;
-    s2 += s1 >> 32;
-    s3 += s2 >> 32;
-    cy = s3 >> 32;
-    *pa = make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
-  }
-}
-
-template <int LV, int K>
-__device__ __forceinline__ void kara_comb_segs(u32* At, const u32* Q0, size_t pst, int O, int r, int c, i64& cy) {
-  if constexpr (K < (LV == 1 ? 4 : 8)) {
-    kara_comb_seg<LV, K>(At, Q0, pst, O, r, c, cy);
-    kara_comb_segs<LV, K + 1>(At, Q0, pst, O, r, c, cy);
-  }
-}
-
-// a -= sum_p c_p(Y) P_p for every live entry of the launch: one thread per
-// entry walks the entry's 4 (one level) or 8 (two) segments of O slabs from
-// the bottom with one signed running carry.
+// a -= sum_p c_p(Y) P_p for every live entry of the launch, one thread per
+// entry.  Y is O slabs, the entry 4 (one level) or 8 (two) segments of O slabs,
+// every product 2 O + 1 slabs with a signed top slab.  Output slab m O + jj
+// takes, from term t, product slab (m - pw) O + jj: slab jj for m = pw, O + jj for
+// m = pw + 1, and the top slab 2 O at jj = 0 for m = pw + 2.  So the thread
+// walks jj, reads the two slabs jj and O + jj of every product once, and updates
+// slab jj of every segment, each segment with its own running carry; at the end
+// the carry out of segment m enters at its successor's first slab.
 template <int LV>
 __global__ __launch_bounds__(256) void k_kara_comb(KaraArgs k, int C_lo) {
+  constexpr int NTERM = LV == 1 ? 5 : 25;
+  constexpr int NP = LV == 1 ? 3 : 9;
+  constexpr int NSEG = LV == 1 ? 4 : 8;
   const UpdArgs& g = k.m.g;
   const int lt = blockIdx.x >> 2, e = (blockIdx.x & 3) * 256 + threadIdx.x;
   int R, C;
   if (!kara_entry(k, C_lo, lt, e, &R, &C) || has_error(g.st)) return;
   const int r = e >> 5, c = e & 31;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
-  const size_t tw = tile_words(k.nwp);
-  i64 cy = 0;
-  kara_comb_segs<LV, 0>(g.A + tix * tile_words(g.nw), k.prod + (size_t)lt * tw + in_tile(r, c, 0),
-                        k.prod_tiles * tw, k.m.S / (LV == 1 ? 32 : 64), r, c, cy);
+  const size_t tw = tile_words(k.nwp), pst = k.prod_tiles * tw;
+  u32* At = g.A + tix * tile_words(g.nw);
+  const u32* Q0 = k.prod + (size_t)lt * tw + in_tile(r, c, 0);
+  const int O = k.m.S / (LV == 1 ? 32 : 64);
+  i64 cy[NSEG];
+#pragma unroll
+  for (int m = 0; m < NSEG; ++m) cy[m] = 0;
+  for (int jj = 0; jj < O; ++jj) {
+    uint4 lo[NP], hi[NP], top[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      lo[p] = *(const uint4*)(Q0 + (size_t)p * pst + (size_t)jj * 4096);
+      hi[p] = *(const uint4*)(Q0 + (size_t)p * pst + (size_t)(O + jj) * 4096);
+      if (jj == 0) top[p] = *(const uint4*)(Q0 + (size_t)p * pst + (size_t)(2 * O) * 4096);
+    }
+#pragma unroll
+    for (int m = 0; m < NSEG; ++m) {
+      uint4* pa = (uint4*)(At + in_tile(r, c, 4 * (m * O + jj)));
+      const uint4 a = *pa;
+      i64 s0 = a.x, s1 = a.y, s2 = a.z, s3 = a.w;
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t) {
+        const KaTerm T = LV == 1 ? kKaTerms1[t] : kKaTerms2[t];
+        const int d = m - T.pw;
+        if (d == 0 || d == 1 || (d == 2 && jj == 0)) {
+          const uint4 v = d == 0 ? lo[T.p] : (d == 1 ? hi[T.p] : top[T.p]);
+          const i64 v3 = d == 2 ? (i64)(int)v.w : (i64)v.w;
+          if (T.sg > 0) {
+            s0 += v.x; s1 += v.y; s2 += v.z; s3 += v3;
+          } else {
+            s0 -= v.x; s1 -= v.y; s2 -= v.z; s3 -= v3;
+          }
+        }
+      }
+      s0 += cy[m];
+      s1 += s0 >> 32;
+      s2 += s1 >> 32;
+      s3 += s2 >> 32;
+      cy[m] = s3 >> 32;
+      *pa = make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
+    }
+  }
+  // carries between segments (the last one leaves the entry)
+#pragma unroll
+  for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy[m]);
 }
 
 // ---------------------------------------------------------------------------
