@@ -19,6 +19,10 @@ struct hl_ctx {
   int device = 0;
   int timing = 0;
   int karatsuba = -1;  // Schur update form for MFMA shapes: -1 by precision, else Karatsuba levels (0 = digit product)
+  // pivot lookahead of the MFMA form: a second stream (default priority) and
+  // the events joining it to the caller's
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_col = nullptr, ev_piv = nullptr;
   hl_timing_t t{};
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -252,6 +256,9 @@ extern "C" hl_status hl_create(hl_ctx** ctx, int device) {
 extern "C" hl_status hl_destroy(hl_ctx* ctx) {
   if (!ctx) return HL_OK;
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->ev_col) (void)hipEventDestroy(ctx->ev_col);
+  if (ctx->ev_piv) (void)hipEventDestroy(ctx->ev_piv);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   delete ctx;
   return HL_OK;
 }
@@ -361,12 +368,25 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   }
 
   const size_t ldb = (size_t)dm.NT * dm.nl;
+  // MFMA form: pivot i + 1 runs on the aux stream while column i's in-panel
+  // update runs on the caller's; it subtracts b_{i+1} u_{i+1} itself, so that
+  // update leaves out the diagonal row i + 1
+  const bool look = sh->form == HL_FORM_MFMA8;
+  if (look && !ctx->aux) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_col, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_piv, hipEventDisableTiming));
+  }
   for (int i0 = col_begin; i0 < col_end; i0 += 16) {
     const int npan = dm.N - i0 < 16 ? dm.N - i0 : 16;
     Stamp pn(ctx, st, 1);
     for (int il = 0; il < npan; ++il) {
       const int i = i0 + il;
-      HIPCHK(launch_pivot(A, dm, i, out->d, out->h, omega, L.omega_stride, dst, st));
+      if (!look || il == 0) {
+        HIPCHK(launch_pivot(A, dm, i, out->d, out->h, omega, L.omega_stride, dst, st));
+      } else {
+        HIPCHK(hipStreamWaitEvent(st, ctx->ev_piv, 0));
+      }
       if (sh->form == HL_FORM_MFMA8) {
         u32* ucol = up + (size_t)il * ldb;
         u32* P = (u32*)(base + L.colprod);
@@ -398,6 +418,14 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
                           out->l + (size_t)i * ldb, dst, st));
       }
       if (il + 1 < npan) {
+        if (look) {
+          HIPCHK(hipEventRecord(ctx->ev_col, st));
+          HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_col, 0));
+          HIPCHK(launch_pivot(A, dm, i + 1, out->d, out->h, omega, L.omega_stride, dst, ctx->aux,
+                              out->l + (size_t)i * ldb + (size_t)(i + 1) * dm.nl,
+                              up + (size_t)il * ldb + (size_t)(i + 1) * dm.nl));
+          HIPCHK(hipEventRecord(ctx->ev_piv, ctx->aux));
+        }
         UpdArgs g{};
         g.A = A;
         g.tri = 1;
@@ -408,7 +436,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         g.Uop = up + (size_t)il * ldb;
         g.ldu = ldb;
         g.npan = 1;
-        g.r_lo = i + 1;
+        g.r_lo = look ? i + 2 : i + 1;
         g.r_hi = dm.N;
         g.c_lo = i + 1;
         g.c_hi = i0 + npan;

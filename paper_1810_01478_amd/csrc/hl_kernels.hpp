@@ -14,7 +14,7 @@ hipError_t launch_scales(const u32* mu, const i64* mu_exp, int w, int N, int E, 
 hipError_t launch_load(const u32* mu, const i64* mu_exp, int w, const i32* s, const Dims& dm, u32* A,
                        DevStatus* st, hipStream_t stream);
 hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
-                        DevStatus* st, hipStream_t stream);
+                        DevStatus* st, hipStream_t stream, const u32* sub_b = nullptr, const u32* sub_u = nullptr);
 hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
                       int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
 hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream);
@@ -35,6 +35,11 @@ struct PivotArgs {
   u32* omega;
   int ostride;
   DevStatus* st;
+  // optional (both or neither): the pivot is a_ii - sub_b sub_u, the previous
+  // column's update of the diagonal entry, which the caller left out of that
+  // column's in-panel update (nl limbs each, two's complement)
+  const u32* sub_b = nullptr;
+  const u32* sub_u = nullptr;
 };
 struct ColArgs {
   const u32* A;

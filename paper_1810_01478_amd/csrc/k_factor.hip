@@ -256,6 +256,30 @@ __device__ void pivot_body(const PivotArgs& a) {
   const u32* src = A + tri_tile_index(i >> 5, i >> 5) * tile_words(nw);
   for (int l = threadIdx.x; l < nw; l += blockDim.x) dl[l] = src[in_tile(i, i, l)];
   __syncthreads();
+  if (a.sub_b) {
+    // a_ii - b u, exact: |b| |u| by the workgroup product, then subtracted or
+    // added by the signs (the scratch regions of the reciprocal are free here)
+    const int NB = nl + 8;
+    u32* Bs = lds;            // |b|
+    u32* Us = lds + NB;       // |u|
+    u32* Pt = lds + 2 * NB;   // |b u| (2 NB)
+    u32* buf = lds + 9 * NB;  // 6 NB: product scratch and carry chains
+    for (int l = threadIdx.x; l < NB; l += blockDim.x) {
+      Bs[l] = l < nl ? a.sub_b[l] : 0u;
+      Us[l] = l < nl ? a.sub_u[l] : 0u;
+    }
+    __syncthreads();
+    const bool nb = (Bs[nl - 1] >> 31) != 0, nu = (Us[nl - 1] >> 31) != 0;
+    __syncthreads();
+    if (nb) wg_neg(Bs, nl, buf);
+    if (nu) wg_neg(Us, nl, buf);
+    pv_mul(Bs, nl, Us, nl, Pt, nw, buf, (size_t)6 * NB * 4);
+    if (nb == nu) {
+      wg_sub(dl, Pt, dl, nw, buf);
+    } else {
+      wg_add(dl, nw, Pt, nw, dl, nw, buf);
+    }
+  }
   const bool neg = (dl[nw - 1] >> 31) != 0;
   if (neg || w_is_zero(dl, nw)) {
     if (threadIdx.x == 0) set_status(st, HL_ENOTPD, i);
@@ -517,10 +541,11 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
 }
 
 hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
-                        DevStatus* st, hipStream_t stream) {
+                        DevStatus* st, hipStream_t stream, const u32* sub_b, const u32* sub_u) {
   hipError_t e = allow_lds((const void*)k_pivot, pivot_lds_bytes(dm.nl));
   if (e != hipSuccess) return e;
-  const PivotArgs a{A, dm, i, d_out, h_out, omega, ostride, st};
+  if ((sub_b == nullptr) != (sub_u == nullptr)) return hipErrorInvalidValue;
+  const PivotArgs a{A, dm, i, d_out, h_out, omega, ostride, st, sub_b, sub_u};
   hipLaunchKernelGGL(k_pivot, dim3(1), dim3(PIVOT_THREADS), pivot_lds_bytes(dm.nl), stream, a);
   return hipGetLastError();
 }
