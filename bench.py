@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (d lambda_1 / d beta)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance workload")
-    ap.add_argument("--karatsuba", default="auto", choices=["auto", "0", "1", "2"],
+    ap.add_argument("--karatsuba", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="Schur-update form of the MFMA path: Karatsuba levels (0: the plain digit product)")
     ap.add_argument("--cpu-rows", type=int, default=48)
     ap.add_argument("--progress", action="store_true",
@@ -202,7 +202,7 @@ def main():
     }
     lv = 0
     if a.form == "mfma" and stages["launches"][2] > 0:
-        lv = 2 if stages["launches"][3] > 0 else 1
+        lv = round(stages["launches"][3] / stages["launches"][2])
     kara = lv > 0
     if a.form == "mfma":
         out["config"]["schur_form"] = "karatsuba x%d" % lv if kara else "digit product"
@@ -210,12 +210,12 @@ def main():
         out["stages_ms"]["kara_combine"] = ms[9]
     if a.form == "mfma" and ms[6] > 0:
         # int8 ops the GEMMs need per entry and panel column: the digit product
-        # multiplies S^2 digit pairs (S = P/8, 16 per limb-MAC), one Karatsuba
-        # level three products of S/2 + 1 digits, two levels nine of S/4 + 2;
+        # multiplies S^2 digit pairs (S = P/8, 16 per limb-MAC), L Karatsuba
+        # levels 3^L products of S/2^L + L digits;
         # 2 ops per multiply-add
         S = P // 8
         units = stages["schur_limb_macs"] / (nl * nl)   # entry x panel-column updates
-        pairs = {0: S * S, 1: 3 * (S // 2 + 1) ** 2, 2: 9 * (S // 4 + 2) ** 2}[lv]
+        pairs = 3 ** lv * (S // 2 ** lv + lv) ** 2   # lv = 0: the digit product
         ops = units * pairs * 2
         achieved = ops / (ms[6] * 1e-3) / 1e12
         kname = "k_upd_kara" if kara else "k_upd_mfma"

@@ -165,7 +165,9 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
  *            carries;
  *         2: two levels (P a multiple of 512): nine GEMMs of (S/4 + 2)-digit
  *            operands (9/16 of the multiply-adds);
- *        -1 (default): 2 from P = 16384 on, 1 from P = 8192 on, else 0.
+ *         3: three levels (P a multiple of 1024): 27 GEMMs of (S/8 + 3)-digit
+ *            operands (27/64 of the multiply-adds);
+ *        -1 (default): 3 from P = 32768 on, 2 from 16384, 1 from 8192, else 0.
  * A mode beyond what P allows runs the deepest allowed one.  Applies to later
  * hl_factor / hl_factor_cols calls on this context (modes may be mixed within
  * one factorisation).  HL_EINVAL for another mode.
@@ -330,7 +332,7 @@ hl_status hl_sync(hl_ctx *ctx, void *ws, void *stream, int32_t *index);
  * ms[5] load, ms[6] the int8 MFMA GEMM kernel alone, ms[7] whole hl_factor,
  * ms[8] hl_lambda_grad, ms[9] the Karatsuba combination kernel alone;
  * launches[0] Schur updates, launches[1] MFMA GEMM launches, launches[2] those
- * of them in a Karatsuba form, launches[3] those with two levels. */
+ * of them in a Karatsuba form, launches[3] the sum of their levels. */
 typedef struct {
   double ms[12];
   int64_t launches[4];

@@ -72,7 +72,11 @@ hl_status make_dims(const hl_shape* sh, Dims* dm) {
   dm->E = sh->exp_block;
   dm->k = sh->k;
   dm->W = 2 * sh->prec_bits - 4;
-  dm->kara = sh->form != HL_FORM_MFMA8 ? 0 : sh->prec_bits % 512 == 0 ? 2 : sh->prec_bits % 256 == 0 ? 1 : 0;
+  dm->kara = sh->form != HL_FORM_MFMA8      ? 0
+             : sh->prec_bits % 1024 == 0 ? 3
+             : sh->prec_bits % 512 == 0  ? 2
+             : sh->prec_bits % 256 == 0  ? 1
+                                         : 0;
   return HL_OK;
 }
 
@@ -106,8 +110,8 @@ Layout make_layout(const Dims& dm) {
     const size_t useful = tiles * (size_t)(kMaxRanges < dm.nl / 2 ? kMaxRanges : dm.nl / 2);
     L.carry_tiles = 16384 + tiles < useful ? 16384 + tiles : useful;
     for (int lv = 1; lv <= dm.kara; ++lv) {
-      // the Karatsuba forms have 3 or 9 products per tile
-      const size_t np = lv == 1 ? 3 : 9;
+      // the Karatsuba forms have 3^lv products per tile
+      const size_t np = kara_products(lv);
       const size_t ntbp = (size_t)kara_nwp(dm.S, lv) / 4;
       const size_t kuse = np * tri * (kMaxRanges < ntbp ? kMaxRanges : ntbp);
       const size_t kt = 16384 + np * tri < kuse ? 16384 + np * tri : kuse;
@@ -181,23 +185,17 @@ Layout make_layout(const Dims& dm) {
     off += al((size_t)dm.N * L.adj_nr * 4);
   }
   if (dm.kara) {
-    L.kara_slices = dm.S / 2 + 1 + 2 * kDigitPad;
-    L.kara_dig_bytes = al((size_t)L.kara_slices * dm.NT * 16);
-    L.kara_dig = off;
-    off += 6 * L.kara_dig_bytes;
-    if (dm.kara >= 2) {
-      L.kara_leaf_slices = kara_leaf_digits(dm.S, 2) + 2 * kDigitPad;
-      L.kara_leaf_bytes = al((size_t)L.kara_leaf_slices * dm.NT * 16);
-      L.kara_leaf = off;
-      off += 18 * L.kara_leaf_bytes;
-    }
     L.kara_tiles = (size_t)dm.nt * (dm.nt + 1) / 2;
-    L.kara_prod = off;
-    size_t words = 3 * L.kara_tiles * tile_words(kara_nwp(dm.S, 1));
-    if (dm.kara >= 2) {
-      const size_t w2 = 9 * L.kara_tiles * tile_words(kara_nwp(dm.S, 2));
-      if (w2 > words) words = w2;
+    size_t words = 0;
+    for (int lv = 1; lv <= dm.kara; ++lv) {
+      L.kara_pan_slices[lv] = kara_leaf_digits(dm.S, lv) + 2 * kDigitPad;
+      L.kara_pan_bytes[lv] = al((size_t)L.kara_pan_slices[lv] * dm.NT * 16);
+      L.kara_pan[lv] = off;
+      off += 2 * kara_products(lv) * L.kara_pan_bytes[lv];
+      const size_t w = kara_products(lv) * L.kara_tiles * tile_words(kara_nwp(dm.S, lv));
+      if (w > words) words = w;
     }
+    L.kara_prod = off;
     off += al(words * 4);
   }
   L.total = off;
@@ -271,7 +269,7 @@ extern "C" hl_status hl_set_timing(hl_ctx* ctx, int enable) {
 
 extern "C" hl_status hl_set_karatsuba(hl_ctx* ctx, int32_t mode) {
   if (!ctx) return fail(HL_EINVAL, "null ctx");
-  if (mode < -1 || mode > 2) return fail(HL_EINVAL, "karatsuba mode %d not in {-1, 0, 1, 2}", mode);
+  if (mode < -1 || mode > 3) return fail(HL_EINVAL, "karatsuba mode %d not in {-1, 0, 1, 2, 3}", mode);
   ctx->karatsuba = mode;
   return HL_OK;
 }
@@ -347,7 +345,11 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   u32* up = (u32*)(base + L.upanel);
   u32* omega = (u32*)(base + L.omega);
   ctx->t = hl_timing_t{};
-  int kara_lv = ctx->karatsuba >= 0 ? ctx->karatsuba : (dm.P >= kKara2MinPrec ? 2 : dm.P >= kKaraMinPrec ? 1 : 0);
+  int kara_lv = ctx->karatsuba >= 0             ? ctx->karatsuba
+                : dm.P >= kKara3MinPrec ? 3
+                : dm.P >= kKara2MinPrec ? 2
+                : dm.P >= kKaraMinPrec  ? 1
+                                        : 0;
   if (kara_lv > dm.kara) kara_lv = dm.kara;
 
   Stamp total(ctx, st, 7);
@@ -359,8 +361,8 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
     // zero digit slices (the padding outside [0, S) must read as zero)
     HIPCHK(launch_fill((u32*)(base + L.bdig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
     HIPCHK(launch_fill((u32*)(base + L.udig), (size_t)L.digit_slices * dm.NT * 4, 0u, st));
-    if (dm.kara) HIPCHK(launch_fill((u32*)(base + L.kara_dig), 6 * L.kara_dig_bytes / 4, 0u, st));
-    if (dm.kara >= 2) HIPCHK(launch_fill((u32*)(base + L.kara_leaf), 18 * L.kara_leaf_bytes / 4, 0u, st));
+    for (int lv = 1; lv <= dm.kara; ++lv)
+      HIPCHK(launch_fill((u32*)(base + L.kara_pan[lv]), 2 * kara_products(lv) * L.kara_pan_bytes[lv] / 4, 0u, st));
   }
   HIPCHK(launch_scales(mu, mu_exp, w, dm.N, dm.E, out->s, dst, st));
   HIPCHK(launch_load(mu, mu_exp, w, out->s, dm, A, dst, st));
@@ -485,11 +487,11 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
           KaraArgs ka{};
           ka.m = m;
           ka.levels = kara_lv;
-          ka.l1 = (int8_t*)(base + L.kara_dig);
-          ka.l1_stride = L.kara_dig_bytes;
-          ka.l1_slices = L.kara_slices;
-          ka.leaf = kara_lv == 1 ? ka.l1 : (int8_t*)(base + L.kara_leaf);
-          ka.leaf_stride = kara_lv == 1 ? L.kara_dig_bytes : L.kara_leaf_bytes;
+          for (int lv = 1; lv <= kara_lv; ++lv) {
+            ka.pan[lv] = (int8_t*)(base + L.kara_pan[lv]);
+            ka.pan_stride[lv] = L.kara_pan_bytes[lv];
+            ka.pan_slices[lv] = L.kara_pan_slices[lv];
+          }
           ka.Sk = kara_leaf_digits(dm.S, kara_lv);
           ka.kslices = ka.Sk + 2 * kDigitPad;
           ka.prod = (u32*)(base + L.kara_prod);

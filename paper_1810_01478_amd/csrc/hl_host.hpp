@@ -10,7 +10,8 @@ constexpr int kDigitPad = 64;     // zero digit slices below 0 and above S-1
 constexpr int kMaxRanges = 64;    // output-limb ranges per tile in the MFMA updates
 constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 constexpr int kKaraMinPrec = 8192;   // by default one Karatsuba level of the Schur update from this precision on
-constexpr int kKara2MinPrec = 16384; // and two levels from this one
+constexpr int kKara2MinPrec = 16384; // two levels from this one
+constexpr int kKara3MinPrec = 32768; // three levels from this one
 
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
@@ -31,12 +32,11 @@ struct Layout {
   int digit_slices;
   int blk_stride;
   int blk_chunks;
-  // Karatsuba form of the Schur update: six half-length digit panels
-  // (kara_slices slices each, kara_dig_bytes apart), with two levels eighteen
-  // quarter-length ones (kara_leaf_slices, kara_leaf_bytes apart), and the
-  // products (3 or 9 x kara_tiles tiles)
-  size_t kara_dig, kara_dig_bytes, kara_leaf, kara_leaf_bytes, kara_prod, kara_tiles;
-  int kara_slices, kara_leaf_slices;
+  // Karatsuba form of the Schur update: the digit panels of level l = 1 .. 3
+  // (2 x 3^l panels of kara_pan_slices[l] slices, kara_pan_bytes[l] apart) and
+  // the products (3^L x kara_tiles tiles for the deepest L the shape allows)
+  size_t kara_pan[4], kara_pan_bytes[4], kara_prod, kara_tiles;
+  int kara_pan_slices[4];
 };
 
 hl_status fail(hl_status s, const char* fmt, ...);

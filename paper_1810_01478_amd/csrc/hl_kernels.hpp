@@ -109,28 +109,29 @@ RangeTab split_ranges_ntb(int ntb, int S, int n);
 double block_work(int tb, int S);  // digit pairs multiplied for output block tb
 constexpr int MF_BLOCK_DIGITS = 16;
 
-// Karatsuba form of the Schur update, one or two levels.  With X = 256^h,
+// Karatsuba form of the Schur update, one to three levels.  With X = 256^h,
 // h = S/2, each factor splits into its balanced digits below and above h:
 // b = b_lo + X b_hi, and b_mid = b_lo + b_hi is recoded into h + 1 balanced
 // digits.  Then
 //   sum_i b_ri u_ci = LL + X (MM - LL - HH) + X^2 HH,
 // LL = sum_i b_lo u_lo, HH = sum_i b_hi u_hi, MM = sum_i b_mid u_mid: three
 // digit-sum GEMMs of (h + 1)-digit operands, 3/4 of the int8 multiply-adds of
-// the S-digit product.  The second level splits each of the six half operands
-// again at digit S/4 (Y = 256^(S/4), X = Y^2): nine GEMMs of (S/4 + 2)-digit
-// operands, 9/16 of the multiply-adds.  The exact sums of every product are
-// stored per entry; then one pass per entry subtracts sum_p c_p(Y) P_p, with
-// the polynomials c_p of the recursion (coefficients +-1), from the trailing
-// matrix with exact carries.
-constexpr int KA_LL = 0, KA_HH = 1, KA_MM = 2;
+// the S-digit product.  Level l + 1 splits every level-l operand again at digit
+// S/2^(l+1): 3^L GEMMs of (S/2^L + L)-digit operands after L levels, (3/4)^L of
+// the multiply-adds.  The exact sums of every product are stored per entry;
+// then one pass per entry subtracts sum_p c_p(Y) P_p, Y = 256^(S/2^L), c_p the
+// product of the levels' polynomials (1 - z), (z^2 - z), z (children lo, hi,
+// mid) at z = Y^(2^(L-l)), from the trailing matrix with exact carries.
+constexpr int KA_MAX_LEVELS = 3;
 struct KaraArgs {
   MfmaArgs m;          // target, pad, NT, S, carry slots (np x tiles x ranges), timing; bdig/udig unused
-  int levels;          // 1 or 2; np = 3^levels products
-  int8_t* l1;          // level-1 panels b_lo, b_hi, b_mid, u_lo, u_hi, u_mid: [l1_slices][NT][16],
-  size_t l1_stride;    //   l1_stride bytes apart
-  int l1_slices;       // S/2 + 1 + 2 pad
-  int8_t* leaf;        // operands of the products: b of product p at leaf + p leaf_stride, u at
-  size_t leaf_stride;  //   leaf + (np + p) leaf_stride (one level: the level-1 panels)
+  int levels;          // L = 1 .. 3; np = 3^L products
+  // level-l digit panels, l = 1 .. L: 3^l of b, then 3^l of u, pan_stride[l]
+  // bytes apart, pan_slices[l] = S/2^l + l + 2 pad slices each; panel 3 q + c of
+  // a side is child c (lo, hi, mid) of its level-(l-1) panel q
+  int8_t* pan[KA_MAX_LEVELS + 1];
+  size_t pan_stride[KA_MAX_LEVELS + 1];
+  int pan_slices[KA_MAX_LEVELS + 1];
   int Sk;              // digits per operand of a product (kara_leaf_digits)
   int kslices;         // Sk + 2 pad
   u32* prod;           // products: [np][prod_tiles] tiles of nwp limbs per entry
@@ -138,12 +139,11 @@ struct KaraArgs {
   size_t prod_tiles;   // tiles per product
 };
 hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream);
-__host__ __device__ __forceinline__ int kara_leaf_digits(int S, int levels) {
-  return levels == 1 ? S / 2 + 1 : S / 4 + 2;
-}
+__host__ __device__ __forceinline__ int kara_leaf_digits(int S, int levels) { return (S >> levels) + levels; }
 __host__ __device__ __forceinline__ int kara_nwp(int S, int levels) {
   return 4 * ((2 * kara_leaf_digits(S, levels) - 1 + 15) / 16);
 }
+__host__ __device__ __forceinline__ int kara_products(int levels) { return levels == 1 ? 3 : levels == 2 ? 9 : 27; }
 
 // Batched form: one entry per instance and step, work items (entry, tile index
 // of the entry's launch, range) in 8 per-XCD queues of per_xcd items (x < 0:

@@ -174,10 +174,11 @@ def test_mfma_equals_valu_bitwise_c2b_shape():
     (Fraction(1, 3), 20, 256, 1),     # shortest halves: 16 digits, one slab
     (1, 97, 3072, 4),
 ])
-@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("levels", [1, 2, 3])
 def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E, levels):
     # the Karatsuba forms of the trailing update are exact: same bits as the
-    # oracle (two levels need P % 512 == 0; P = 256 runs one)
+    # oracle (two levels need P % 512 == 0, three P % 1024 == 0; a shape that
+    # allows fewer runs the deepest it allows)
     say("factor karatsuba", beta, N, P, E, levels)
     mu = moments(beta, 2 * N - 1)
     f = C.factor(mu, N, P, E)
@@ -192,9 +193,9 @@ def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E, levels):
 
 
 def test_karatsuba_equals_digit_product_c2b_shape():
-    # beta = 1/2, N = 256 at 8192 bits: the digit product, one and two Karatsuba
-    # levels, and a continuation in pieces that switches form between pieces,
-    # all give the same bits
+    # beta = 1/2, N = 256 at 8192 bits: the digit product, one, two and three
+    # Karatsuba levels, and a continuation in pieces that switches form between
+    # pieces, all give the same bits
     import torch
     N, P = 256, 8192
     say("karatsuba vs digit product", N, P)
@@ -205,13 +206,13 @@ def test_karatsuba_equals_digit_product_c2b_shape():
         c.set_karatsuba(0)
         fa = c.factor(mu, N, 8, P, 16, "mfma")
         c.sync(fa)
-        for lv in (1, 2):
+        for lv in (1, 2, 3):
             c.set_karatsuba(lv)
             fb = c.factor(mu, N, 8, P, 16, "mfma")
             c.sync(fb)
             got.append(fb)
         fc = c.factor_cols(mu, N, 8, P, 16, "mfma", 0, 96)
-        for lv, (c0, c1) in zip((0, 1, 2), ((96, 160), (160, 208), (208, N))):
+        for lv, (c0, c1) in zip((0, 3, 1, 2), ((96, 128), (128, 160), (160, 208), (208, N))):
             c.set_karatsuba(lv)
             c.factor_cols(mu, N, 8, P, 16, "mfma", c0, c1, fac=fc)
         c.sync(fc)
@@ -225,5 +226,5 @@ def test_karatsuba_equals_digit_product_c2b_shape():
 def test_set_karatsuba_rejects_bad_mode():
     from paper_1810_01478_amd._lib import HLError, HL_EINVAL
     with pytest.raises(HLError) as e:
-        ctx().set_karatsuba(3)
+        ctx().set_karatsuba(4)
     assert e.value.code == HL_EINVAL
