@@ -686,7 +686,7 @@ void k_kara_comb(KaraArgs k, int C_lo) {
   const u32* P0 = k.prod + (size_t)lt * tw;
   const u32 voff = (u32)in_tile(r, c, 0) * 4;
   const int O = k.m.S / (16 << LV);
-  if constexpr (NSEG <= 8) {
+  if constexpr (NSEG <= 16) {
     i64 cy[NSEG];
     ka_pass<LV, 0, NSEG>(At, P0, voff, pst, O, cy);
 #pragma unroll
