@@ -80,6 +80,17 @@ hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int 
 
 namespace hl {
 // exact update with int8-digit MFMA GEMMs
+// register window of the int8 MFMA tile loop (k_upd_mfma.hip)
+constexpr int MF_T = 16;             // output digits per accumulation block
+constexpr int MF_LPB = MF_T / 4;     // limbs per block (one 16-byte slab of an entry)
+constexpr int MF_PF = 8;             // operands are loaded this many steps ahead
+constexpr int MF_WIN = MF_T + 2 * MF_PF;  // B window: MF_T slices in use, the rest in flight
+constexpr int MF_ROT = MF_WIN / 2;   // steps per rotation of the window (a multiple of MF_PF)
+static_assert(MF_ROT % MF_PF == 0, "the A ring must turn a whole number of times per rotation");
+// zero slices needed at each end of the digit panels: the loads run MF_PF steps
+// (2 MF_PF slices) ahead and the steps are rounded up to whole rotations
+constexpr int MF_PAD_MIN = 2 * (MF_ROT + MF_PF) + 14;
+
 struct MfmaArgs {
   UpdArgs g;
   int8_t* bdig;       // [slices][NT][16] digits of b (slice index = digit + pad)
@@ -92,6 +103,21 @@ struct MfmaArgs {
   int u_rows;           // rows of the u operand (NT for the Schur update, k for X)
 };
 hipError_t launch_upd_mfma(const MfmaArgs& m, hipStream_t stream);
+
+// tile (R, C) of work item lt of an entry's launch (see k_upd_mfma)
+__device__ __forceinline__ void item_tile(const UpdArgs& g, int C_lo, int lt, int* R, int* C) {
+  if (g.tri) {
+    int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
+    while (r > 0 && r * (r + 1) / 2 > lt) --r;
+    while ((r + 1) * (r + 2) / 2 <= lt) ++r;
+    *R = C_lo + r;
+    *C = C_lo + (lt - r * (r + 1) / 2);
+  } else {
+    *R = C_lo + lt / g.ntc;
+    *C = lt % g.ntc;
+  }
+}
+
 
 // Output-limb ranges of one MFMA launch: output block boundaries tb[0..n]
 // (a block is 16 digits = 4 limbs).
@@ -139,6 +165,9 @@ struct KaraArgs {
   size_t prod_tiles;   // tiles per product
 };
 hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream);
+// the digit-sum GEMMs alone (k_upd_mfma.hip), 8 x per_xcd work items
+hipError_t launch_kara_gemm(const KaraArgs& k, const RangeTab& rt, int C_lo, int ntiles, int per_xcd,
+                            hipStream_t stream);
 __host__ __device__ __forceinline__ int kara_leaf_digits(int S, int levels) { return (S >> levels) + levels; }
 __host__ __device__ __forceinline__ int kara_nwp(int S, int levels) {
   return 4 * ((2 * kara_leaf_digits(S, levels) - 1 + 15) / 16);

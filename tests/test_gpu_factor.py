@@ -228,3 +228,26 @@ def test_set_karatsuba_rejects_bad_mode():
     with pytest.raises(HLError) as e:
         ctx().set_karatsuba(4)
     assert e.value.code == HL_EINVAL
+
+
+def test_live_trailing_matrix_equal_across_forms():
+    # after the first 96 columns (beta = 1/2, N = 256, 8192 bits) the part of the
+    # trailing matrix still to be factored (tiles (R, C), C >= 3) is the same in
+    # the VALU form and the MFMA form, whose pivot lookahead leaves the dead
+    # diagonal entries of factored columns alone
+    import torch
+    N, P, cols = 256, 8192, 96
+    say("live trailing matrix", N, P, cols)
+    mu = moments(Fraction(1, 2), 2 * N - 1)
+    c = ctx()
+    fa = c.factor_cols(mu, N, 8, P, 16, "mfma", 0, cols)
+    c.sync(fa)
+    fb = c.factor_cols(mu, N, 8, P, 16, "valu", 0, cols)
+    c.sync(fb)
+    so, tb = fa.sizes.trail_offset, 1024 * 2 * (P // 32) * 4
+    assert so == fb.sizes.trail_offset
+    for R in range(cols // 32, N // 32):
+        t0 = so + (R * (R + 1) // 2 + cols // 32) * tb
+        t1 = so + (R * (R + 1) // 2 + R + 1) * tb
+        assert torch.equal(fa.ws[t0:t1], fb.ws[t0:t1]), R
+    assert torch.equal(fa.d[:cols * 2 * (P // 32)], fb.d[:cols * 2 * (P // 32)])
