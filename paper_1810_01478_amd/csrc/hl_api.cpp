@@ -320,6 +320,15 @@ static hl_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
 }
 
 // ---------------------------------------------------------------------------
+// the context's second stream (default priority) and its events, made once
+static hipError_t ensure_aux(hl_ctx* ctx) {
+  if (ctx->aux) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_col, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_piv, hipEventDisableTiming);
+  return e;
+}
+
 extern "C" hl_status hl_factor(hl_ctx* ctx, const hl_shape* sh, const uint32_t* mu, const int64_t* mu_exp,
                                int32_t w, void* ws, size_t ws_bytes, const hl_factor_t* out, void* stream) {
   return hl_factor_cols(ctx, sh, mu, mu_exp, w, ws, ws_bytes, out, 0, sh ? sh->N : 0, stream);
@@ -374,11 +383,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   // update runs on the caller's; it subtracts b_{i+1} u_{i+1} itself, so that
   // update leaves out the diagonal row i + 1
   const bool look = sh->form == HL_FORM_MFMA8;
-  if (look && !ctx->aux) {
-    HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ctx->ev_col, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ctx->ev_piv, hipEventDisableTiming));
-  }
+  if (look) HIPCHK(ensure_aux(ctx));
   for (int i0 = col_begin; i0 < col_end; i0 += 16) {
     const int npan = dm.N - i0 < 16 ? dm.N - i0 : 16;
     Stamp pn(ctx, st, 1);
@@ -699,7 +704,8 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   DevStatus* dst = (DevStatus*)(base + L.status);
   void* ews = base + L.eig;
   Stamp te(ctx, st, 4);
-  HIPCHK(launch_eig_host(blk, dm, ews, dst, st));
+  HIPCHK(ensure_aux(ctx));
+  HIPCHK(launch_eig_host(blk, dm, ews, dst, st, ctx->aux));
   te.end();
   int32_t idx = 0;
   if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;

@@ -231,7 +231,9 @@ struct EigArgs {
 };
 EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st);
 // the same eigen-step driven from the host, one workgroup per product (synchronises)
-hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
+// aux: an optional second stream for the (k-1) x (k-1) block (nullptr: one stream)
+hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream,
+                           hipStream_t aux = nullptr);
 hipError_t launch_eig_batch(const EigArgs* tab, int count, int nl_max, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
 void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out);

@@ -19,6 +19,8 @@
 //   * the working precision grows with the number of bits the bracket has
 //     resolved, so only the last steps run at full precision.
 // The iteration stops when the bracket is narrower than 2^-(P+32) relative.
+#include <thread>
+
 #include "hl_kernels.hpp"
 #include "mp_mfma.hpp"
 #include "hl_host.hpp"
@@ -1360,18 +1362,49 @@ static hipError_t eig2_noconv(DevStatus* st, int which, hipStream_t stream) {
   return hipStreamSynchronize(stream);
 }
 
-// Host-driven eigen-step of both blocks; ENOCONV goes to the status word.
-hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream) {
+// Host-driven eigen-step of both blocks; ENOCONV goes to the status word.  With
+// a second stream the (k-1) x (k-1) block runs on it from a second host thread
+// while the k x k block runs on the caller's: their launches are small and
+// their workspace regions disjoint, so the two iterations overlap.
+hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream,
+                           hipStream_t aux) {
   const EigArgs a = eig_args(blk, dm, eig_ws, st);
   E2CHK(eig2_attrs(eig2_lds_bytes(a.NWM)));
   bool stop = false;
   E2CHK(eig2_status(st, stream, &stop));
   if (stop) return hipSuccess;
-  for (int which = 0; which < (dm.k >= 2 ? 2 : 1); ++which) {
-    int conv = 1;
-    E2CHK(eig2_block(a, which, stream, &conv));
-    if (!conv) return eig2_noconv(st, which, stream);
+  const int nb = dm.k >= 2 ? 2 : 1;
+  int conv[2] = {1, 1};
+  if (nb == 2 && aux) {
+    int dev = 0;
+    E2CHK(hipGetDevice(&dev));
+    hipEvent_t ev = nullptr;
+    E2CHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e1 = hipEventRecord(ev, stream);   // the block is ready on the caller's stream
+    if (e1 == hipSuccess) e1 = hipStreamWaitEvent(aux, ev, 0);
+    if (e1 != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      return e1;
+    }
+    std::thread other([&]() {
+      e1 = hipSetDevice(dev);
+      if (e1 == hipSuccess) e1 = eig2_block(a, 1, aux, &conv[1]);
+      if (e1 == hipSuccess) e1 = hipEventRecord(ev, aux);
+    });
+    const hipError_t e0 = eig2_block(a, 0, stream, &conv[0]);
+    other.join();
+    if (e1 == hipSuccess) e1 = hipStreamWaitEvent(stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    E2CHK(e0);
+    E2CHK(e1);
+  } else {
+    for (int which = 0; which < nb; ++which) {
+      E2CHK(eig2_block(a, which, stream, &conv[which]));
+      if (!conv[which]) break;
+    }
   }
+  for (int which = 0; which < nb; ++which)
+    if (!conv[which]) return eig2_noconv(st, which, stream);
   hipLaunchKernelGGL(k_eig_diff, dim3(1), dim3(64), (size_t)2 * (a.NWM + 8) * 4, stream, a);
   return hipGetLastError();
 }
