@@ -168,7 +168,9 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
  *         3: three levels (P a multiple of 1024): 27 GEMMs of (S/8 + 3)-digit
  *            operands (27/64 of the multiply-adds);
  *        -1 (default): 3 from P = 32768 on, 2 from 16384, 1 from 8192, else 0.
- * A mode beyond what P allows runs the deepest allowed one.  Applies to later
+ * A mode beyond what the shape allows runs the deepest allowed one (levels
+ * deeper than the default are allowed only while their products fit 16 GiB of
+ * workspace).  Applies to later
  * hl_factor / hl_factor_cols calls on this context (modes may be mixed within
  * one factorisation).  HL_EINVAL for another mode.
  */

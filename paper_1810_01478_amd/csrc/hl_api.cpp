@@ -72,11 +72,18 @@ hl_status make_dims(const hl_shape* sh, Dims* dm) {
   dm->E = sh->exp_block;
   dm->k = sh->k;
   dm->W = 2 * sh->prec_bits - 4;
-  dm->kara = sh->form != HL_FORM_MFMA8      ? 0
-             : sh->prec_bits % 1024 == 0 ? 3
-             : sh->prec_bits % 512 == 0  ? 2
-             : sh->prec_bits % 256 == 0  ? 1
-                                         : 0;
+  // Karatsuba levels offered: the split points on whole slabs (P a multiple of
+  // 256, 512, 1024), and beyond the default level only while the products fit
+  // kKaraExtraBytes
+  dm->kara = 0;
+  if (sh->form == HL_FORM_MFMA8)
+    for (int lv = 1; lv <= KA_MAX_LEVELS; ++lv) {
+      if (sh->prec_bits % (128 << lv)) break;
+      const size_t tri = (size_t)dm->nt * (dm->nt + 1) / 2;
+      const size_t bytes = (size_t)kara_products(lv) * tri * tile_words(kara_nwp(dm->S, lv)) * 4;
+      if (lv > kara_auto_level(dm->P) && bytes > kKaraExtraBytes) break;
+      dm->kara = lv;
+    }
   return HL_OK;
 }
 
@@ -354,11 +361,7 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   u32* up = (u32*)(base + L.upanel);
   u32* omega = (u32*)(base + L.omega);
   ctx->t = hl_timing_t{};
-  int kara_lv = ctx->karatsuba >= 0             ? ctx->karatsuba
-                : dm.P >= kKara3MinPrec ? 3
-                : dm.P >= kKara2MinPrec ? 2
-                : dm.P >= kKaraMinPrec  ? 1
-                                        : 0;
+  int kara_lv = ctx->karatsuba >= 0 ? ctx->karatsuba : kara_auto_level(dm.P);
   if (kara_lv > dm.kara) kara_lv = dm.kara;
 
   Stamp total(ctx, st, 7);

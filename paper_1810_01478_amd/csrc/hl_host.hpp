@@ -12,6 +12,13 @@ constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 constexpr int kKaraMinPrec = 8192;   // by default one Karatsuba level of the Schur update from this precision on
 constexpr int kKara2MinPrec = 16384; // two levels from this one
 constexpr int kKara3MinPrec = 32768; // three levels from this one
+// levels deeper than the default for P are offered only while their products
+// fit in this many bytes (a factorisation at the default level does not carry
+// the deeper levels' buffers)
+constexpr size_t kKaraExtraBytes = (size_t)16 << 30;
+inline int kara_auto_level(int P) {
+  return P >= kKara3MinPrec ? 3 : P >= kKara2MinPrec ? 2 : P >= kKaraMinPrec ? 1 : 0;
+}
 
 struct Layout {
   size_t status, tiles, upanel, omega, bdig, udig, carry, blk_part, blk_sum, eig, total;
