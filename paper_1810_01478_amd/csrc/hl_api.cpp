@@ -400,29 +400,37 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
       if (sh->form == HL_FORM_MFMA8) {
         u32* ucol = up + (size_t)il * ldb;
         u32* P = (u32*)(base + L.colprod);
-        HIPCHK(launch_col_u(A, dm, i, i0, out->h, ucol, dst, st));
-        // P_r = u_r w_i for rows i+1 .. N-1: rank 1 against the single column w_i
-        UpdArgs g{};
-        g.A = P;
-        g.nw = L.colprod_ld;
-        g.nl = dm.nl;
-        g.Bop = ucol;
-        g.Uop = omega + (size_t)i * L.omega_stride;
-        g.npan = 1;
-        g.r_lo = i + 1;
-        g.r_hi = dm.N;
-        g.c_lo = 0;
-        g.c_hi = 1;
-        g.st = dst;
-        ToepArgs ta = toep_args(g, L, base, dm);
-        ta.nlb = dm.nl;
-        ta.nlu = dm.nl + 1;  // w_i <= 2^P
-        ta.plain = 1;
-        ta.ldr = (size_t)L.colprod_ld;
-        ta.ldc = 0;
-        ta.add = 2;
-        HIPCHK(launch_upd_toep(ta, st));
-        HIPCHK(launch_col_fin(dm, i, i0, P, L.colprod_ld, out->l + (size_t)i * ldb, dst, st));
+        // one launch with a workgroup MFMA product per row; where its LDS does
+        // not fit, col_u -> Toeplitz product -> col_fin
+        const hipError_t ec = launch_col_m(A, dm, i, i0, out->h, omega, L.omega_stride, ucol,
+                                           out->l + (size_t)i * ldb, dst, st);
+        if (ec != hipErrorInvalidValue) {
+          HIPCHK(ec);
+        } else {
+          HIPCHK(launch_col_u(A, dm, i, i0, out->h, ucol, dst, st));
+          // P_r = u_r w_i for rows i+1 .. N-1: rank 1 against the single column w_i
+          UpdArgs g{};
+          g.A = P;
+          g.nw = L.colprod_ld;
+          g.nl = dm.nl;
+          g.Bop = ucol;
+          g.Uop = omega + (size_t)i * L.omega_stride;
+          g.npan = 1;
+          g.r_lo = i + 1;
+          g.r_hi = dm.N;
+          g.c_lo = 0;
+          g.c_hi = 1;
+          g.st = dst;
+          ToepArgs ta = toep_args(g, L, base, dm);
+          ta.nlb = dm.nl;
+          ta.nlu = dm.nl + 1;  // w_i <= 2^P
+          ta.plain = 1;
+          ta.ldr = (size_t)L.colprod_ld;
+          ta.ldc = 0;
+          ta.add = 2;
+          HIPCHK(launch_upd_toep(ta, st));
+          HIPCHK(launch_col_fin(dm, i, i0, P, L.colprod_ld, out->l + (size_t)i * ldb, dst, st));
+        }
       } else {
         HIPCHK(launch_col(A, dm, i, i0, out->h, omega, L.omega_stride, up + (size_t)il * ldb,
                           out->l + (size_t)i * ldb, dst, st));

@@ -18,6 +18,10 @@ hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u
 hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
                       int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
 hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream);
+// the column step in one launch with the workgroup int8 MFMA product per row
+// (hipErrorInvalidValue when its LDS would exceed 160 KiB)
+hipError_t launch_col_m(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
+                        int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
 // the column step split around an MFMA product (see k_col_u, k_col_fin)
 hipError_t launch_col_u(const u32* A, const Dims& dm, int i, int r0, const i32* h, u32* u_out, DevStatus* st,
                         hipStream_t stream);

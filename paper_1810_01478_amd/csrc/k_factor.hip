@@ -308,7 +308,9 @@ __global__ __launch_bounds__(PIVOT_THREADS) void k_pivot_b(const PivotArgs* __re
 // workgroup of COL_THREADS per row: the product u w is formed by all its waves.
 constexpr int COL_THREADS = 256;
 
-__device__ void col_body(const ColArgs& a, int bx) {
+// mcap > 0: the product u w by the one-workgroup int8 MFMA product (pv_mul),
+// its scratch of mcap bytes at cb; 0: the product scan on the vector ALU
+__device__ void col_body(const ColArgs& a, int bx, size_t mcap = 0) {
   const u32* __restrict__ A = a.A;
   const Dims dm = a.dm;
   const int i = a.i;
@@ -362,7 +364,10 @@ __device__ void col_body(const ColArgs& a, int bx) {
     return;
   }
   // b = (u w + 2^(P-1)) >> P: limbs nl .. 2nl of the product plus the half
-  g_mul(Us, nl, Ws, nl + 1, Pr, 2 * nl + 1, cb);
+  if (mcap)
+    pv_mul(Us, nl, Ws, nl + 1, Pr, 2 * nl + 1, cb, mcap);
+  else
+    g_mul(Us, nl, Ws, nl + 1, Pr, 2 * nl + 1, cb);
   if (w0) {
     w_add_word(Pr, 2 * nl + 1, nl - 1, 0x80000000u);
     wsync();
@@ -390,6 +395,10 @@ __global__ __launch_bounds__(COL_THREADS) void k_col(ColArgs a) { col_body(a, bl
 __global__ __launch_bounds__(COL_THREADS) void k_col_b(const ColArgs* __restrict__ tab) {
   col_body(tab[blockIdx.y], blockIdx.x);
 }
+
+// The MFMA form's column step in one launch: one workgroup per row, the
+// product u w by the workgroup's int8 MFMAs (same bits as k_col).
+__global__ __launch_bounds__(COL_THREADS) void k_col_m(ColArgs a, size_t mcap) { col_body(a, blockIdx.x, mcap); }
 
 // ---------------------------------------------------------------------------
 // The same column in three launches, for the MFMA form: k_col_u forms the
@@ -558,6 +567,23 @@ hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h,
   hipError_t e = allow_lds((const void*)k_col, col_lds_bytes(dm.nl));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_col, dim3(nrows), dim3(COL_THREADS), col_lds_bytes(dm.nl), stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_m(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
+                        int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream) {
+  const int nrows = dm.NT - r0;
+  if (nrows <= 0) return hipSuccess;
+  const int nl = dm.nl;
+  const size_t fixed = (size_t)(6 * nl + 20) * 4;  // flag, As, Us, Ws, Pr as in col_body
+  size_t mcap = (size_t)3 * (2 * nl + 1) * 4;
+  if (wm_scratch_bytes(nl, nl + 1) > mcap) mcap = wm_scratch_bytes(nl, nl + 1);
+  mcap = (mcap + 15) / 16 * 16;
+  if (fixed + mcap > (size_t)160 * 1024) return hipErrorInvalidValue;
+  const ColArgs a{A, dm, i, r0, h, omega, ostride, u_out, l_col, st};
+  hipError_t e = allow_lds((const void*)k_col_m, fixed + mcap);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_m, dim3(nrows), dim3(COL_THREADS), fixed + mcap, stream, a, mcap);
   return hipGetLastError();
 }
 
