@@ -327,6 +327,20 @@ static hl_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
 }
 
 // ---------------------------------------------------------------------------
+// A narrow update of the MFMA form: few entries take one workgroup each (the
+// workgroup MFMA product), the others the Toeplitz-form kernel; same bits.
+// Used for the triangular solve's updates inside a 16-row block (at most 15 x k
+// entries); the in-panel updates of the factorisation measured faster in the
+// Toeplitz form even when few.
+static hipError_t launch_upd_narrow(const UpdArgs& g, const Layout& L, char* base, const Dims& dm, hipStream_t st) {
+  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  if ((size_t)(g.r_hi - g.r_lo) * (g.c_hi - g.c_lo) <= kUpdWgEntries) {
+    const hipError_t e = launch_upd_wg(g, st);
+    if (e != hipErrorInvalidValue) return e;
+  }
+  return launch_upd_toep(toep_args(g, L, base, dm), st);
+}
+
 // the context's second stream (default priority) and its events, made once
 static hipError_t ensure_aux(hl_ctx* ctx) {
   if (ctx->aux) return hipSuccess;
@@ -611,7 +625,7 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
         g.c_hi = dm.k;
         g.st = dst;
         if (sh->form == HL_FORM_MFMA8) {
-          HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
+          HIPCHK(launch_upd_narrow(g, L, base, dm, st));
         } else {
           HIPCHK(launch_upd_valu(g, st));
         }

@@ -77,6 +77,11 @@ hipError_t launch_debug_mul_wg(const u32* a, int na, const u32* b, int nb, u32* 
 // takes a device array of records (grid nr_max x nc_max x count, each record
 // bounded by its own row and column ranges; npan <= 0 skips a record)
 hipError_t launch_upd_valu(const UpdArgs& g, hipStream_t stream);
+// the same with one workgroup per target entry and the workgroup int8 MFMA
+// product (for few entries; hipErrorInvalidValue when its LDS would exceed 160 KiB)
+hipError_t launch_upd_wg(const UpdArgs& g, hipStream_t stream);
+// target entries at or below which the MFMA form takes launch_upd_wg
+constexpr size_t kUpdWgEntries = 1024;
 hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int nc_max, int nw_max, int nl_max,
                                  hipStream_t stream);
 

@@ -401,6 +401,50 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_b(const ColArgs* __restrict
 __global__ __launch_bounds__(COL_THREADS) void k_col_m(ColArgs a, size_t mcap) { col_body(a, blockIdx.x, mcap); }
 
 // ---------------------------------------------------------------------------
+// Exact update of few entries, A[r][c] -= sum_i b_ri u_ci (UpdArgs), one
+// workgroup per entry (blockIdx.x = (r - r_lo) (c_hi - c_lo) + c - c_lo): each
+// product |b| |u| by the workgroup's int8 MFMAs, then subtracted or added by
+// the signs, modulo 2^(32 nw) as every form of the update.  For launches whose
+// entries are too few to fill the Toeplitz-form kernel's work items.
+__global__ __launch_bounds__(COL_THREADS) void k_upd_wg(UpdArgs g, size_t mcap) {
+  const int ncols = g.c_hi - g.c_lo;
+  const int r = g.r_lo + (int)(blockIdx.x / ncols), c = g.c_lo + (int)(blockIdx.x % ncols);
+  if (r >= g.r_hi || (g.tri && r < c)) return;
+  if (has_error(g.st)) return;
+  const int nl = g.nl, nw = g.nw, NB = nl + 8;
+  const size_t tix = g.tri ? tri_tile_index(r >> 5, c >> 5) : (size_t)(r >> 5) * g.ntc + (c >> 5);
+  u32* At = g.A + tix * tile_words(nw);
+  extern __shared__ u32 lds[];
+  u32* Bs = lds;              // |b|
+  u32* Us = Bs + NB;          // |u|
+  u32* Pt = Us + NB;          // |b u|, nw + 8
+  u32* Es = Pt + nw + 8;      // the entry, nw + 8
+  u32* buf = Es + nw + 8;     // mcap bytes: product scratch and carry chains
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) Es[l] = At[in_tile(r, c, l)];
+  const size_t rsb = g.rsb ? g.rsb : (size_t)nl;
+  for (int il = 0; il < g.npan; ++il) {
+    const u32* b = g.Bop + il * g.ldb + (size_t)r * rsb;
+    const u32* u = g.Uop + il * g.ldu + (size_t)c * nl;
+    for (int l = threadIdx.x; l < NB; l += blockDim.x) {
+      Bs[l] = l < nl ? b[l] : 0u;
+      Us[l] = l < nl ? u[l] : 0u;
+    }
+    __syncthreads();
+    const bool nb = (Bs[nl - 1] >> 31) != 0, nu = (Us[nl - 1] >> 31) != 0;
+    __syncthreads();
+    if (nb) wg_neg(Bs, nl, buf);
+    if (nu) wg_neg(Us, nl, buf);
+    pv_mul(Bs, nl, Us, nl, Pt, nw, buf, mcap);
+    if (nb == nu) {
+      wg_sub(Es, Pt, Es, nw, buf);
+    } else {
+      wg_add(Es, nw, Pt, nw, Es, nw, buf);
+    }
+  }
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) At[in_tile(r, c, l)] = Es[l];
+}
+
+// ---------------------------------------------------------------------------
 // The same column in three launches, for the MFMA form: k_col_u forms the
 // signed u_r, the product P_r = u_r w_i runs as an int8 MFMA GEMM (Toeplitz
 // form, all rows against the one w_i), and k_col_fin rounds
@@ -567,6 +611,21 @@ hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h,
   hipError_t e = allow_lds((const void*)k_col, col_lds_bytes(dm.nl));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_col, dim3(nrows), dim3(COL_THREADS), col_lds_bytes(dm.nl), stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_upd_wg(const UpdArgs& g, hipStream_t stream) {
+  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  const int nl = g.nl;
+  const size_t fixed = (size_t)(2 * (nl + 8) + 2 * (g.nw + 8)) * 4;
+  size_t mcap = (size_t)3 * (2 * nl + 1) * 4;
+  if (wm_scratch_bytes(nl, nl) > mcap) mcap = wm_scratch_bytes(nl, nl);
+  mcap = (mcap + 15) / 16 * 16;
+  if (fixed + mcap > (size_t)160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = allow_lds((const void*)k_upd_wg, fixed + mcap);
+  if (e != hipSuccess) return e;
+  const size_t entries = (size_t)(g.r_hi - g.r_lo) * (g.c_hi - g.c_lo);
+  hipLaunchKernelGGL(k_upd_wg, dim3((unsigned)entries), dim3(COL_THREADS), fixed + mcap, stream, g, mcap);
   return hipGetLastError();
 }
 
