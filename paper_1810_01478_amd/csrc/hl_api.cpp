@@ -329,9 +329,10 @@ static hl_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
 // ---------------------------------------------------------------------------
 // A narrow update of the MFMA form: few entries take one workgroup each (the
 // workgroup MFMA product), the others the Toeplitz-form kernel; same bits.
-// Used for the triangular solve's updates inside a 16-row block (at most 15 x k
-// entries); the in-panel updates of the factorisation measured faster in the
-// Toeplitz form even when few.
+// Used for the updates inside a 16-row block of the triangular solve (at most
+// 15 x k entries) and of the adjoint's back substitution (at most 15); the
+// in-panel updates of the factorisation measured faster in the Toeplitz form
+// even when few.
 static hipError_t launch_upd_narrow(const UpdArgs& g, const Layout& L, char* base, const Dims& dm, hipStream_t st) {
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
   if ((size_t)(g.r_hi - g.r_lo) * (g.c_hi - g.c_lo) <= kUpdWgEntries) {
@@ -970,7 +971,7 @@ extern "C" hl_status hl_lambda_grad(hl_ctx* ctx, const hl_shape* sh, const hl_fa
         g.c_hi = 1;
         g.st = dst;
         if (sh->form == HL_FORM_MFMA8) {
-          HIPCHK(launch_upd_toep(toep_args(g, L, base, dm), st));
+          HIPCHK(launch_upd_narrow(g, L, base, dm, st));
         } else {
           HIPCHK(launch_upd_valu(g, st));
         }

@@ -406,7 +406,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_m(ColArgs a, size_t mcap) {
 // product |b| |u| by the workgroup's int8 MFMAs, then subtracted or added by
 // the signs, modulo 2^(32 nw) as every form of the update.  For launches whose
 // entries are too few to fill the Toeplitz-form kernel's work items.
-__global__ __launch_bounds__(COL_THREADS) void k_upd_wg(UpdArgs g, size_t mcap) {
+constexpr int UPD_WG_THREADS = 1024;
+__global__ __launch_bounds__(UPD_WG_THREADS) void k_upd_wg(UpdArgs g, size_t mcap) {
   const int ncols = g.c_hi - g.c_lo;
   const int r = g.r_lo + (int)(blockIdx.x / ncols), c = g.c_lo + (int)(blockIdx.x % ncols);
   if (r >= g.r_hi || (g.tri && r < c)) return;
@@ -625,7 +626,7 @@ hipError_t launch_upd_wg(const UpdArgs& g, hipStream_t stream) {
   hipError_t e = allow_lds((const void*)k_upd_wg, fixed + mcap);
   if (e != hipSuccess) return e;
   const size_t entries = (size_t)(g.r_hi - g.r_lo) * (g.c_hi - g.c_lo);
-  hipLaunchKernelGGL(k_upd_wg, dim3((unsigned)entries), dim3(COL_THREADS), fixed + mcap, stream, g, mcap);
+  hipLaunchKernelGGL(k_upd_wg, dim3((unsigned)entries), dim3(UPD_WG_THREADS), fixed + mcap, stream, g, mcap);
   return hipGetLastError();
 }
 
