@@ -398,7 +398,8 @@ __global__ __launch_bounds__(COL_THREADS) void k_col_b(const ColArgs* __restrict
 
 // The MFMA form's column step in one launch: one workgroup per row, the
 // product u w by the workgroup's int8 MFMAs (same bits as k_col).
-__global__ __launch_bounds__(COL_THREADS) void k_col_m(ColArgs a, size_t mcap) { col_body(a, blockIdx.x, mcap); }
+constexpr int COL_M_THREADS = 1024;
+__global__ __launch_bounds__(COL_M_THREADS) void k_col_m(ColArgs a, size_t mcap) { col_body(a, blockIdx.x, mcap); }
 
 // ---------------------------------------------------------------------------
 // Exact update of few entries, A[r][c] -= sum_i b_ri u_ci (UpdArgs), one
@@ -643,7 +644,7 @@ hipError_t launch_col_m(const u32* A, const Dims& dm, int i, int r0, const i32* 
   const ColArgs a{A, dm, i, r0, h, omega, ostride, u_out, l_col, st};
   hipError_t e = allow_lds((const void*)k_col_m, fixed + mcap);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_col_m, dim3(nrows), dim3(COL_THREADS), fixed + mcap, stream, a, mcap);
+  hipLaunchKernelGGL(k_col_m, dim3(nrows), dim3(COL_M_THREADS), fixed + mcap, stream, a, mcap);
   return hipGetLastError();
 }
 
