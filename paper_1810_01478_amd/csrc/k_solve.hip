@@ -22,7 +22,12 @@ __device__ __forceinline__ int q_of(const i32* s, int k, int W) {
   return W - (mx + 64);
 }
 
-// Finish row r of X: one wave per column m.
+constexpr int TRSM_THREADS = 256;
+// LDS words of the carry-chain table for nw limbs (as wg_resolve needs)
+__host__ __device__ constexpr int trsm_rip_words(int nw) { return 2 * ((nw + WAVE - 1) / WAVE) + 4; }
+
+// Finish row r of X: one workgroup of TRSM_THREADS per column m, the carry
+// chains resolved by the whole workgroup.
 __device__ void trsm_row_body(const TrsmRowArgs& a, int m) {
   const u32* __restrict__ ACC = a.ACC;
   const Dims dm = a.dm;
@@ -35,46 +40,49 @@ __device__ void trsm_row_body(const TrsmRowArgs& a, int m) {
   const int nl = dm.nl, nw = dm.nw;
   u32* xo = X + ((size_t)r * dm.k + m) * nl;
   if (r < m) {
-    for (int l = lane_id(); l < nl; l += WAVE) xo[l] = 0;
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) xo[l] = 0;
     return;
   }
   if (r == m) {
     const int Q = q_of(s, dm.k, dm.W);
     const int e = Q - h[m];
     if (e < 0 || e > dm.P - 2) {
-      if (lane_id() == 0) set_status(st, HL_EOVERFLOW, r);
+      if (threadIdx.x == 0) set_status(st, HL_EOVERFLOW, r);
       return;
     }
-    for (int l = lane_id(); l < nl; l += WAVE) xo[l] = (l == (e >> 5)) ? (1u << (e & 31)) : 0u;
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) xo[l] = (l == (e >> 5)) ? (1u << (e & 31)) : 0u;
     return;
   }
   extern __shared__ u32 lds[];
   u32* As = lds;           // nw + 4
   u32* Xs = As + nw + 4;   // nl + 4
+  u32* rip = Xs + nl + 4;  // trsm_rip_words(nw)
   const u32* src = ACC + (size_t)(r >> 5) * tile_words(nw);
-  for (int l = lane_id(); l < nw; l += WAVE) As[l] = src[in_tile(r, m, l)];
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) As[l] = src[in_tile(r, m, l)];
   __syncthreads();
+  // every thread reads the sign before the negation's first write (which
+  // follows two of its barriers)
   const bool neg = (As[nw - 1] >> 31) != 0;
-  if (neg) w_neg(As, nw);
-  __syncthreads();
+  if (neg) wg_neg(As, nw, rip);
   const int hr = h[r];
-  if (hr > 0) w_add_word(As, nw, (hr - 1) >> 5, 1u << ((hr - 1) & 31));
-  __syncthreads();
-  w_shift_right(As, nw, hr, Xs, nl + 1);
-  __syncthreads();
+  if (hr > 0) {
+    const int pos = (hr - 1) >> 5;
+    const u32 v = 1u << ((hr - 1) & 31);
+    wg_resolve(nw, [=](int p) -> u64 { return (u64)As[p] + (p == pos ? v : 0u); }, As, rip);
+  }
+  wg_shift_right(As, nw, hr, Xs, nl + 1);
   if (Xs[nl] != 0 || Xs[nl - 1] >= 0x60000000u) {
-    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, r);
+    if (threadIdx.x == 0) set_status(st, HL_EOVERFLOW, r);
     return;
   }
-  if (neg) w_neg(Xs, nl);
-  __syncthreads();
-  for (int l = lane_id(); l < nl; l += WAVE) xo[l] = Xs[l];
+  if (neg) wg_neg(Xs, nl, rip);
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) xo[l] = Xs[l];
 }
 
-__global__ __launch_bounds__(64) void k_trsm_row(TrsmRowArgs a) { trsm_row_body(a, blockIdx.x); }
+__global__ __launch_bounds__(TRSM_THREADS) void k_trsm_row(TrsmRowArgs a) { trsm_row_body(a, blockIdx.x); }
 
 // batch: blockIdx.y is the instance
-__global__ __launch_bounds__(64) void k_trsm_row_b(const TrsmRowArgs* __restrict__ tab) {
+__global__ __launch_bounds__(TRSM_THREADS) void k_trsm_row_b(const TrsmRowArgs* __restrict__ tab) {
   trsm_row_body(tab[blockIdx.y], blockIdx.x);
 }
 
@@ -278,16 +286,16 @@ __global__ __launch_bounds__(64) void k_block_gather(const u32* __restrict__ M, 
 // ---------------------------------------------------------------------------
 hipError_t launch_trsm_row(const u32* ACC, const Dims& dm, int r, const i32* s, const i32* h, u32* X,
                            DevStatus* st, hipStream_t stream) {
-  const size_t lds = (size_t)(dm.nw + 4 + dm.nl + 4) * 4;
+  const size_t lds = (size_t)(dm.nw + 4 + dm.nl + 4 + trsm_rip_words(dm.nw)) * 4;
   const TrsmRowArgs a{ACC, dm, r, s, h, X, st};
-  hipLaunchKernelGGL(k_trsm_row, dim3(dm.k), dim3(64), lds, stream, a);
+  hipLaunchKernelGGL(k_trsm_row, dim3(dm.k), dim3(TRSM_THREADS), lds, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_trsm_row_batch(const TrsmRowArgs* tab, int count, int k_max, int nl_max, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * nl_max + 4 + nl_max + 4) * 4;
-  hipLaunchKernelGGL(k_trsm_row_b, dim3(k_max, count), dim3(64), lds, stream, tab);
+  const size_t lds = (size_t)(2 * nl_max + 4 + nl_max + 4 + trsm_rip_words(2 * nl_max)) * 4;
+  hipLaunchKernelGGL(k_trsm_row_b, dim3(k_max, count), dim3(TRSM_THREADS), lds, stream, tab);
   return hipGetLastError();
 }
 
