@@ -182,27 +182,42 @@ __global__ __launch_bounds__(64) void k_adj_g(const u32* __restrict__ X, const u
 }
 
 // z_i = rnd(ACC_i / 2^h_i), checked against 3 2^(P-3).  One wave.
-__global__ __launch_bounds__(64) void k_adj_row(const u32* __restrict__ ACC, Dims dm, int i,
-                                                const i32* __restrict__ h, u32* __restrict__ Z, DevStatus* st) {
+// z_i = rnd(acc_i / 2^h_i) of one row, by one workgroup (the carry chains
+// resolved by all its waves); same value as w_round_shift.
+constexpr int ADJ_ROW_THREADS = 256;
+__host__ __device__ constexpr int adj_rip_words(int nw) { return 2 * ((nw + WAVE - 1) / WAVE) + 4; }
+__global__ __launch_bounds__(ADJ_ROW_THREADS) void k_adj_row(const u32* __restrict__ ACC, Dims dm, int i,
+                                                             const i32* __restrict__ h, u32* __restrict__ Z,
+                                                             DevStatus* st) {
   if (has_error(st)) return;
   const int nl = dm.nl, nw = dm.nw;
   extern __shared__ u32 lds[];
   u32* a = lds;             // nw + 2
-  u32* tmp = a + nw + 2;    // nw + 2
-  u32* z = tmp + nw + 2;    // nl + 1
+  u32* z = a + nw + 2;      // nl + 2
+  u32* rip = z + nl + 2;    // adj_rip_words(nw)
   const u32* src = ACC + (size_t)(i >> 5) * tile_words(nw);
-  for (int l = lane_id(); l < nw; l += WAVE) a[l] = src[in_tile(i, 0, l)];
-  wsync();
-  w_round_shift(a, nw, h[i], z, nl + 1, tmp);
+  for (int l = threadIdx.x; l < nw; l += blockDim.x) a[l] = src[in_tile(i, 0, l)];
+  __syncthreads();
+  // |a| rounded to nearest (ties away from zero) at bit sh, then the sign back
+  const bool neg = (a[nw - 1] >> 31) != 0;
+  if (neg) wg_neg(a, nw, rip);
+  const long sh = h[i];
+  if (sh > 0) {
+    const int pos = (int)((sh - 1) >> 5);
+    const u32 v = 1u << ((sh - 1) & 31);
+    wg_resolve(nw, [=](int p) -> u64 { return (u64)a[p] + (p == pos ? v : 0u); }, a, rip);
+  }
+  wg_shift_right(a, nw, sh, z, nl + 1);
+  if (neg) wg_neg(z, nl + 1, rip);
   // |z| < 3 2^(P-3): the top limb of the sign-extended value is 0 or ~0 and
   // limb nl-1 lies within the bound
   const u32 top = z[nl], t1 = z[nl - 1];
   const bool ok = (top == 0 && t1 < 0x60000000u) || (top == 0xffffffffu && t1 > 0xa0000000u);
   if (!ok) {
-    if (lane_id() == 0) set_status(st, HL_EOVERFLOW, i);
+    if (threadIdx.x == 0) set_status(st, HL_EOVERFLOW, i);
     return;
   }
-  for (int l = lane_id(); l < nl; l += WAVE) Z[(size_t)i * nl + l] = z[l];
+  for (int l = threadIdx.x; l < nl; l += blockDim.x) Z[(size_t)i * nl + l] = z[l];
 }
 
 // W' = min_m (2P - 3 - bitlen(dmu_m) + min_{i+j=m} (s_i + s_j)) over nonzero dmu_m.
@@ -404,12 +419,12 @@ hipError_t launch_adj_g(const u32* X, const u32* Yc, const u32* omega, int ostri
 
 hipError_t launch_adj_row(const u32* ACC, const Dims& dm, int i, const i32* h, u32* Z, DevStatus* st,
                           hipStream_t stream) {
-  const size_t lds = (size_t)(2 * (dm.nw + 2) + dm.nl + 1) * 4;
+  const size_t lds = (size_t)(dm.nw + 2 + dm.nl + 2 + adj_rip_words(dm.nw)) * 4;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_adj_row, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_adj_row, dim3(1), dim3(64), lds, stream, ACC, dm, i, h, Z, st);
+  hipLaunchKernelGGL(k_adj_row, dim3(1), dim3(ADJ_ROW_THREADS), lds, stream, ACC, dm, i, h, Z, st);
   return hipGetLastError();
 }
 
