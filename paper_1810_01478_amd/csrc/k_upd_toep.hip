@@ -202,14 +202,27 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
   if (h == 0) cb[n] = live ? carry : 0;
 }
 
+// Item of block b.  Workgroups go to the 8 XCDs in turn (block b to XCD
+// b mod 8); the G = ncols items of one range and row block (consecutive
+// columns) are given to one XCD in consecutive slots, so that the 16-byte
+// pieces their epilogues read and write of each 128-byte line of the target
+// tiles (8 columns of one row) meet in that XCD's L2.  Bijective: whole rounds
+// of 8 groups are permuted, the remainder keeps its order.
+__device__ __forceinline__ int toep_item_of_block(int b, int nitems, int G) {
+  const int full = nitems / (8 * G) * (8 * G);
+  if (G <= 1 || b >= full) return b;
+  const int x = b & 7, t = b >> 3;
+  return ((t / G) * 8 + x) * G + t % G;
+}
+
 // Work items (range, row block, column) in range-major order, the ranges with
 // the most steps first; block b takes item b, so the workgroups dealt to the
 // 8 XCDs in turn give every XCD the same mix of long and short items, and the
 // short ones fill in at the end.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_upd_toep(ToepArgs a) {
-  const int item = blockIdx.x;
   const int per_rg = a.nrb * a.ncols;
+  const int item = toep_item_of_block((int)blockIdx.x, a.nrg * per_rg, a.ncols);
   if (item >= a.nrg * per_rg) return;
   const int k = item / per_rg, rem = item - k * per_rg;
   const int rg = a.rg_order[k];  // longest ranges are dealt first
