@@ -61,8 +61,13 @@ def _as_fraction(beta) -> Fraction:
         return beta
     if isinstance(beta, int):
         return Fraction(beta)
-    # floats such as 0.45 are taken as the decimal the user wrote
-    return Fraction(str(beta)).limit_denominator(10**6)
+    # floats such as 0.45 are taken as the decimal the user wrote, exactly; a
+    # decimal whose reduced denominator exceeds 10**6 is refused rather than
+    # snapped to a nearby rational (pass a Fraction for such a beta)
+    f = Fraction(str(beta))
+    if f.denominator > 10**6:
+        raise ValueError("beta = %r: its decimal %s has a denominator above 10**6; pass a Fraction" % (beta, f))
+    return f
 
 
 def is_exact_beta(beta) -> bool:

@@ -27,8 +27,8 @@ Readings where the paper is silent (each one listed in the design doc):
 * pivot balance: for pivot d_i the factor column is split by h_i = bitlen(d_i)//2
   into u_r = rnd(a_ri / 2**h_i) (the paper's A_i[j], cut to P bits) and
   b_r = rnd(u_r w_i / 2**P) (the paper's B_i[k] = A_i[k]/A_i[i], scaled), where
-  w_i = rnd(2**(2 h_i + P) / d_i) is the one division per pivot, taken with d_i
-  cut to its top P + 64 bits (``pivot_reciprocal``).  Algorithm 1
+  w_i = rnd(2**(2 h_i + P) / d_i), the exactly rounded quotient by the whole
+  pivot, is the one division per pivot (``pivot_reciprocal``).  Algorithm 1
   precomputes B_i because divisions are expensive (Section 4.3); here the
   division is done once per pivot and each entry of B_i costs one P x P-bit
   product.  Both u and b then fit in P bits.
@@ -121,15 +121,15 @@ def load(mu: Sequence, N: int, P: int, s: Sequence[int]) -> List[List[int]]:
 # ---------------------------------------------------------------- LDL^T
 
 def pivot_reciprocal(d: int, P: int):
-    """h = bitlen(d) // 2 and w = rnd(2**(2h + P) / d~), where d~ keeps the top
-    P + 64 bits of d: d~ = floor(d / 2**m), m = max(0, bitlen(d) - P - 64), with
-    the power of two lowered by the same m.  (w is the rounded reciprocal of the
-    pivot to P + 1 bits; cutting d to P + 64 bits changes it only when the exact
-    quotient lies within 2**-60 of a rounding tie.)"""
-    L = d.bit_length()
-    h = L // 2
-    m = max(0, L - P - 64)
-    return h, rnd_div(1 << (2 * h + P - m), d >> m)
+    """h = bitlen(d) // 2 and w = rnd(2**(2h + P) / d): the pivot's reciprocal,
+    rounded once to the nearest integer (ties away from zero), by the whole d.
+    Algorithm 1 forms B_i = A_i / A_i[i]; Section 4.3 precomputes it because
+    divisions are expensive, so the contract divides once per pivot and keeps
+    w_i (P + 1 bits) for the multipliers and the block."""
+    if d <= 0:
+        raise ValueError("pivot_reciprocal needs d > 0")
+    h = d.bit_length() // 2
+    return h, rnd_div(1 << (2 * h + P), d)
 
 
 @dataclass

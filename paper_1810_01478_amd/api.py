@@ -410,8 +410,11 @@ class LambdaMin(torch.autograd.Function):
     eigen-step on the GPU.  Backward: d mu / d beta on the host (digamma chain),
     then the adjoint kernels (hl_lambda_grad) give d lambda_1 / d beta.
 
-    beta is a 0-dim float64 tensor; its value is read as the decimal it prints as
-    (0.45 -> 9/20), so the moments are those of that rational."""
+    beta is a 0-dim float64 tensor; its value is read as the shortest decimal
+    that prints as it (0.45 -> 9/20), exactly, so the moments are those of that
+    rational.  A value whose decimal has a reduced denominator above 10**6 (for
+    example 0.1234567891) raises ValueError instead of being snapped to a nearby
+    rational, so lambda_1 and its derivative are never those of another beta."""
 
     @staticmethod
     def forward(ctx_, beta, N, k, P, E, form, context):

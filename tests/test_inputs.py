@@ -79,3 +79,13 @@ def test_precision_rule_beta_half_matches_condition_estimate():
     est = math.lgamma(4 * N - 2) / math.log(2) + math.log2(20)
     P = precision_rule(Fraction(1, 2), N)
     assert est + 512 <= P + 2 and P < est + 512 + 130
+
+
+def test_float_beta_is_its_exact_decimal_or_refused():
+    from hankel_inputs.moments import _as_fraction
+    assert _as_fraction(0.45) == Fraction(9, 20)
+    assert _as_fraction(0.5) == Fraction(1, 2)
+    assert _as_fraction(0.123456) == Fraction(123456, 10**6)
+    # a decimal that would need a larger denominator is refused, not snapped
+    with pytest.raises(ValueError):
+        _as_fraction(0.1234567891)

@@ -389,14 +389,75 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
     assert not ok
 
 
-def test_pivot_reciprocal_against_exact_quotient():
-    # the cut to P + 64 bits must leave w equal to the exactly rounded quotient
-    # except within 2^-60 of a tie; random pivots of 2P bits never hit one
-    import random
-    rng = random.Random(11)
-    for P in (256, 2048):
-        for _ in range(300):
-            d = rng.randrange(1 << (2 * P - 40), 1 << (2 * P - 4))
-            h, w = C.pivot_reciprocal(d, P)
-            assert w == C.rnd_div(1 << (2 * h + P), d)
-            assert (1 << (P - 1)) < w <= (1 << (P + 1))
+def _round_fraction(x: Fraction) -> int:
+    # nearest integer, ties away from zero, from the definition (floor of x + 1/2
+    # for x >= 0), independent of the oracle's rounding helpers
+    assert x >= 0
+    return math.floor(x + Fraction(1, 2))
+
+
+@pytest.mark.parametrize("P", [256, 2048])
+def test_pivot_reciprocal_is_the_rounded_quotient(P):
+    # w = rnd(2^(2h+P) / d) with the whole pivot, h = floor(bitlen(d) / 2), on
+    # random pivots and on pivots whose quotient sits within 2^-60 of a tie
+    from recip_cases import near_tie_pivots, random_pivots
+    for d in random_pivots(P, 200, P) + near_tie_pivots(P, 200, P + 1):
+        h, w = C.pivot_reciprocal(d, P)
+        L = 0
+        while (1 << L) <= d:
+            L += 1
+        assert h == L // 2
+        assert w == _round_fraction(Fraction(1 << (2 * h + P), d))
+        assert (1 << (P - 1)) <= w <= (1 << (P + 1))
+
+
+def test_planted_cut_reciprocal_fails_near_ties():
+    # a reciprocal taken from d cut to its top P + 64 bits agrees on random
+    # pivots but not on every near-tie pivot: the near-tie cases pin the
+    # definition where the two readings differ
+    from recip_cases import near_tie_pivots
+    P = 256
+    differ = 0
+    for d in near_tie_pivots(P, 400, 5):
+        h, w = C.pivot_reciprocal(d, P)
+        m = max(0, d.bit_length() - P - 64)
+        cut = _round_fraction(Fraction(1 << (2 * h + P - m), d >> m))
+        differ += cut != w
+    assert differ > 0
+
+
+def test_scales_by_hand_beta1():
+    # beta = 1: mu_2j = (2j)!, whose bit lengths for j = 0..19 are
+    # 1 2 5 10 | 16 22 29 37 | 45 53 62 70 | 80 89 98 108 | 118 128 139 149;
+    # with E = 4 the block maxima are 10, 37, 70, 108, 149 and s = ceil(t / 2)
+    N, E = 20, 4
+    mu = _mu(1, N)
+    bl = [1, 2, 5, 10, 16, 22, 29, 37, 45, 53, 62, 70, 80, 89, 98, 108, 118, 128, 139, 149]
+    assert [math.factorial(2 * j).bit_length() for j in range(N)] == bl
+    assert C.scales(mu, N, E) == [5] * 4 + [19] * 4 + [35] * 4 + [54] * 4 + [75] * 4
+    # E = 1: every row its own ceil(bitlen / 2); E = 7: ragged last block
+    assert C.scales(mu, N, 1) == [1, 1, 3, 5, 8, 11, 15, 19, 23, 27, 31, 35, 40, 45, 49, 54, 59, 64, 70, 75]
+    assert C.scales(mu, N, 7) == [15] * 7 + [45] * 7 + [75] * 6
+    # dyadic exponents count: mu * 2^-9 lowers every bit length by 9
+    from hankel_inputs import Dyadic
+    mu9 = [Dyadic(m.M, m.e - 9) for m in mu]
+    assert C.scales(mu9, N, E) == [1] * 4 + [14] * 4 + [31] * 4 + [50] * 4 + [70] * 4
+
+
+@pytest.mark.parametrize("mutation", ["floor", "block_shift"])
+def test_planted_scale_mistakes_are_caught(monkeypatch, mutation):
+    orig = C.scales
+
+    def bad(mu, N, E):
+        if mutation == "floor":
+            t = [C.bitlen(mu[2 * j].M, mu[2 * j].e) for j in range(N)]
+            out = []
+            for j0 in range(0, N, E):
+                tJ = max(t[j0:j0 + E])
+                out.extend([tJ // 2] * (min(N, j0 + E) - j0))
+            return out
+        s = orig(mu, N, E)
+        return s[1:] + s[-1:]
+    monkeypatch.setattr(C, "scales", bad)
+    N, E = 20, 4
+    assert C.scales(_mu(1, N), N, E) != [5] * 4 + [19] * 4 + [35] * 4 + [54] * 4 + [75] * 4
