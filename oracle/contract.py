@@ -104,18 +104,29 @@ def scales(mu: Sequence, N: int, E: int) -> List[int]:
     return s
 
 
+def load_entry(mu: Sequence, r: int, c: int, W: int, s: Sequence[int]) -> int:
+    """One entry of the scaled Hankel matrix: a_rc = rnd(mu_{r+c} 2**(W - s_r - s_c))."""
+    m = mu[r + c]
+    return rnd_shift(m.M, -(m.e + W - s[r] - s[c]))
+
+
 def load(mu: Sequence, N: int, P: int, s: Sequence[int]) -> List[List[int]]:
     """Lower triangle of the scaled Hankel matrix (Section 2, eq. ``matrix``):
     a_rc = rnd(mu_{r+c} 2**(W - s_r - s_c)), rows r, columns c <= r."""
     W = 2 * P - 4
-    A = []
-    for r in range(N):
-        row = []
-        for c in range(r + 1):
-            m = mu[r + c]
-            row.append(rnd_shift(m.M, -(m.e + W - s[r] - s[c])))
-        A.append(row)
-    return A
+    return [[load_entry(mu, r, c, W, s) for c in range(r + 1)] for r in range(N)]
+
+
+def column_factors(a: int, h: int, w: int, P: int, i: int):
+    """The two factor entries of row r in column i (Algorithm 1, B_i
+    precomputed): u = rnd(a_ri / 2**h_i) and b = rnd(u w_i / 2**P); both must
+    stay below 3 * 2**(P-3), else EOVERFLOW at column i."""
+    u = rnd_shift(a, h)
+    b = rnd_shift(u * w, P)
+    lim = limit(P)
+    if abs(u) >= lim or abs(b) >= lim:
+        raise ContractError(EOVERFLOW, i, "factor exceeds P bits")
+    return u, b
 
 
 # ---------------------------------------------------------------- LDL^T
@@ -165,10 +176,8 @@ def factor(mu: Sequence, N: int, P: int, E: int = 16, keep_u: bool = False,
         raise ContractError(EINVAL, -1, "P must be a positive multiple of 32")
     if N < 1 or E < 1:
         raise ContractError(EINVAL, -1, "bad N or E")
-    W = 2 * P - 4
     s = scales(mu, N, E)
     A = load(mu, N, P, s)
-    lim = limit(P)
     d: List[int] = []
     h: List[int] = []
     w: List[int] = []
@@ -182,11 +191,7 @@ def factor(mu: Sequence, N: int, P: int, E: int = 16, keep_u: bool = False,
         u: Dict[int, int] = {}
         bc: Dict[int, int] = {}
         for r in range(i + 1, N):
-            a = A[r][i]
-            u[r] = rnd_shift(a, hi)
-            bc[r] = rnd_shift(u[r] * wi, P)
-            if abs(u[r]) >= lim or abs(bc[r]) >= lim:
-                raise ContractError(EOVERFLOW, i, "factor exceeds P bits")
+            u[r], bc[r] = column_factors(A[r][i], hi, wi, P, i)
         # trailing update, exact: column c, rows r >= c
         for c in range(i + 1, N):
             uc = u[c]
@@ -234,6 +239,12 @@ class Solve:
     X: List[List[int]]            # X[r][m], m < k, zero for r < m
 
 
+def solve_exponents(s: Sequence[int], k: int, W: int):
+    """G = max_{m<k} s_m + 64 and Q = W - G."""
+    G = max(s[:k]) + 64
+    return G, W - G
+
+
 def solve(f: Factor, k: int) -> Solve:
     """Algorithm 4 (first N x m columns of L^-1, Section 4.4), as a forward
     substitution on the scaled factor: x_mm = 2**(Q - h_m) and, for r > m,
@@ -242,26 +253,32 @@ def solve(f: Factor, k: int) -> Solve:
     N, P = f.N, f.P
     if not 1 <= k <= N:
         raise ContractError(EINVAL, -1, "need 1 <= k <= N")
-    W = f.W
-    G = max(f.s[:k]) + 64
-    Q = W - G
-    lim = limit(P)
+    G, Q = solve_exponents(f.s, k, f.W)
     X = [[0] * k for _ in range(N)]
     for m in range(k):
-        e = Q - f.h[m]
-        if e < 0:
-            raise ContractError(EOVERFLOW, m, "Q below h_m")
-        X[m][m] = 1 << e
+        X[m][m] = linv_diag(Q, f.h[m], m)
         for r in range(m + 1, N):
             acc = 0
-            br = None
             for i in range(m, r):
                 acc += f.b[i][r] * X[i][m]
-            x = rnd_shift(-acc, f.h[r])
-            if abs(x) >= lim:
-                raise ContractError(EOVERFLOW, r, "L^-1 entry exceeds P bits")
-            X[r][m] = x
+            X[r][m] = linv_entry(acc, f.h[r], P, r)
     return Solve(k=k, G=G, Q=Q, X=X)
+
+
+def linv_diag(Q: int, h: int, m: int) -> int:
+    """x_mm = 2**(Q - h_m) (EOVERFLOW if Q < h_m)."""
+    if Q - h < 0:
+        raise ContractError(EOVERFLOW, m, "Q below h_m")
+    return 1 << (Q - h)
+
+
+def linv_entry(acc: int, h: int, P: int, r: int) -> int:
+    """x_rm = rnd(-acc / 2**h_r) for acc = sum_{i=m}^{r-1} b_ri x_im; it must
+    stay below 3 * 2**(P-3), else EOVERFLOW at row r."""
+    x = rnd_shift(-acc, h)
+    if abs(x) >= limit(P):
+        raise ContractError(EOVERFLOW, r, "L^-1 entry exceeds P bits")
+    return x
 
 
 # ---------------------------------------------------------------- k x k block of H^-1
@@ -283,19 +300,28 @@ def block(f: Factor, sv: Solve) -> Block:
     (H^-1)_ab = M_ab 2**(W - 2Q - P - s_a - s_b).  The entries are brought to
     the common scale 2**(2 s* - s_a - s_b) (s* = max s_a) and rounded once to at
     most P-2 bits."""
-    N, P, k = f.N, f.P, sv.k
-    W, Q = f.W, sv.Q
-    w = f.w
+    N, k = f.N, sv.k
     Mt = [[0] * k for _ in range(k)]
     for a in range(k):
         for b2 in range(a, k):
-            acc = 0
-            for r in range(b2, N):
-                acc += sv.X[r][a] * sv.X[r][b2] * w[r]
-            Mt[a][b2] = acc
-            Mt[b2][a] = acc
-    sstar = max(f.s[:k])
-    m = [[Mt[a][b2] << (2 * sstar - f.s[a] - f.s[b2]) for b2 in range(k)] for a in range(k)]
+            Mt[a][b2] = Mt[b2][a] = block_sum(sv.X, f.w, a, b2, N)
+    return block_from_sums(Mt, f.s, k, f.P, f.W, sv.Q)
+
+
+def block_sum(X, w: Sequence[int], a: int, b: int, N: int) -> int:
+    """M_ab = sum_{r >= max(a,b)} x_ra x_rb w_r, exactly."""
+    acc = 0
+    for r in range(max(a, b), N):
+        acc += X[r][a] * X[r][b] * w[r]
+    return acc
+
+
+def block_from_sums(Mt, s: Sequence[int], k: int, P: int, W: int, Q: int) -> Block:
+    """The exact sums M_ab brought to the common scale 2**(2 s* - s_a - s_b)
+    (s* = max_{a<k} s_a) and rounded once to at most P-2 bits; the block is
+    blk 2**blk_exp."""
+    sstar = max(s[:k])
+    m = [[Mt[a][b2] << (2 * sstar - s[a] - s[b2]) for b2 in range(k)] for a in range(k)]
     top = max(abs(v) for row in m for v in row)
     tau = max(0, top.bit_length() - (P - 2))
     blk = [[rnd_shift(v, tau) for v in row] for row in m]
