@@ -82,13 +82,20 @@ __global__ void k_load(const u32* __restrict__ mu, const i64* __restrict__ mu_ex
 
 // ---------------------------------------------------------------------------
 // Pivot reciprocal.  For the pivot d (nw limbs in LDS, positive) computes
-//   h = bitlen(d) / 2, and w = rnd(2^(2h+P) / d~) where d~ is d cut to its top
-//   P + 64 bits: d~ = floor(d / 2^m), m = max(0, bitlen(d) - P - 64), and the
-//   power is lowered by m as well.
-// Newton's iteration y <- y + y (1 - delta y) for y ~ 1/delta, delta = d~ /
-// 2^bitlen(d~), with the working precision roughly doubled per step; the
-// quotient is then corrected to the exact floor with the remainder.
-// LDS needs 9 * (nl + 8) words (see pivot_lds_words).
+//   h = bitlen(d) / 2 and w = rnd(2^(2h+P) / d), the quotient by the whole
+//   pivot rounded once (ties away from zero).
+// The work runs on d~ = floor(d / 2^m), d cut to its top P + 64 bits
+// (m = max(0, bitlen(d) - P - 64)), with the power lowered by m: Newton's
+// iteration y <- y + y (1 - delta y) for y ~ 1/delta, delta = d~ / 2^bitlen(d~),
+// with the working precision roughly doubled per step, then the remainder
+// R~ = 2^(2h+P-m) - Z d~ corrects Z to the exact floor of q~ = 2^(2h+P-m) / d~.
+// Since d~ 2^m <= d < (d~ + 1) 2^m and q < 2^(P+1), q~ - 2^-62 < q <= q~, so
+// rnd(q) is rnd(q~) or one less, and it can be one less only when q~ lies
+// within 2^-62 above a half-integer (2 R~ - d~ < d~ 2^-61).  In that case the
+// cut part delta = d mod 2^m decides exactly: with r = Z + 1,
+//   (2r - 1) d - 2^(2h+P+1) = (2Z + 1) delta - (2 R~ - d~) 2^m,
+// and q < r - 1/2 (round down) exactly when that is positive.
+// LDS: 15 (nl + 8) words below the pivot (see pivot_lds_bytes).
 struct PivotOut {
   int h;
   int ok;
@@ -227,10 +234,34 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
       break;
     }
   }
-  // omega = Z + [2R >= D]
+  // omega = Z + [2R >= D], then the near-tie decision by the whole pivot
   wg_shift_right(T, nR, -1, Yn, nR > NB ? NB : nR);  // 2R fits: R < D < 2^(P+64)
-  const bool up = w_cmp(Yn, T2, nd + 1) >= 0;
+  bool up = w_cmp(Yn, T2, nd + 1) >= 0;
   __syncthreads();
+  if (up && m > 0) {
+    u32* Dt = dq;  // 2 R~ - d~ (non-negative), nd + 1 limbs
+    wg_sub(Yn, T2, Dt, nd + 1, rip);
+    // bitlen(2R~ - d~) >= bitlen(d~) - 55 puts q~ at least 2^-56 above the
+    // half-integer: no decision by delta is needed
+    if (w_bitlen(Dt, nd + 1) <= LD - 56) {
+      const int nm = (int)((m + 31) / 32);  // delta = d mod 2^m, nm <= nl limbs
+      for (int j = threadIdx.x; j < nm; j += blockDim.x) {
+        u32 v = d[j];
+        if (j == nm - 1 && (m & 31)) v &= (1u << (m & 31)) - 1u;
+        Yn[j] = v;
+      }
+      wg_shift_right(Z, nz, -1, Y, nz + 1);  // 2Z, then + 1
+      if (threadIdx.x == 0) Y[0] |= 1u;
+      __syncthreads();
+      // X = (2Z + 1) delta over T..T2 (4 NB limbs); (2R~ - d~) 2^m beside it
+      const int nX = nz + 1 + nm;
+      pv_mul(Y, nz + 1, Yn, nm, T, nX, colbuf, cap);
+      wg_shift_right(Dt, nd + 1, -m, colbuf, nX);
+      const int c = w_cmp(T, colbuf, nX);
+      __syncthreads();
+      if (c > 0) up = false;
+    }
+  }
   if (up) wg_add_i32(Z, nz, 1, rip);
   for (int j = threadIdx.x; j < n_omega; j += blockDim.x) omega[j] = j < nz ? Z[j] : 0u;
   __syncthreads();

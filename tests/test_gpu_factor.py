@@ -58,17 +58,19 @@ def test_debug_mul_wg_matches_host(na, nb, threads):
         assert got == (a * b) % (1 << (32 * nout)), (it, nout)
 
 
-@pytest.mark.parametrize("P", [256, 2048, 8192])
+@pytest.mark.parametrize("P", [256, 2048, 8192, 49152])
 def test_debug_pivot_reciprocal(P):
+    # w = rnd(2^(2h+P) / d) by the whole pivot: random pivots, and pivots whose
+    # quotient lies within 2^-60 of a half-integer (where a reciprocal of d cut
+    # to its top P + 64 bits can round the other way)
+    from recip_cases import near_tie_pivots, random_pivots
     say("debug_recip", P)
-    rng = random.Random(P)
-    for j in range(12):
-        bits = rng.randrange(2, 2 * P - 3)
-        d = rng.getrandbits(bits) | (1 << (bits - 1))
+    cases = random_pivots(P, 6, P) + near_tie_pivots(P, 10 if P < 49152 else 4, P + 1)
+    for j, d in enumerate(cases):
         w, h = ctx().debug_recip(d, P)
         hh, ww = C.pivot_reciprocal(d, P)
-        assert h == hh
-        assert w == ww, (bits, j)
+        assert h == hh, j
+        assert w == ww, (d.bit_length(), j)
 
 
 def _check_factor(fac, f, N):
