@@ -202,6 +202,26 @@ hl_status hl_lambda_min(hl_ctx *ctx, const hl_shape *sh, const uint32_t *blk, co
                         hl_lambda_t *out, void *stream);
 
 /*
+ * hl_lambda_min_noalloc -- hl_lambda_min for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same results, bit for bit, from the block alone.  Its scratch (status word
+ * and the eigen-step's work area) is a static device array of 64 MiB per GPU,
+ * held from library load until the process ends.  That covers every precision
+ * for k <= 16, P <= 36224 bits for k = 24 and P <= 20608 bits for k = 32;
+ * larger shapes return HL_EINVAL.  Both blocks run on the caller's stream one
+ * after the other.  Calls that overlap on one GPU share that array and race:
+ * serialise them.  Every call clears the array first.  Synchronises the stream;
+ * returns HL_ENOCONV (index 0 or 1, the block) if the eigen-step does not
+ * converge.  Allocates no device memory.
+ *   blk, blk_exp            device, as written by hl_inv_block
+ *   lam_mant, lam_mant_km1  optional device outputs, nl limbs each (NULL: skip)
+ *   out                     host
+ */
+hl_status hl_lambda_min_noalloc(hl_ctx *ctx, const hl_shape *sh, const uint32_t *blk, const int64_t *blk_exp,
+                                uint32_t *lam_mant, uint32_t *lam_mant_km1, hl_lambda_t *out, void *stream);
+
+/*
  * hl_lambda_next -- lambda_2 and lambda_3 with their truncation estimates (the
  * further columns of Table 2; the estimate as in Section 4.5): the j-th
  * smallest eigenvalue of H_N taken as 1 / (j-th largest eigenvalue of the

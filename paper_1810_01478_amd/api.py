@@ -213,6 +213,25 @@ class Context:
             res["mant_km1"] = _ints(m2, nl, signed=False)[0]
         return res
 
+    def eigen_noalloc(self, fac: Factorization, want_mant=True, stream=None):
+        """The eigen-step of eigen() through hl_lambda_min_noalloc: the same
+        results from the block alone, its scratch in the library's static
+        device array instead of the workspace."""
+        out = L.hl_lambda_t()
+        nl = fac.nl
+        m1 = torch.zeros(nl, dtype=torch.int32, device=self.device) if want_mant else None
+        m2 = torch.zeros(nl, dtype=torch.int32, device=self.device) if want_mant else None
+        L.check(L.lib().hl_lambda_min_noalloc(self.h, ctypes.byref(fac.shape), _ptr(fac.blk), _ptr(fac.blk_exp),
+                                              _ptr(m1) if m1 is not None else None,
+                                              _ptr(m2) if m2 is not None else None,
+                                              ctypes.byref(out), _stream(stream)))
+        res = {"lambda1": out.lambda1, "lambda1_km1": out.lambda1_km1, "trunc": out.trunc,
+               "exp": out.exp, "exp_km1": out.exp_km1, "iterations": out.iterations}
+        if want_mant:
+            res["mant"] = _ints(m1, nl, signed=False)[0]
+            res["mant_km1"] = _ints(m2, nl, signed=False)[0]
+        return res
+
     def lambda_min(self, fac: Factorization, stream=None):
         self.inv_block(fac, stream)
         return self.eigen(fac, stream=stream)

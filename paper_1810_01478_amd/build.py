@@ -16,6 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["k_factor.hip", "k_upd_valu.hip", "k_upd_mfma.hip", "k_kara.hip", "k_upd_toep.hip", "k_solve.hip", "k_eig.hip", "k_adjoint.hip",
+           "hl_noalloc.hip",
            "hl_api.cpp", "hl_batch.cpp"]
 
 # packed-fp32 instructions are kept off in every device compilation

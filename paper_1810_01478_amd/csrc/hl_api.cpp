@@ -252,6 +252,7 @@ extern "C" hl_status hl_create(hl_ctx** ctx, int device) {
   HIPCHK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(HL_EINVAL, "device %d of %d", device, n);
   HIPCHK(hipSetDevice(device));
+  HIPCHK(noalloc_init(device));  // device address of hl_lambda_min_noalloc's scratch
   hl_ctx* c = new hl_ctx();
   c->device = device;
   *ctx = c;
