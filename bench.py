@@ -10,8 +10,12 @@ update as exact int8 MFMA GEMMs.  Prints one JSON line:
   value        algorithmic Schur limb-MACs of the step / step time (whole job)
   ms_per_step  time-to-lambda_1
   roofline     the int8 MFMA GEMM kernel against the int8 dense MFMA peak
-  cpu_baseline the CPU oracle on a bounded sample (leading block of the same
-               matrix at the same precision), also used as a parity check
+  roofline_valu the plain vector-ALU form's Schur update (first two panels of
+               the same matrix) against the VALU integer multiply-add peak,
+               with the issue rate an ALU probe measures beside it
+  cpu_baseline the CPU oracle (row-parallel contract on GMP, one process per
+               host core up to 16) on the first pivots of the same matrix at
+               the same precision, also a bit-exact check of those columns
   valu_sample  the plain vector-ALU form on the first two panels of the same
                matrix, checked bit-identical against the MFMA form
   adjoint      d lambda_1 / d beta on the same factorisation (hl_lambda_grad)
@@ -40,6 +44,11 @@ WORKLOADS = {
 }
 
 MFMA_INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA, MI355X: 5.0 POP/s
+# vector-ALU 32 x 32 -> 64-bit integer multiply-add (v_mad_u64_u32, the plain
+# form's limb product): 256 CUs x 4 SIMDs x 16 lanes, one per lane and clock
+# (the issue-rate probe measures 82% of this at the clock the GPU holds), at
+# 2.4 GHz
+VALU_MAD_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def schur_limb_macs(N, nl):
@@ -64,15 +73,42 @@ def measured_traffic(workload, kernel="k_upd_mfma"):
     return float(rec["bytes_per_launch"])
 
 
-def cpu_sample(mu, N_s, P, E):
-    """The oracle on the leading N_s x N_s block (same moments, precision and
-    exponent blocks): its pivots and multipliers are exactly the first N_s of
-    the full factorisation."""
-    from oracle import contract as C
-    t = time.time()
-    f = C.factor(mu, N_s, P, E)
-    dt = time.time() - t
-    return f, dt
+def cpu_workers():
+    """Host threads for the oracle sample: the cores this process may use, at
+    most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_sample(mu, N, k, P, E, cols, procs):
+    """The oracle (row-parallel contract on GMP, one process per core) on the
+    first `cols` pivots of the same matrix: their d_i, h_i and multiplier
+    columns are exactly those of the full factorisation.  Returns the oracle's
+    record and the wall time of its column loop (the load of the matrix
+    excluded)."""
+    from oracle import parallel as PAR
+    f = PAR.factor_solve(mu, N, P, E, k, procs, columns=cols)
+    return f, f.column_seconds
+
+
+def sample_limb_macs(N, cols, nl):
+    """Schur limb multiply-adds of the first `cols` pivots of an N x N
+    factorisation: pivot i updates the (N-i-1)(N-i)/2 entries r >= c > i."""
+    return sum((N - i - 1) * (N - i) / 2 for i in range(cols)) * nl * nl
+
+
+def valu_roofline(ctx, achieved, what):
+    """The VALU form's Schur update against the vector ALU's integer
+    multiply-add peak, with the rate the issue-rate probe measures beside it."""
+    probe, _ = ctx.debug_valu_peak(mode=1)
+    pair, _ = ctx.debug_valu_peak(mode=0)
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_MAD_PEAK, "unit": "limb-MAC/s",
+            "frac": achieved / VALU_MAD_PEAK, "traffic": None, "kernel": what,
+            "probe_mad_per_s": probe, "probe_mad_carry_pair_per_s": pair,
+            "frac_of_probe": achieved / probe}
 
 
 def main():
@@ -88,7 +124,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance workload")
     ap.add_argument("--karatsuba", default="auto", choices=["auto", "0", "1", "2", "3"],
                     help="Schur-update form of the MFMA path: Karatsuba levels (0: the plain digit product)")
-    ap.add_argument("--cpu-rows", type=int, default=48)
+    ap.add_argument("--cpu-cols", type=int, default=4,
+                    help="pivots of the oracle sample (about 5 s each on 8 cores at the default workload)")
     ap.add_argument("--progress", action="store_true",
                     help="factor in pieces of 128 columns, printing a line after each (profiler runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -220,11 +257,14 @@ def main():
         achieved = ops / (ms[6] * 1e-3) / 1e12
         kname = "k_upd_kara" if kara else "k_upd_mfma"
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": MFMA_INT8_PEAK_TOPS,
-                           "unit": "TFLOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
+                           "unit": "TOP/s", "frac": achieved / MFMA_INT8_PEAK_TOPS,
                            "traffic": measured_traffic(workload, kname),
                            "kernel": kname + " (int8 ops of the algorithm, padding excluded)",
                            "launches": stages["launches"][1],
                            "avg_launch_ms": ms[6] / max(1, stages["launches"][1])}
+    if a.form == "valu" and ms[0] > 0:
+        achieved = stages["schur_limb_macs"] / (ms[0] * 1e-3)
+        out["roofline"] = valu_roofline(ctx, achieved, "k_upd_valu (every Schur update of the step)")
 
     # adjoint on the same factorisation: d lambda_1 / d beta (after the timed steps)
     if not a.no_grad:
@@ -267,23 +307,29 @@ def main():
         del bt
         torch.cuda.empty_cache()
 
-    # CPU oracle on a bounded sample, doubling as a parity check of the leading block
+    # CPU oracle on a bounded sample, doubling as a parity check of its columns
     if not a.no_cpu:
-        Ns = min(a.cpu_rows, N)
-        if Ns < N:
-            Ns -= Ns % E   # whole exponent blocks: the leading block then has the same scales
-        log("cpu oracle sample", Ns)
-        fs, tcpu = cpu_sample(mu, Ns, P, E)
+        import hashlib
+        cols = max(1, min(a.cpu_cols, N - 1))
+        procs = cpu_workers()
+        log("cpu oracle sample", cols, "pivots on", procs, "processes")
+        fs, tcpu = cpu_sample(mu, N, k, P, E, cols, procs)
         ctx.sync(fac)
-        piv = fac.pivots()[:Ns]
-        ok = piv == fs.d and fac.h_list()[:Ns] == fs.h
-        for i in range(Ns - 1):
-            ok = ok and fac.multipliers(i, range(i + 1, Ns)) == [fs.b[i][r] for r in range(i + 1, Ns)]
-        sample_macs = schur_limb_macs(Ns, nl)
-        out["cpu_baseline"] = {"value": sample_macs / tcpu, "unit": "limb-MAC/s", "cores": 1, "kind": "oracle",
-                               "sample": "oracle LDL^T of the leading %dx%d block of the same matrix at P=%d "
-                                         "(Python integers, one thread), %.1f s" % (Ns, Ns, P, tcpu),
-                               "parity_leading_block_bit_exact": bool(ok)}
+        nw_, NT = 2 * nl, fac.NT
+        d = fac.d.view(-1)[:N * nw_].view(N, nw_).cpu().numpy()
+        lv = fac.l.view(-1)
+        ok = fac.h_list()[:cols] == fs.h and fac.s_list() == fs.s
+        for i in range(cols):
+            ok = ok and hashlib.sha256(d[i].tobytes()).hexdigest() == fs.d_sha[i]
+            col = lv[(i * NT + i + 1) * nl:(i * NT + N) * nl].cpu().numpy()
+            ok = ok and hashlib.sha256(col.tobytes()).hexdigest() == fs.b_sha[i]
+        sample_macs = sample_limb_macs(N, cols, nl)
+        out["cpu_baseline"] = {"value": sample_macs / tcpu, "unit": "limb-MAC/s", "cores": procs, "kind": "oracle",
+                               "sample": "oracle (row-parallel contract, GMP multiply-subtract) on the first %d "
+                                         "pivots of the same %dx%d matrix at P=%d: %.3g Schur limb-MACs in %.1f s "
+                                         "of column loop on %d processes (matrix load excluded)"
+                                         % (cols, N, N, P, sample_macs, tcpu, procs),
+                               "parity_sample_columns_bit_exact": bool(ok)}
     # VALU sample: first two panels of the same matrix in both forms, bitwise
     if not a.no_valu and N > 32:
         cols = 32
@@ -310,6 +356,9 @@ def main():
         out["valu_sample"] = {"columns": cols, "mfma_limb_mac_per_s": rates["mfma"],
                               "valu_limb_mac_per_s": rates["valu"], "mfma_over_valu": rates["mfma"] / rates["valu"],
                               "bit_identical": same}
+        if a.form == "mfma":
+            out["roofline_valu"] = valu_roofline(ctx, rates["valu"], "k_upd_valu (Schur updates of the first %d "
+                                                                     "pivots of the same matrix)" % cols)
         del fac2
         torch.cuda.empty_cache()
 

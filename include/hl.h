@@ -370,6 +370,14 @@ hl_status hl_debug_mul(const uint32_t *a, int32_t na, const uint32_t *b, int32_t
                        int32_t nout, void *stream);
 hl_status hl_debug_recip(const uint32_t *d, int32_t nd, int32_t P, uint32_t *omega, int32_t *h,
                          void *stream);
+/* Issue-rate probe of the vector ALU's 32 x 32 -> 64-bit integer multiply-add,
+ * the limb product of the HL_FORM_VALU Schur update: `blocks` workgroups of 256
+ * threads, each thread running 8 independent chains of `iters` steps (mode 0:
+ * v_mad_u64_u32 plus v_addc_co_u32 of its carry, the form's pair; mode 1:
+ * v_mad_u64_u32 alone), operands in registers: blocks * 256 * iters * 8
+ * multiply-adds.  sink: device, one uint64 (written only on an impossible
+ * value).  Time it with events on `stream`. */
+hl_status hl_debug_valu_peak(int32_t mode, int32_t blocks, int32_t iters, uint64_t *sink, void *stream);
 /* out[0..nout) = a b mod 2^(32 nout) for non-negative a (na limbs) and b (nb
  * limbs), all device pointers, by the one-workgroup int8 MFMA product that the
  * pivot reciprocal uses (threads: 256 or 1024 per workgroup).  HL_EHIP when the

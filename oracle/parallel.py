@@ -44,6 +44,7 @@ from __future__ import annotations
 import hashlib
 import multiprocessing as mp
 import threading
+import time
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -80,6 +81,7 @@ class ParallelFactor:
     X: List[List[int]]            # X[r][m], m < k
     G: int
     Q: int
+    column_seconds: float = 0.0   # wall time of the column loop (after the load), slowest worker
 
     @property
     def W(self) -> int:
@@ -111,12 +113,15 @@ def _worker(p: int, nproc: int, mu, N: int, P: int, s: List[int], k: int, ncols:
     acc = {r: [Mpz() for _ in range(min(r, k))] for r in rows}   # acc_rm, m < min(r, k)
     digests = []
     solve_err = None
+    t_start = None
 
     def fail(code, idx):
         if ctrl[0] == 0:
             ctrl[0], ctrl[1] = code, idx
 
     try:
+        barrier.wait()   # every worker has loaded its rows: the column loop starts together
+        t_start = time.perf_counter()
         for i in range(ncols):
             cur = i & 1
             # -- the pivot row's owner: d_i, h_i, w_i and row i of X
@@ -185,7 +190,7 @@ def _worker(p: int, nproc: int, mu, N: int, P: int, s: List[int], k: int, ncols:
                     row[c].submul(b, uc[c])
     except threading.BrokenBarrierError:
         pass
-    out_q.put((p, digests, solve_err))
+    out_q.put((p, digests, solve_err, time.perf_counter() - t_start if t_start is not None else 0.0))
 
 
 def factor_solve(mu, N: int, P: int, E: int, k: int, nproc: int = 8, timeout: float = 6 * 3600,
@@ -227,11 +232,12 @@ def factor_solve(mu, N: int, P: int, E: int, k: int, nproc: int = 8, timeout: fl
     ctrl = _view("ctrl")
     if ctrl[0]:
         raise C.ContractError(int(ctrl[0]), int(ctrl[1]), "parallel factorisation")
-    errs = [e for _, _, e in results if e is not None]
+    errs = [e for _, _, e, _ in results if e is not None]
+    tcols = max(t for _, _, _, t in results)
     if errs:
         code, idx = min(errs, key=lambda t: t[1])
         raise C.ContractError(code, idx, "L^-1 entry")
-    dig = sorted(x for _, ds, _ in results for x in ds)
+    dig = sorted(x for _, ds, _, _ in results for x in ds)
     assert [x[0] for x in dig] == list(range(ncols))
     if ncols < N:
         Dsh, Hsh, Wsh = _view("d"), _view("h"), _view("w")
@@ -239,7 +245,8 @@ def factor_solve(mu, N: int, P: int, E: int, k: int, nproc: int = 8, timeout: fl
                              d=[int.from_bytes(Dsh[i].tobytes(), "little", signed=True) for i in range(ncols)],
                              h=[int(v) for v in Hsh[:ncols]],
                              w=[int.from_bytes(Wsh[i].tobytes(), "little", signed=True) for i in range(ncols)],
-                             b_sha=[x[2] for x in dig], d_sha=[x[1] for x in dig], X=[], G=G, Q=Q)
+                             b_sha=[x[2] for x in dig], d_sha=[x[1] for x in dig], X=[], G=G, Q=Q,
+                             column_seconds=tcols)
         _SH.clear()
         return out
     Dsh, Hsh, Wsh, Xsh = _view("d"), _view("h"), _view("w"), _view("x")
@@ -247,7 +254,8 @@ def factor_solve(mu, N: int, P: int, E: int, k: int, nproc: int = 8, timeout: fl
     w = [int.from_bytes(Wsh[i].tobytes(), "little", signed=True) for i in range(N)]
     X = [[int.from_bytes(Xsh[r, m].tobytes(), "little", signed=True) for m in range(k)] for r in range(N)]
     out = ParallelFactor(N=N, P=P, E=E, k=k, s=s, d=d, h=[int(v) for v in Hsh], w=w,
-                         b_sha=[x[2] for x in dig[:-1]], d_sha=[x[1] for x in dig], X=X, G=G, Q=Q)
+                         b_sha=[x[2] for x in dig[:-1]], d_sha=[x[1] for x in dig], X=X, G=G, Q=Q,
+                         column_seconds=tcols)
     _SH.clear()
     return out
 

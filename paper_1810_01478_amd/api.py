@@ -327,6 +327,25 @@ class Context:
         torch.cuda.synchronize()
         return O.cpu().tolist()
 
+    def debug_valu_peak(self, mode: int = 1, blocks: int = 8192, iters: int = 8192, repeats: int = 3):
+        """Rate of the VALU integer multiply-add (hl_debug_valu_peak): best of
+        `repeats` launches, timed with events on the current stream.  Returns
+        (multiply-adds per second, ms per launch)."""
+        sink = torch.zeros(1, dtype=torch.int64, device=self.device)
+        st = torch.cuda.current_stream()
+        L.check(L.lib().hl_debug_valu_peak(mode, blocks, iters, _ptr(sink), _stream()))   # warm-up
+        best = None
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            L.check(L.lib().hl_debug_valu_peak(mode, blocks, iters, _ptr(sink), _stream()))
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        macs = blocks * 256.0 * iters * 8
+        return macs / (best * 1e-3), best
+
     def debug_recip(self, d: int, P: int):
         nl = P // 32
         nd = max(1, (d.bit_length() + 31) // 32)

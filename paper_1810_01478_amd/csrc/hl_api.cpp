@@ -575,6 +575,12 @@ extern "C" hl_status hl_debug_mul_wg(const uint32_t* a, int32_t na, const uint32
   return HL_OK;
 }
 
+extern "C" hl_status hl_debug_valu_peak(int32_t mode, int32_t blocks, int32_t iters, uint64_t* sink, void* stream) {
+  if ((mode != 0 && mode != 1) || blocks < 1 || iters < 1 || !sink) return fail(HL_EINVAL, "bad debug_valu_peak args");
+  HIPCHK(launch_valu_peak(mode, blocks, iters, (u64*)sink, (hipStream_t)stream));
+  return HL_OK;
+}
+
 extern "C" hl_status hl_debug_recip(const uint32_t* d, int32_t nd, int32_t P, uint32_t* omega, int32_t* h,
                                     void* stream) {
   if (!d || !omega || !h || P % 128 || P < 256 || P > kMaxPrec || nd < 1 || nd > 2 * (P / 32))

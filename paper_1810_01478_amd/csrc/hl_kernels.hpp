@@ -70,6 +70,8 @@ hipError_t launch_debug_mul(const u32* a, int na, const u32* b, int nb, u32* out
                             hipStream_t stream);
 hipError_t launch_debug_recip(const u32* d, int nd, int P, u32* omega, int n_omega, i32* h,
                               hipStream_t stream);
+// VALU multiply-add issue-rate probe (mode 0: v_mad_u64_u32 + carry count, 1: v_mad_u64_u32)
+hipError_t launch_valu_peak(int mode, int blocks, int iters, u64* sink, hipStream_t stream);
 hipError_t launch_debug_mul_wg(const u32* a, int na, const u32* b, int nb, u32* out, int nout, int threads,
                                hipStream_t stream);
 

@@ -99,6 +99,34 @@ __device__ __forceinline__ size_t launch_tile_index(const UpdArgs& g, int R, int
 // block tb).  STORE = true: the exact sums themselves are written to the tile
 // Out, block tb as limbs 4 tb .. 4 tb + 3 of the entry.  Either way the carry
 // out of the range goes to cb (1024 entries).
+// acc * m2 + d for an int32 digit sum acc and m2 = 2^(8 m): one 32 x 32 ->
+// 64-bit signed multiply-add (v_mad_i64_i32) once m2 is opaque to the compiler
+// (a known power of two would become 64-bit shifts)
+__device__ __forceinline__ i64 mad_digit(int acc, int m2, i64 d) { return (i64)acc * (i64)m2 + d; }
+// one accumulator register, read from the accumulation file by itself (an
+// element taken from the vector otherwise copies the whole vector)
+__device__ __forceinline__ int acc_elem(int a) {
+  int v;
+  asm("v_accvgpr_read_b32 %0, %1" : "=v"(v) : "a"(a));
+  return v;
+}
+__device__ __forceinline__ int opaque_i32(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// The digit-sum GEMM of tile (R, C) over output blocks [tb0, tb1) of the
+// product of the digit panels bdig (rows) and udig (columns), S digits each,
+// slices = S + 2 pad slices of NT x 16 bytes.  STORE = false: the sums are
+// subtracted from the trailing-matrix tile Out (limb 4 tb of an entry receives
+// block tb).  STORE = true: the exact sums themselves are written to the tile
+// Out, block tb as limbs 4 tb .. 4 tb + 3 of the entry.  Either way the carry
+// out of the range goes to cb (1024 entries).
+//
+// Per block the steps run in whole rotations of the register window and one
+// last partial rotation whose steps are skipped past the block's end (no
+// padding steps); the next block's operands are requested before this block's
+// sums are folded, so their latency hides behind the fold.
 template <bool STORE>
 __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig, const int8_t* udig, int slices,
                                             int S, int pad, int NT, int R, int C, int tb0, int tb1, long long* cb,
@@ -110,7 +138,7 @@ __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig
   // A operand (b digits of tile rows), B operand (u digits of tile columns),
   // read through buffer descriptors: a 32-bit lane offset plus a wave-uniform
   // slice offset stepped in scalar registers, so no load in flight holds a
-  // per-lane 64-bit address
+  // per-lane 64-bit address; loads past the panels return zero
   const __amdgpu_buffer_rsrc_t rb =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(bdig), 0, slices * sst, kRawBufferWord3);
   const __amdgpu_buffer_rsrc_t ru =
@@ -124,82 +152,111 @@ __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig
     const int r = R * 32 + mf_row(l, v), c = C * 32 + mf_col(l);
     if ((!g.tri || r >= c) && r >= g.r_lo && r < g.r_hi && c >= g.c_lo && c < g.c_hi) live |= 1u << v;
   }
+  // Window slot (y mod MF_WIN) holds the slice at offset t0 - jlo + y; step s
+  // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -2 MF_PF - 2s,
+  // -2 MF_PF + 1 - 2s for step s + MF_PF.  A digits are likewise loaded MF_PF
+  // steps ahead into a ring.
+  v4i w[MF_WIN];
+  v4i an[MF_PF];
+  int ap = 0, un = 0, nsteps = 0;
+  // block tb's steps (pairs of digits j) and its first operands
+#define MF_PROLOGUE(tb_)                                                          \
+  do {                                                                           \
+    const int t0_ = MF_T * (tb_);                                                \
+    int jlo_ = t0_ - (S - 1);                                                    \
+    if (jlo_ < 0) jlo_ = 0;                                                      \
+    jlo_ &= ~1;                                                                  \
+    int jhi_ = t0_ + MF_T - 1;                                                   \
+    if (jhi_ > S - 1) jhi_ = S - 1;                                              \
+    nsteps = (jhi_ - jlo_) / 2 + 1;                                              \
+    const int ub_ = (pad - 1 + t0_ - jlo_) * sst;                                \
+    _Pragma("unroll") for (int y = 0; y < MF_T; ++y) w[y] = bld16(ru, uoff, ub_ + y * sst); \
+    _Pragma("unroll") for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = bld16(ru, uoff, ub_ + y * sst); \
+    ap = (pad + jlo_) * sst;                                                     \
+    _Pragma("unroll") for (int q = 0; q < MF_PF; ++q) an[q] = bld16(rb, aoff, ap + 2 * q * sst); \
+    ap += 2 * MF_PF * sst;                                                       \
+    un = ub_ - 2 * MF_PF * sst;                                                  \
+  } while (0)
+  // one step (st: its place in the rotation, a compile-time constant)
+#define MF_STEP(st)                                                               \
+  do {                                                                           \
+    const v4i a_ = an[(st) % MF_PF];                                             \
+    an[(st) % MF_PF] = bld16(rb, aoff, ap);                                      \
+    const int k0_ = (MF_WIN * 4 - 2 * MF_PF - 2 * (st)) % MF_WIN;                \
+    w[k0_] = bld16(ru, uoff, un);                                                \
+    w[k0_ + 1] = bld16(ru, uoff, un + sst);                                      \
+    _Pragma("unroll") for (int q = 0; q < MF_T; ++q)                             \
+      acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_, w[(q - 2 * (st) + MF_WIN * 4) % MF_WIN], acc[q], 0, 0, 0); \
+    ap += 2 * sst;                                                               \
+    un -= 2 * sst;                                                               \
+    __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);                           \
+    __builtin_amdgcn_sched_group_barrier(0x008, MF_T, 0);                        \
+  } while (0)
+
+  if (tb0 < tb1) MF_PROLOGUE(tb0);
   for (int tb = tb0; tb < tb1; ++tb) {
-    const int t0 = MF_T * tb;
     v16i acc[MF_T];
 #pragma unroll
     for (int q = 0; q < MF_T; ++q) acc[q] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int jlo = t0 - (S - 1);
-    if (jlo < 0) jlo = 0;
-    jlo &= ~1;
-    int jhi = t0 + MF_T - 1;
-    if (jhi > S - 1) jhi = S - 1;
-    // steps of two digits, padded to whole rotations of the register window;
-    // the extra steps pair A digits with zero B padding (or the reverse) and
-    // add nothing
-    const int nsteps = (jhi - jlo) / 2 + 1;
-    const int nrot = (nsteps + MF_ROT - 1) / MF_ROT;
-    // Window slot (y mod MF_WIN) holds the slice at offset t0 - jlo + y; step s
-    // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -2 MF_PF - 2s,
-    // -2 MF_PF + 1 - 2s for step s + MF_PF.  A digits are likewise loaded
-    // MF_PF steps ahead into a ring.
-    const int ub = (pad - 1 + t0 - jlo) * sst;
-    v4i w[MF_WIN];
-#pragma unroll
-    for (int y = 0; y < MF_T; ++y) w[y] = bld16(ru, uoff, ub + y * sst);
-#pragma unroll
-    for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = bld16(ru, uoff, ub + y * sst);
-    int ap = (pad + jlo) * sst;
-    v4i an[MF_PF];
-#pragma unroll
-    for (int q = 0; q < MF_PF; ++q) an[q] = bld16(rb, aoff, ap + 2 * q * sst);
-    ap += 2 * MF_PF * sst;
-    int un = ub - 2 * MF_PF * sst;
     // Let the prologue's loads land here, once per block: the loop header then
     // only sees the loads in flight from the previous rotation, and its wait
     // keeps the MF_PF steps of prefetch instead of draining them every rotation.
     __builtin_amdgcn_s_waitcnt(kVmcntZero);
-    for (int rot = 0; rot < nrot; ++rot) {
+    const int nfull = nsteps / MF_ROT, rem = nsteps - nfull * MF_ROT;
+    for (int rot = 0; rot < nfull; ++rot) {
 #pragma unroll
-      for (int st = 0; st < MF_ROT; ++st) {
-        const v4i a = an[st % MF_PF];
-        an[st % MF_PF] = bld16(rb, aoff, ap);
-        const int k0 = (MF_WIN * 4 - 2 * MF_PF - 2 * st) % MF_WIN;  // slot of y = -2 MF_PF - 2 st (even)
-        w[k0] = bld16(ru, uoff, un);
-        w[k0 + 1] = bld16(ru, uoff, un + sst);
-#pragma unroll
-        for (int q = 0; q < MF_T; ++q)
-          acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, w[(q - 2 * st + MF_WIN * 4) % MF_WIN], acc[q], 0, 0, 0);
-        ap += 2 * sst;
-        un -= 2 * sst;
-        __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, MF_T, 0);
-      }
+      for (int st = 0; st < MF_ROT; ++st) MF_STEP(st);
     }
-    // fold the 16 digit sums of each entry into limbs 4 tb .. 4 tb + 3 (one slab)
+    // the last partial rotation: steps past the block's end are skipped
+#pragma unroll
+    for (int st = 0; st < MF_ROT - 1; ++st)
+      if (st < rem) MF_STEP(st);
+    // the next block's first operands, in flight during the fold
+    if (tb + 1 < tb1) MF_PROLOGUE(tb + 1);
+    // fold the 16 digit sums of each entry into limbs 4 tb .. 4 tb + 3 (one
+    // slab): V = sum_k d_k 2^(32 k) + carry, d_k = sum_m out_(t0+4k+m) 2^(8 m),
+    // resolved 32 bits at a time (|d_k| < 2^53, so every partial sum is exact
+    // in 64 bits); the limbs are V mod 2^128 (or the old limbs minus the sums
+    // plus the carry), the carry V >> 128
+    const int m8 = opaque_i32(1 << 8), m16 = opaque_i32(1 << 16), m24 = opaque_i32(1 << 24);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       if (!((live >> v) & 1u)) continue;
       const int r = mf_row(l, v), c = mf_col(l);
       uint4* p = (uint4*)(Out + in_tile(r, c, MF_LPB * tb));
-      i64 d[4] = {0, 0, 0, 0};
+      i64 d[4];
 #pragma unroll
-      for (int q = 0; q < MF_T; ++q) d[q >> 2] += (i64)acc[q][v] << (8 * (q & 3));
-      __int128 X, Y;
+      for (int k = 0; k < 4; ++k) {
+        i64 x = (i64)acc_elem(acc[4 * k][v]);
+        x = mad_digit(acc_elem(acc[4 * k + 1][v]), m8, x);
+        x = mad_digit(acc_elem(acc[4 * k + 2][v]), m16, x);
+        d[k] = mad_digit(acc_elem(acc[4 * k + 3][v]), m24, x);
+      }
+      i64 cy = carry_s[v * WAVE + l];
+      u32 o[4];
       if (STORE) {
-        X = (__int128)d[0] + ((__int128)d[1] << 32) + (__int128)carry_s[v * WAVE + l];
-        Y = (__int128)d[2] + ((__int128)d[3] << 32) + (__int128)(i64)(X >> 64);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const i64 t = d[k] + cy;
+          o[k] = (u32)t;
+          cy = t >> 32;
+        }
       } else {
         const uint4 x = *p;
-        X = (__int128)(((u64)x.y << 32) | x.x) - (__int128)d[0] - ((__int128)d[1] << 32) +
-            (__int128)carry_s[v * WAVE + l];
-        Y = (__int128)(((u64)x.w << 32) | x.z) - (__int128)d[2] - ((__int128)d[3] << 32) + (__int128)(i64)(X >> 64);
+        const u32 xa[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const i64 t = (i64)xa[k] - d[k] + cy;
+          o[k] = (u32)t;
+          cy = t >> 32;
+        }
       }
-      const u64 lo = (u64)X, hi = (u64)Y;
-      *p = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
-      carry_s[v * WAVE + l] = (i64)(Y >> 64);
+      *p = make_uint4(o[0], o[1], o[2], o[3]);
+      carry_s[v * WAVE + l] = cy;
     }
   }
+#undef MF_STEP
+#undef MF_PROLOGUE
   // carries out of this range
 #pragma unroll
   for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry_s[v * WAVE + l];

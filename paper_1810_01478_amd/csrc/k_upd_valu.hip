@@ -267,6 +267,46 @@ hipError_t launch_upd_valu(const UpdArgs& g, hipStream_t stream) {
   return launch_any(&g, nullptr, 1, nr, nc, g.nw, g.nl, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Issue-rate probe of the vector ALU's integer multiply-add (the plain form's
+// limb product): every lane runs 8 independent chains of iters steps, either
+// the plain form's pair (v_mad_u64_u32 into a 64-bit accumulator and
+// v_addc_co_u32 of its carry into a count, MODE 0) or v_mad_u64_u32 alone
+// (MODE 1).  Operands stay in registers, so nothing but the ALU is measured.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_valu_peak(int iters, u64* sink) {
+  const u32 b = threadIdx.x * 2654435761u + blockIdx.x;
+  u64 lo[8];
+  u32 hi[8], a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    lo[k] = k;
+    hi[k] = 0;
+    a[k] = (b ^ (0x9e3779b9u * (k + 1))) | 1u;
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (MODE == 0)
+        mac96(lo[k], hi[k], a[k], b);
+      else
+        asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(lo[k]) : "v"(a[k]), "v"(b) : "vcc");
+    }
+  }
+  u64 s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += lo[k] + hi[k];
+  if (s == 0x0123456789abcdefull) sink[0] = s;  // keeps the chains live
+}
+
+hipError_t launch_valu_peak(int mode, int blocks, int iters, u64* sink, hipStream_t stream) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_valu_peak<0>, dim3(blocks), dim3(256), 0, stream, iters, sink);
+  else
+    hipLaunchKernelGGL(k_valu_peak<1>, dim3(blocks), dim3(256), 0, stream, iters, sink);
+  return hipGetLastError();
+}
+
 hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int nc_max, int nw_max, int nl_max,
                                  hipStream_t stream) {
   return launch_any(nullptr, tab, count, nr_max, nc_max, nw_max, nl_max, stream);
