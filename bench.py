@@ -46,7 +46,7 @@ WORKLOADS = {
 MFMA_INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA, MI355X: 5.0 POP/s
 # vector-ALU 32 x 32 -> 64-bit integer multiply-add (v_mad_u64_u32, the plain
 # form's limb product): 256 CUs x 4 SIMDs x 16 lanes, one per lane and clock
-# (the issue-rate probe measures 82% of this at the clock the GPU holds), at
+# (the issue-rate probe measures about 80% of this at the clock the GPU holds), at
 # 2.4 GHz
 VALU_MAD_PEAK = 256 * 4 * 16 * 2.4e9
 
@@ -60,15 +60,18 @@ def schur_limb_macs(N, nl):
 def measured_traffic(workload, kernel="k_upd_mfma"):
     """HBM traffic per trailing-update launch from the rocprofv3 counter runs
     recorded under profiles/, if they were taken on this workload and on the
-    kernel source as it is now; else None."""
+    kernel sources (the tile loop and its constants) as they are now; else
+    None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", kernel + "_c4_traffic.json")
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        for name, digest in rec["sources"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, name), "rb").read()).hexdigest() != digest:
+                return None
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
-    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if rec.get("workload") != workload:
         return None
     return float(rec["bytes_per_launch"])
 
