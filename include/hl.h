@@ -363,6 +363,13 @@ typedef struct {
 hl_status hl_set_timing(hl_ctx *ctx, int enable);
 hl_status hl_get_timing(hl_ctx *ctx, hl_timing_t *out);
 
+/* Iteration limit of the eigen-step of hl_lambda_min and hl_lambda_min_noalloc
+ * on this context, per block: 0 (the default) keeps the built-in limit of 400;
+ * a smaller limit makes a call that needs more iterations return HL_ENOCONV
+ * with the block as index (0: the k x k block, 1: the leading (k-1) x (k-1)
+ * block).  For exercising that error path; EINVAL for a negative limit. */
+hl_status hl_set_eig_maxit(hl_ctx *ctx, int32_t maxit);
+
 /* Test hooks (not part of the method): exact products and the pivot
  * reciprocal on the device, for checking the multi-limb primitives against
  * host integers. */

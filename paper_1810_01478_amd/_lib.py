@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "HL_OK", 1: "HL_EINVAL", 2: "HL_ENOTPD", 3: "HL_EOVERFLOW", 4
                 5: "HL_EHIP", 6: "HL_ENOMEM"}
 
 EXPORTS = ["hl_create", "hl_destroy", "hl_last_error", "hl_get_sizes", "hl_factor", "hl_factor_cols", "hl_inv_block",
-           "hl_lambda_min", "hl_lambda_min_noalloc", "hl_lambda_next", "hl_sync", "hl_set_timing", "hl_set_karatsuba", "hl_get_timing", "hl_debug_mul", "hl_debug_recip", "hl_debug_valu_peak",
+           "hl_lambda_min", "hl_lambda_min_noalloc", "hl_lambda_next", "hl_sync", "hl_set_timing", "hl_set_karatsuba", "hl_set_eig_maxit", "hl_get_timing", "hl_debug_mul", "hl_debug_recip", "hl_debug_valu_peak",
            "hl_debug_mfma_layout", "hl_debug_mul_wg", "hl_lambda_grad", "hl_batch_plan_bytes", "hl_batch_create", "hl_batch_launch",
            "hl_batch_results", "hl_batch_destroy", "hl_autotune"]
 
@@ -103,6 +103,7 @@ def lib():
             "hl_sync": [P, P, P, ctypes.POINTER(I32)],
             "hl_set_timing": [P, ctypes.c_int],
             "hl_set_karatsuba": [P, ctypes.c_int32],
+            "hl_set_eig_maxit": [P, ctypes.c_int32],
             "hl_get_timing": [P, ctypes.POINTER(hl_timing_t)],
             "hl_debug_mul": [P, I32, P, I32, P, I32, P],
             "hl_debug_recip": [P, I32, I32, P, P, P],

@@ -299,6 +299,11 @@ class Context:
         precision (the default)."""
         L.check(L.lib().hl_set_karatsuba(self.h, int(mode)))
 
+    def set_eig_maxit(self, maxit: int):
+        """Iteration limit of the eigen-step per block (0: the default); a
+        smaller one makes eigen() raise HL_ENOCONV (exercises that path)."""
+        L.check(L.lib().hl_set_eig_maxit(self.h, int(maxit)))
+
     def timing(self):
         t = L.hl_timing_t()
         L.check(L.lib().hl_get_timing(self.h, ctypes.byref(t)))

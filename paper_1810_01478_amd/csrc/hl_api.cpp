@@ -19,6 +19,7 @@ struct hl_ctx {
   int device = 0;
   int timing = 0;
   int karatsuba = -1;  // Schur update form for MFMA shapes: -1 by precision, else Karatsuba levels (0 = digit product)
+  int eig_maxit = 0;   // iteration limit of the eigen-step per block (0: the default)
   // pivot lookahead of the MFMA form: a second stream (default priority) and
   // the events joining it to the caller's
   hipStream_t aux = nullptr;
@@ -268,6 +269,15 @@ extern "C" hl_status hl_destroy(hl_ctx* ctx) {
   delete ctx;
   return HL_OK;
 }
+
+extern "C" hl_status hl_set_eig_maxit(hl_ctx* ctx, int32_t maxit) {
+  if (!ctx) return fail(HL_EINVAL, "null ctx");
+  if (maxit < 0) return fail(HL_EINVAL, "maxit=%d must be >= 0", maxit);
+  ctx->eig_maxit = maxit;
+  return HL_OK;
+}
+
+int hl::ctx_eig_maxit(const hl_ctx* ctx) { return ctx ? ctx->eig_maxit : 0; }
 
 extern "C" hl_status hl_set_timing(hl_ctx* ctx, int enable) {
   if (!ctx) return fail(HL_EINVAL, "null ctx");
@@ -738,7 +748,7 @@ extern "C" hl_status hl_lambda_min(hl_ctx* ctx, const hl_shape* sh, const uint32
   void* ews = base + L.eig;
   Stamp te(ctx, st, 4);
   HIPCHK(ensure_aux(ctx));
-  HIPCHK(launch_eig_host(blk, dm, ews, dst, st, ctx->aux));
+  HIPCHK(launch_eig_host(blk, dm, ews, dst, st, ctx->aux, ctx->eig_maxit));
   te.end();
   int32_t idx = 0;
   if ((s = hl_sync(ctx, ws, stream, &idx)) != HL_OK) return s;

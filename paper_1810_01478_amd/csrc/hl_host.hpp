@@ -52,6 +52,8 @@ Layout make_layout(const Dims& dm);
 size_t eig_ws_bytes(const Dims& dm);
 hl_status read_lambda(const Dims& dm, void* eig_ws, int64_t bexp, uint32_t* lam_mant, uint32_t* lam_mant_km1,
                       hl_lambda_t* out);
+// the eigen-step iteration limit set on a context (0: the default)
+int ctx_eig_maxit(const hl_ctx* ctx);
 // looks up, once per device, the device address of hl_lambda_min_noalloc's scratch
 hipError_t noalloc_init(int device);
 struct ToepArgs;

@@ -239,12 +239,14 @@ struct EigArgs {
   size_t nums_per;
   int* flags;
   DevStatus* st;
+  int maxit;  // iteration limit of each block's eigen-step
 };
 EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st);
 // the same eigen-step driven from the host, one workgroup per product (synchronises)
 // aux: an optional second stream for the (k-1) x (k-1) block (nullptr: one stream)
+// maxit: iteration limit per block (0: the default, 400); ENOCONV beyond it
 hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream,
-                           hipStream_t aux = nullptr);
+                           hipStream_t aux = nullptr, int maxit = 0);
 hipError_t launch_eig_batch(const EigArgs* tab, int count, int nl_max, hipStream_t stream);
 void eig_result_refs(const Dims& dm, void* eig_ws, int which, int** hdr_out, u32** mant_out);
 void eig_vector_refs(const Dims& dm, void* eig_ws, int** hdr_out, u32** mant_out);

@@ -87,7 +87,7 @@ extern "C" hl_status hl_lambda_min_noalloc(hl_ctx* ctx, const hl_shape* sh, cons
   // the array keeps the last call's contents: clear the status word and the
   // whole work area first (a fill kernel, no memset node)
   NACHK(launch_fill((u32*)base, need / 4, 0u, st));
-  NACHK(launch_eig_host(blk, dm, ews, dst, st, nullptr));
+  NACHK(launch_eig_host(blk, dm, ews, dst, st, nullptr, ctx_eig_maxit(ctx)));
   NACHK(hipStreamSynchronize(st));
   unsigned long long v = 0;
   NACHK(hipMemcpy(&v, dst, 8, hipMemcpyDeviceToHost));

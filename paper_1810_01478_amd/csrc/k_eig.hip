@@ -558,7 +558,7 @@ __device__ void eig_body(const EigArgs& ea, int which) {
     float cexp = 2.0f;  // log2 of the constant c in hi' = lo + c (hi - lo)^2 / hi
     int it = 0;
     bool have_factor = false;
-    for (; it < EIG_MAXIT; ++it) {
+    for (; it < ea.maxit; ++it) {
       if (!have_factor) {
         const bool pd = eig_factor(M, c, num(M, ix_s(n, S_HI)), lds_int + 4);
         if (!pd) {
@@ -650,7 +650,7 @@ __device__ void eig_body(const EigArgs& ea, int which) {
       }
     }
     if (threadIdx.x == 0) M.flags[1] = it;
-    if (it >= EIG_MAXIT) {
+    if (it >= ea.maxit) {
       if (threadIdx.x == 0) set_status(st, HL_ENOCONV, which);
       return;
     }
@@ -1270,7 +1270,7 @@ static hipError_t eig2_block(const EigArgs& a, int which, hipStream_t st, int* c
       return hipSuccess;
     };
     int it = 0;
-    for (; it < EIG_MAXIT; ++it) {
+    for (; it < a.maxit; ++it) {
       if (!have_factor) {
         E2CHK(factor(S_HI));
         const int pd = read_flag(a, which, 2, st, &err);
@@ -1325,7 +1325,7 @@ static hipError_t eig2_block(const EigArgs& a, int which, hipStream_t st, int* c
     }
     hipLaunchKernelGGL(k_e2_control, dim3(1), dim3(64), lw, st, a, which, nw, 3, it);
     E2CHK(hipGetLastError());
-    if (it >= EIG_MAXIT) {
+    if (it >= a.maxit) {
       *conv = 0;
       return hipSuccess;
     }
@@ -1367,8 +1367,9 @@ static hipError_t eig2_noconv(DevStatus* st, int which, hipStream_t stream) {
 // while the k x k block runs on the caller's: their launches are small and
 // their workspace regions disjoint, so the two iterations overlap.
 hipError_t launch_eig_host(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream,
-                           hipStream_t aux) {
-  const EigArgs a = eig_args(blk, dm, eig_ws, st);
+                           hipStream_t aux, int maxit) {
+  EigArgs a = eig_args(blk, dm, eig_ws, st);
+  if (maxit > 0) a.maxit = maxit;
   E2CHK(eig2_attrs(eig2_lds_bytes(a.NWM)));
   bool stop = false;
   E2CHK(eig2_status(st, stream, &stop));
@@ -1456,6 +1457,7 @@ EigArgs eig_args(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st) {
   a.hdr = a.flags + EIG_FLAG_INTS;
   a.mant = (u32*)(a.hdr + 2 * EIG_MATS * a.nums_per);
   a.st = st;
+  a.maxit = EIG_MAXIT;
   return a;
 }
 
