@@ -55,6 +55,44 @@ def build(jobs=None, verbose=False):
     return LIB
 
 
+def build_host_sanitized(out_dir, driver_src, jobs=None):
+    """The library's sources and a host driver built with AddressSanitizer and
+    UBSan on the host code only (the device code is compiled as usual), linked
+    into one executable in out_dir; returns its path.  For host-side checks on
+    a machine without a GPU."""
+    os.makedirs(out_dir, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    flags = ["--offload-arch=" + ARCH, "-O1", "-g", "-std=c++17", "-fPIC", "-I" + os.path.join(HERE, "..", "include")]
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + flags + (DEVICE_FLAGS if src.endswith(".hip") else []) + san + \
+            ["-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, r.returncode, r.stderr
+
+    objs = []
+    with ThreadPoolExecutor(jobs or min(8, os.cpu_count() or 1)) as ex:
+        for src, obj, rc, err in ex.map(one, srcs):
+            if rc != 0:
+                raise RuntimeError("hipcc (sanitized host) failed on %s:\n%s" % (src, err))
+            objs.append(obj)
+    clangxx = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clangxx):
+        clangxx = "/opt/rocm/llvm/bin/clang++"
+    drv_obj = os.path.join(out_dir, "driver.o")
+    exe = os.path.join(out_dir, "driver")
+    for cmd in ([clangxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                 "-I" + os.path.join(HERE, "..", "include"), "-c", driver_src, "-o", drv_obj],
+                [clangxx, "-fsanitize=address,undefined", drv_obj] + objs +
+                ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", exe]):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("sanitized driver build failed:\n" + r.stdout + r.stderr)
+    return exe
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)

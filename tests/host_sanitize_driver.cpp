@@ -1,0 +1,96 @@
+// Host-side checks of libhankel under AddressSanitizer and UBSan (built by
+// paper_1810_01478_amd.build.build_host_sanitized; no GPU is touched).
+//
+// Reads instance shapes "N k P E form" from stdin, then
+//   * hl_get_sizes of every shape and of a grid of shapes at the edges of the
+//     supported ranges, and the argument checks of the entry points;
+//   * hl_batch_plan_bytes of the whole batch under several launch shapes (the
+//     batch planner: per-instance layouts, update steps, work-item queues,
+//     Toeplitz records), with stand-in device addresses that are never
+//     dereferenced.
+// Exits 0 when every call returns the expected status.
+#include <cstdio>
+#include <vector>
+
+#include "hl.h"
+
+static int fails = 0;
+#define EXPECT(c)                                                  \
+  do {                                                             \
+    if (!(c)) {                                                    \
+      printf("FAIL line %d: %s (%s)\n", __LINE__, #c, hl_last_error()); \
+      ++fails;                                                     \
+    }                                                              \
+  } while (0)
+
+int main() {
+  std::vector<hl_instance> v;
+  size_t fake = 0x100000;
+  auto addr = [&](size_t bytes) {
+    const size_t a = fake;
+    fake += (bytes + 4095) / 4096 * 4096 + 4096;
+    return (void*)a;
+  };
+  int N, k, P, E, form;
+  while (scanf("%d %d %d %d %d", &N, &k, &P, &E, &form) == 5) {
+    hl_instance in{};
+    in.shape = hl_shape{N, k, P, E, form};
+    hl_sizes sz{};
+    EXPECT(hl_get_sizes(&in.shape, &sz) == HL_OK);
+    in.mu = (const uint32_t*)addr(8);
+    in.mu_exp = (const int64_t*)addr(8);
+    in.w = 1;
+    in.ws = addr(sz.workspace_bytes);
+    in.ws_bytes = sz.workspace_bytes;
+    in.f.d = (uint32_t*)addr(sz.d_words * 4);
+    in.f.h = (int32_t*)addr((size_t)N * 4);
+    in.f.s = (int32_t*)addr((size_t)N * 4);
+    in.f.l = (uint32_t*)addr(sz.l_words * 4);
+    in.x = (uint32_t*)addr(sz.x_words * 4);
+    in.blk = (uint32_t*)addr(sz.blk_words * 4);
+    in.blk_exp = (int64_t*)addr(8);
+    v.push_back(in);
+  }
+  // sizes over the edges of the supported shapes
+  const int Ns[] = {1, 2, 31, 32, 33, 64, 1000, 1024, 4500, 8192};
+  const int Ps[] = {256, 384, 1024, 8192, 16384, 32768, 49152, 57344};
+  for (int n : Ns)
+    for (int p : Ps)
+      for (int f = 0; f < 2; ++f) {
+        hl_shape sh{n, n < 16 ? n : 16, p, 16, f};
+        hl_sizes sz{};
+        EXPECT(hl_get_sizes(&sh, &sz) == HL_OK);
+        EXPECT(sz.nl == p / 32 && sz.NT >= n && sz.workspace_bytes > 0);
+      }
+  hl_shape bad[] = {{0, 1, 256, 16, 0}, {8193, 8, 256, 16, 0}, {64, 33, 256, 16, 0}, {64, 8, 200, 16, 0},
+                    {64, 8, 65536, 16, 0}, {64, 8, 256, 0, 0}, {64, 8, 256, 16, 2}};
+  for (const hl_shape& sh : bad) {
+    hl_sizes sz{};
+    EXPECT(hl_get_sizes(&sh, &sz) == HL_EINVAL);
+  }
+  EXPECT(hl_factor(nullptr, &bad[0], nullptr, nullptr, 1, nullptr, 0, nullptr, nullptr) == HL_EINVAL);
+  EXPECT(hl_set_karatsuba(nullptr, 0) == HL_EINVAL);
+  EXPECT(hl_set_eig_maxit(nullptr, 1) == HL_EINVAL);
+  EXPECT(hl_lambda_min_noalloc(nullptr, &bad[0], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == HL_EINVAL);
+  size_t bytes = 0;
+  EXPECT(hl_batch_plan_bytes(0, v.data(), nullptr, &bytes) == HL_EINVAL);
+  if (!v.empty()) {
+    hl_instance broken = v[0];
+    broken.ws_bytes = 16;
+    EXPECT(hl_batch_plan_bytes(1, &broken, nullptr, &bytes) == HL_ENOMEM);
+    broken = v[0];
+    broken.x = nullptr;
+    EXPECT(hl_batch_plan_bytes(1, &broken, nullptr, &bytes) == HL_EINVAL);
+  }
+  // the batch planner under several launch shapes
+  const hl_tune_t tunes[] = {{2, 64, 0, 0}, {4, 16, 0, 0}, {8, 64, 4096, 0}, {1, 1, 1 << 20, 0}};
+  for (const hl_tune_t& t : tunes) {
+    bytes = 0;
+    EXPECT(hl_batch_plan_bytes((int)v.size(), v.data(), &t, &bytes) == HL_OK);
+    printf("plan %zu bytes (items per SIMD %d, range cap %d, VALU below %d bits)\n", bytes, t.items_per_simd,
+           t.range_cap, t.valu_below_bits);
+  }
+  EXPECT(hl_batch_plan_bytes((int)v.size(), v.data(), nullptr, &bytes) == HL_OK);
+  printf("%d instances, %d failures\n", (int)v.size(), fails);
+  return fails ? 1 : 0;
+}
