@@ -73,15 +73,14 @@ hl_status make_dims(const hl_shape* sh, Dims* dm) {
   dm->E = sh->exp_block;
   dm->k = sh->k;
   dm->W = 2 * sh->prec_bits - 4;
-  // Karatsuba levels offered: the split points on whole slabs (P a multiple of
-  // 256, 512, 1024), and beyond the default level only while the products fit
-  // kKaraExtraBytes
+  dm->Sk0 = (dm->S + 127) / 128 * 128;
+  // Karatsuba levels offered: every level splits the Sk0-digit strings on whole
+  // slabs; beyond the default level only while the products fit kKaraExtraBytes
   dm->kara = 0;
   if (sh->form == HL_FORM_MFMA8)
     for (int lv = 1; lv <= KA_MAX_LEVELS; ++lv) {
-      if (sh->prec_bits % (128 << lv)) break;
       const size_t tri = (size_t)dm->nt * (dm->nt + 1) / 2;
-      const size_t bytes = (size_t)kara_products(lv) * tri * tile_words(kara_nwp(dm->S, lv)) * 4;
+      const size_t bytes = (size_t)kara_products(lv) * tri * tile_words(kara_nwp(dm->Sk0, lv)) * 4;
       if (lv > kara_auto_level(dm->P) && bytes > kKaraExtraBytes) break;
       dm->kara = lv;
     }
@@ -120,7 +119,7 @@ Layout make_layout(const Dims& dm) {
     for (int lv = 1; lv <= dm.kara; ++lv) {
       // the Karatsuba forms have 3^lv products per tile
       const size_t np = kara_products(lv);
-      const size_t ntbp = (size_t)kara_nwp(dm.S, lv) / 4;
+      const size_t ntbp = (size_t)kara_nwp(dm.Sk0, lv) / 4;
       const size_t kuse = np * tri * (kMaxRanges < ntbp ? kMaxRanges : ntbp);
       const size_t kt = 16384 + np * tri < kuse ? 16384 + np * tri : kuse;
       if (kt > L.carry_tiles) L.carry_tiles = kt;
@@ -196,11 +195,11 @@ Layout make_layout(const Dims& dm) {
     L.kara_tiles = (size_t)dm.nt * (dm.nt + 1) / 2;
     size_t words = 0;
     for (int lv = 1; lv <= dm.kara; ++lv) {
-      L.kara_pan_slices[lv] = kara_leaf_digits(dm.S, lv) + 2 * kDigitPad;
+      L.kara_pan_slices[lv] = kara_leaf_digits(dm.Sk0, lv) + 2 * kDigitPad;
       L.kara_pan_bytes[lv] = al((size_t)L.kara_pan_slices[lv] * dm.NT * 16);
       L.kara_pan[lv] = off;
       off += 2 * kara_products(lv) * L.kara_pan_bytes[lv];
-      const size_t w = kara_products(lv) * L.kara_tiles * tile_words(kara_nwp(dm.S, lv));
+      const size_t w = kara_products(lv) * L.kara_tiles * tile_words(kara_nwp(dm.Sk0, lv));
       if (w > words) words = w;
     }
     L.kara_prod = off;
@@ -528,16 +527,17 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         if (kara_lv > 0) {
           KaraArgs ka{};
           ka.m = m;
+          ka.m.S = dm.Sk0;  // the Karatsuba form's digit strings (zero digits above S)
           ka.levels = kara_lv;
           for (int lv = 1; lv <= kara_lv; ++lv) {
             ka.pan[lv] = (int8_t*)(base + L.kara_pan[lv]);
             ka.pan_stride[lv] = L.kara_pan_bytes[lv];
             ka.pan_slices[lv] = L.kara_pan_slices[lv];
           }
-          ka.Sk = kara_leaf_digits(dm.S, kara_lv);
+          ka.Sk = kara_leaf_digits(dm.Sk0, kara_lv);
           ka.kslices = ka.Sk + 2 * kDigitPad;
           ka.prod = (u32*)(base + L.kara_prod);
-          ka.nwp = kara_nwp(dm.S, kara_lv);
+          ka.nwp = kara_nwp(dm.Sk0, kara_lv);
           ka.prod_tiles = L.kara_tiles;
           e = launch_upd_kara(ka, st);
         } else {

@@ -34,7 +34,9 @@ struct Dims {
   int E;         // exponent block
   int k;
   int W;         // 2P - 4
-  int kara;      // Karatsuba levels of the Schur update available: 0, 1 (MFMA form, P % 256 == 0), 2 (P % 512 == 0)
+  int kara;      // Karatsuba levels of the Schur update available (MFMA form): 0 .. 3
+  int Sk0;       // digits of a factor in the Karatsuba form: S rounded up to a multiple of 128
+                 // (zero digits on top), so every level splits on whole 16-digit slabs
 };
 
 // Trailing matrix: 32 x 32 tiles (R >= C) packed row by row; inside a tile the

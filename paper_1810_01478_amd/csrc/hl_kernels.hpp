@@ -161,7 +161,9 @@ constexpr int MF_BLOCK_DIGITS = 16;
 // mid) at z = Y^(2^(L-l)), from the trailing matrix with exact carries.
 constexpr int KA_MAX_LEVELS = 3;
 struct KaraArgs {
-  MfmaArgs m;          // target, pad, NT, S, carry slots (np x tiles x ranges), timing; bdig/udig unused
+  MfmaArgs m;          // target, pad, NT, carry slots (np x tiles x ranges), timing; bdig/udig unused;
+                       // S here is the digit count of the split strings, a multiple of 16 x 2^L at
+                       // least 4 nl (the digits above 4 nl are zero)
   int levels;          // L = 1 .. 3; np = 3^L products
   // level-l digit panels, l = 1 .. L: 3^l of b, then 3^l of u, pan_stride[l]
   // bytes apart, pan_slices[l] = S/2^l + l + 2 pad slices each; panel 3 q + c of

@@ -317,8 +317,12 @@ __device__ __forceinline__ void ka_terms(std::integer_sequence<int, TI...>, i64 
 // segments [M0, M1) of the entry: slab jj of each in registers, the products
 // reaching them streamed through once per jj; cy[m - M0] is the carry out of
 // segment m
+// Slabs at or above nq (the entry's nw / 4; there are some when the split
+// strings carry zero digits above the factors') are neither read nor written:
+// they only receive carries, and the entry keeps its value modulo 2^(32 nw).
 template <int LV, int M0, int M1>
-__device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_t pst, int O, i64 (&cy)[M1 - M0]) {
+__device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_t pst, int O, int nq,
+                                        i64 (&cy)[M1 - M0]) {
   constexpr int NS = M1 - M0;
 #pragma unroll
   for (int m = 0; m < NS; ++m) cy[m] = 0;
@@ -327,7 +331,8 @@ __device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_
     i64 s[NS][4];
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-      const uint4 a = ld_lane(At + (size_t)((M0 + m) * O + jj) * 4096, voff);
+      uint4 a = make_uint4(0u, 0u, 0u, 0u);
+      if ((M0 + m) * O + jj < nq) a = ld_lane(At + (size_t)((M0 + m) * O + jj) * 4096, voff);
       s[m][0] = a.x; s[m][1] = a.y; s[m][2] = a.z; s[m][3] = a.w;
     }
     ka_terms<LV, M0, M1>(std::make_integer_sequence<int, KaPoly<LV>::NT>{}, s, P0, voff, pst, O, jj);
@@ -338,8 +343,9 @@ __device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_
       s2 += s1 >> 32;
       s3 += s2 >> 32;
       cy[m] = s3 >> 32;
-      *(uint4*)((char*)(At + (size_t)((M0 + m) * O + jj) * 4096) + voff) =
-          make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
+      if ((M0 + m) * O + jj < nq)
+        *(uint4*)((char*)(At + (size_t)((M0 + m) * O + jj) * 4096) + voff) =
+            make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
     }
   }
 }
@@ -362,16 +368,16 @@ void k_kara_comb(KaraArgs k, int C_lo) {
   u32* At = g.A + tix * tile_words(g.nw);   // wave-uniform bases, the lane's offset apart
   const u32* P0 = k.prod + (size_t)lt * tw;
   const u32 voff = (u32)in_tile(r, c, 0) * 4;
-  const int O = k.m.S / (16 << LV);
+  const int O = k.m.S / (16 << LV), nq = g.nw / 4;
   if constexpr (NSEG <= 16) {
     i64 cy[NSEG];
-    ka_pass<LV, 0, NSEG>(At, P0, voff, pst, O, cy);
+    ka_pass<LV, 0, NSEG>(At, P0, voff, pst, O, nq, cy);
 #pragma unroll
     for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy[m]);
   } else {
     i64 cy0[8], cy1[NSEG - 8];
-    ka_pass<LV, 0, 8>(At, P0, voff, pst, O, cy0);
-    ka_pass<LV, 8, NSEG>(At, P0, voff, pst, O, cy1);
+    ka_pass<LV, 0, 8>(At, P0, voff, pst, O, nq, cy0);
+    ka_pass<LV, 8, NSEG>(At, P0, voff, pst, O, nq, cy1);
 #pragma unroll
     for (int m = 0; m < 8; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy0[m]);
 #pragma unroll
@@ -388,7 +394,7 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
   if (L < 1 || L > KA_MAX_LEVELS) return hipErrorInvalidValue;
   const int np = kara_products(L);
   // the split points on whole 4-limb slabs, padding, 32-bit buffer offsets
-  bool ok = m.S % (16 << L) == 0 && m.S == 4 * g.nl && k.Sk == kara_leaf_digits(m.S, L) &&
+  bool ok = m.S % (16 << L) == 0 && m.S >= 4 * g.nl && k.Sk == kara_leaf_digits(m.S, L) &&
             k.nwp == kara_nwp(m.S, L) && m.pad >= MF_PAD_MIN && k.kslices == k.Sk + 2 * m.pad &&
             k.nwp / 4 == 2 * (m.S / (16 << L)) + 1;
   for (int l = 1; l <= L; ++l)

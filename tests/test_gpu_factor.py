@@ -173,14 +173,15 @@ def test_mfma_equals_valu_bitwise_c2b_shape():
     (Fraction(1, 2), 80, 1024, 7),    # ragged last tile
     (Fraction(1, 3), 45, 1536, 1),
     (Fraction(1, 2), 100, 4096, 16),
-    (Fraction(1, 3), 20, 256, 1),     # shortest halves: 16 digits, one slab
+    (Fraction(1, 3), 20, 256, 1),     # 32 digits split as 128 (zero digits on top)
     (1, 97, 3072, 4),
+    (Fraction(1, 3), 128, 19072, 16),  # a batched-workload precision: 2384 digits split as 2432
 ])
 @pytest.mark.parametrize("levels", [1, 2, 3])
 def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E, levels):
     # the Karatsuba forms of the trailing update are exact: same bits as the
-    # oracle (two levels need P % 512 == 0, three P % 1024 == 0; a shape that
-    # allows fewer runs the deepest it allows)
+    # oracle at every level and precision (the split digit strings are the
+    # factor's S = P/8 digits with zero digits up to a multiple of 128)
     say("factor karatsuba", beta, N, P, E, levels)
     mu = moments(beta, 2 * N - 1)
     f = C.factor(mu, N, P, E)
@@ -223,6 +224,28 @@ def test_karatsuba_equals_digit_product_c2b_shape():
         c.set_karatsuba(-1)
     for f in got:
         assert torch.equal(fa.d, f.d) and torch.equal(fa.l, f.l) and torch.equal(fa.h, f.h)
+
+
+@pytest.mark.parametrize("N,P", [(200, 8320), (160, 10368)])
+def test_karatsuba_padded_digits_equal_digit_product(N, P):
+    # P not a multiple of 1024: the split strings carry zero digits above the
+    # factors' (1040 -> 1152, 1296 -> 1408 digits); every level gives the digit
+    # product's bits
+    import torch
+    say("karatsuba padded digits", N, P)
+    mu = moments(Fraction(1, 2), 2 * N - 1)
+    c = ctx()
+    try:
+        c.set_karatsuba(0)
+        fa = c.factor(mu, N, 8, P, 16, "mfma")
+        c.sync(fa)
+        for lv in (1, 2, 3):
+            c.set_karatsuba(lv)
+            fb = c.factor(mu, N, 8, P, 16, "mfma")
+            c.sync(fb)
+            assert torch.equal(fa.d, fb.d) and torch.equal(fa.l, fb.l) and torch.equal(fa.h, fb.h), lv
+    finally:
+        c.set_karatsuba(-1)
 
 
 def test_set_karatsuba_rejects_bad_mode():
