@@ -290,7 +290,9 @@ hl_status hl_lambda_grad(hl_ctx *ctx, const hl_shape *sh, const hl_factor_t *f, 
  * lock step over a global pivot counter, every launch covering every instance
  * that still has work (so the sequential chain of Algorithm 1 is paid once per
  * batch), the trailing updates of a step go to one persistent int8 MFMA launch
- * fed from per-XCD queues of work items, largest first, and the whole sequence
+ * fed from per-XCD queues of work items, largest first (an instance in the
+ * Karatsuba form contributes its 3^L digit-sum products, combined into its
+ * trailing matrix after the launch), and the whole sequence
  * (load, panels, the first k columns of L^-1, the blocks, the eigen-steps) is
  * captured once in a hipGraph and replayed.  Results are bit-identical to
  * hl_factor + hl_inv_block + hl_lambda_min on each instance.
@@ -313,7 +315,9 @@ typedef struct {
   int32_t items_per_simd;  /* MFMA work items per SIMD and step (granularity)        */
   int32_t range_cap;       /* most output-limb ranges per tile                        */
   int32_t valu_below_bits; /* instances with P below this use the VALU update form   */
-  int32_t reserved;
+  int32_t karatsuba;       /* trailing-update form of MFMA-form instances: 0 by
+                              precision (as hl_set_karatsuba(-1)), -1 the digit
+                              product, 1 .. 3 that many Karatsuba levels          */
 } hl_tune_t;
 
 typedef struct hl_batch hl_batch;
@@ -336,8 +340,9 @@ hl_status hl_batch_destroy(hl_batch *b);
 
 /* Autotuner: builds and times the batch's first `panels` panel steps under each
  * candidate launch shape (items per SIMD 2, 4, 8; range cap 16, 64; VALU
- * below 0, 4096 bits) and returns the fastest in *best (its time per
- * replay in *best_ms).  Uses the instances' workspaces and `plan` as scratch. */
+ * below 0, 4096 bits; Karatsuba by precision or the digit product) and returns
+ * the fastest in *best (its time per replay in *best_ms).  Uses the instances'
+ * workspaces and `plan` as scratch. */
 hl_status hl_autotune(hl_ctx *ctx, int32_t count, const hl_instance *inst, void *plan, size_t plan_bytes,
                       int32_t panels, hl_tune_t *best, double *best_ms);
 

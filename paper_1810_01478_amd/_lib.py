@@ -68,7 +68,7 @@ class hl_instance(ctypes.Structure):
 
 class hl_tune_t(ctypes.Structure):
     _fields_ = [("items_per_simd", ctypes.c_int32), ("range_cap", ctypes.c_int32),
-                ("valu_below_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("valu_below_bits", ctypes.c_int32), ("karatsuba", ctypes.c_int32)]
 
 
 class HLError(RuntimeError):

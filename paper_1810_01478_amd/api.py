@@ -435,7 +435,7 @@ def autotune(batch: Batch, panels: int = 2):
     torch.cuda.synchronize()
     del scratch
     return ({"items_per_simd": best.items_per_simd, "range_cap": best.range_cap,
-             "valu_below_bits": best.valu_below_bits}, ms.value)
+             "valu_below_bits": best.valu_below_bits, "karatsuba": best.karatsuba}, ms.value)
 
 
 def lambda_min(beta, N: int, k: int, P: int, E: int = 16, form: str = "mfma", mant_bits: int = 0,

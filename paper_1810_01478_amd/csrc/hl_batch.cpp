@@ -57,6 +57,7 @@ struct Inst {
   Dims dm;
   Layout L;
   int form;  // trailing-update form used in the batch
+  int kara;  // Karatsuba levels of its trailing updates (MFMA form; 0: the digit product)
   char* base;
   DevStatus* st;
   u32 *A, *up, *omega;
@@ -67,7 +68,7 @@ struct Inst {
 struct Op {
   enum Kind {
     FILL, SCALES, LOAD, PIVOT, COL, VALU, RECODE, MFMA, CARRY, TRSM_ROW, BLOCK, EIG, COLU, COLFIN, TOEP, BLOCKY,
-    BLOCKSUM
+    BLOCKSUM, KARA_PREP, KARA_FIN
   } kind;
   int inst = -1;           // FILL, SCALES, LOAD, BLOCK: the instance
   size_t off = 0;          // table offset
@@ -77,6 +78,8 @@ struct Op {
   u32* fp = nullptr;       // FILL target
   size_t fn = 0;           // FILL words
   size_t x[4] = {0, 0, 0, 0};  // TOEP: recode threads (b, u), work items, entries
+  KaraArgs ka{};           // KARA_PREP, KARA_FIN: the instance's Karatsuba record
+  RangeTab rt{};           // KARA_FIN: its ranges (a = C_lo, b = tiles)
 };
 
 // one batched Toeplitz-form launch set over prepared records
@@ -174,6 +177,25 @@ MfmaArgs mfma_args(const Inst& I, const UpdArgs& g, int u_rows) {
   return m;
 }
 
+// Karatsuba record of an instance's update g (as hl_factor builds it)
+KaraArgs kara_args(const Inst& I, const UpdArgs& g, int u_rows) {
+  KaraArgs ka{};
+  ka.m = mfma_args(I, g, u_rows);
+  ka.m.S = I.dm.Sk0;
+  ka.levels = I.kara;
+  for (int lv = 1; lv <= I.kara; ++lv) {
+    ka.pan[lv] = (int8_t*)(I.base + I.L.kara_pan[lv]);
+    ka.pan_stride[lv] = I.L.kara_pan_bytes[lv];
+    ka.pan_slices[lv] = I.L.kara_pan_slices[lv];
+  }
+  ka.Sk = kara_leaf_digits(I.dm.Sk0, I.kara);
+  ka.kslices = ka.Sk + 2 * kDigitPad;
+  ka.prod = (u32*)(I.base + I.L.kara_prod);
+  ka.nwp = kara_nwp(I.dm.Sk0, I.kara);
+  ka.prod_tiles = I.L.kara_tiles;
+  return ka;
+}
+
 // Work items of one step's MFMA entries into 8 per-XCD queues.  Bundles are the
 // tiles of one (entry, range), cut into chunks of at most 128 items (one round of
 // an XCD); chunks go to the least loaded XCD, largest item cost first.
@@ -238,18 +260,30 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
   // VALU-form instances
   std::vector<UpdArgs> vt;
   int nr = 0, nc = 0, nwm = 0, nlm = 0;
-  // MFMA-form instances
+  // MFMA-form instances: digit-product entries first (their carries are added
+  // into the targets by k_carry_fix_b), then the Karatsuba products
   std::vector<RecodeArgs> rc;
-  std::vector<MfmaEntry> ents;
+  std::vector<MfmaEntry> ents, kents;
+  std::vector<Op> kprep, kfin;
   int NTm = 0, nrowm = 0, ncolm = 0;
   double step_cost = 0;
+  // per update: the cost of one work item covering a whole tile (of one product
+  // for the Karatsuba form), its records
   std::vector<double> tile_cost(ups.size(), 0.0);
+  std::vector<KaraArgs> kas(ups.size());
   for (size_t j = 0; j < ups.size(); ++j) {
     const Inst& I = B->inst[ups[j].i];
     if (I.form != HL_FORM_MFMA8) continue;
-    const RangeTab one = split_ranges(I.dm.nl, I.dm.S, 1);
-    tile_cost[j] = item_cost(one, 0, I.dm.S);
-    step_cost += tile_cost[j] * ups[j].ntiles;
+    if (I.kara > 0) {
+      kas[j] = kara_args(I, ups[j].g, ups[j].u_rows);
+      const RangeTab one = split_ranges_ntb(kas[j].nwp / 4, kas[j].Sk, 1);
+      tile_cost[j] = item_cost(one, 0, kas[j].Sk);
+      step_cost += tile_cost[j] * ups[j].ntiles * kara_products(I.kara);
+    } else {
+      const RangeTab one = split_ranges(I.dm.nl, I.dm.S, 1);
+      tile_cost[j] = item_cost(one, 0, I.dm.S);
+      step_cost += tile_cost[j] * ups[j].ntiles;
+    }
   }
   for (size_t j = 0; j < ups.size(); ++j) {
     const StepUpd& u = ups[j];
@@ -260,6 +294,38 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
       nc = std::max(nc, u.g.c_hi - u.g.c_lo);
       nwm = std::max(nwm, I.dm.nw);
       nlm = std::max(nlm, I.dm.nl);
+      continue;
+    }
+    if (I.kara > 0) {
+      const KaraArgs& ka = kas[j];
+      const int np = kara_products(I.kara);
+      const int n = pick_ranges(tile_cost[j], step_cost, np * u.ntiles, ka.nwp / 4, B->tune, I.L.carry_tiles);
+      const RangeTab rt = split_ranges_ntb(ka.nwp / 4, ka.Sk, n);
+      for (int p = 0; p < np; ++p) {
+        MfmaEntry E{};
+        E.m = ka.m;
+        E.m.bdig = ka.pan[I.kara] + (size_t)p * ka.pan_stride[I.kara];
+        E.m.udig = ka.pan[I.kara] + (size_t)(np + p) * ka.pan_stride[I.kara];
+        E.m.slices = ka.kslices;
+        E.m.S = ka.Sk;
+        E.m.carry = ka.m.carry + (size_t)p * u.ntiles * rt.n * 1024;
+        E.rt = rt;
+        E.C_lo = u.C_lo;
+        E.ntiles = u.ntiles;
+        E.store = ka.prod + (size_t)p * ka.prod_tiles * tile_words(ka.nwp);
+        E.store_nw = ka.nwp;
+        kents.push_back(E);
+      }
+      Op o;
+      o.kind = Op::KARA_PREP;
+      o.inst = u.i;
+      o.ka = ka;
+      kprep.push_back(o);
+      o.kind = Op::KARA_FIN;
+      o.rt = rt;
+      o.a = u.C_lo;
+      o.b = u.ntiles;
+      kfin.push_back(o);
       continue;
     }
     rc.push_back(RecodeArgs{u.bsrc, u.blds, u.g.npan, I.dm.NT, I.dm.NT, I.dm.nl, kDigitPad,
@@ -289,13 +355,18 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
     o.d = nlm;
     B->ops.push_back(o);
   }
-  if (!ents.empty()) {
+  if (!rc.empty()) {
     Op r;
     r.kind = Op::RECODE;
     r.off = blob.put(rc);
     r.count = (int)rc.size();
     r.a = NTm;
     B->ops.push_back(r);
+  }
+  for (const Op& o : kprep) B->ops.push_back(o);
+  const int nd = (int)ents.size();
+  ents.insert(ents.end(), kents.begin(), kents.end());
+  if (!ents.empty()) {
     std::vector<MfmaEntry> e2;
     std::vector<int4> items;
     int per = 0;
@@ -307,14 +378,17 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
     m.count = (int)e2.size();
     m.a = per;
     B->ops.push_back(m);
-    Op c;
-    c.kind = Op::CARRY;
-    c.off = m.off;
-    c.count = (int)e2.size();
-    c.a = nrowm;
-    c.b = ncolm;
-    B->ops.push_back(c);
+    if (nd > 0) {
+      Op c;
+      c.kind = Op::CARRY;
+      c.off = m.off;  // the digit-product entries lead the table
+      c.count = nd;
+      c.a = nrowm;
+      c.b = ncolm;
+      B->ops.push_back(c);
+    }
   }
+  for (const Op& o : kfin) B->ops.push_back(o);
 }
 
 // Record the whole plan (max_panels < 0: everything; else only that many panel
@@ -338,6 +412,12 @@ hl_status record_plan(hl_batch* B, Blob& blob, int max_panels) {
     B->ops.push_back(f);
     f.fp = (u32*)(I.base + I.L.udig);
     B->ops.push_back(f);
+    for (int lv = 1; lv <= I.kara; ++lv) {
+      // zero digit slices: the padding and the digits above the factors' read as zero
+      f.fp = (u32*)(I.base + I.L.kara_pan[lv]);
+      f.fn = 2 * kara_products(lv) * I.L.kara_pan_bytes[lv] / 4;
+      B->ops.push_back(f);
+    }
     Op s;
     s.kind = Op::SCALES;
     s.inst = i;
@@ -769,6 +849,12 @@ hl_status issue(hl_batch* B, hipStream_t st) {
       case Op::TOEP:
         HIPCHK(launch_upd_toep_batch((const ToepArgs*)(P + o.off), o.count, o.x[0], o.x[1], o.x[2], o.x[3], o.a, st));
         break;
+      case Op::KARA_PREP:
+        HIPCHK(launch_kara_prep(o.ka, st));
+        break;
+      case Op::KARA_FIN:
+        HIPCHK(launch_kara_finish(o.ka, o.rt, o.a, o.b, st));
+        break;
     }
   }
   return HL_OK;
@@ -823,6 +909,11 @@ hl_status init_batch(hl_ctx* ctx, int32_t count, const hl_instance* inst, const 
     Inst& I = B->inst[i];
     I.form = I.in.shape.form;
     if (I.dm.P < B->tune.valu_below_bits) I.form = HL_FORM_VALU;
+    I.kara = 0;
+    if (I.form == HL_FORM_MFMA8) {
+      const int want = B->tune.karatsuba == 0 ? kara_auto_level(I.dm.P) : std::max(0, B->tune.karatsuba);
+      I.kara = std::min(want, I.dm.kara);
+    }
     B->nl_max = std::max(B->nl_max, I.dm.nl);
   }
   return HL_OK;
@@ -901,7 +992,7 @@ extern "C" hl_status hl_batch_destroy(hl_batch* B) {
 // Autotuner: times the first `panels` panel steps of the factorisation under
 // each candidate tuning (each replayed `reps` times after one warm-up) and
 // returns the fastest.  Candidates: items per SIMD in {2, 4, 8} x range cap
-// in {16, 64} x VALU below {0, 4096} bits.  Results are bit-identical
+// in {16, 64} x VALU below {0, 4096} bits x Karatsuba by precision or not.  Results are bit-identical
 // under every candidate; only the time differs.
 extern "C" hl_status hl_autotune(hl_ctx* ctx, int32_t count, const hl_instance* inst, void* plan, size_t plan_bytes,
                                  int32_t panels, hl_tune_t* best, double* best_ms) {
@@ -909,6 +1000,7 @@ extern "C" hl_status hl_autotune(hl_ctx* ctx, int32_t count, const hl_instance* 
   const int ips[] = {2, 4, 8};
   const int caps[] = {16, 64};
   const int valu[] = {0, 4096};
+  const int kara[] = {0, -1};
   double bt = 1e300;
   hl_tune_t bb{4, kMaxRanges, 0, 0};
   hipStream_t st = nullptr;
@@ -919,8 +1011,9 @@ extern "C" hl_status hl_autotune(hl_ctx* ctx, int32_t count, const hl_instance* 
   hl_status result = HL_OK;
   for (int a : ips)
     for (int c : caps)
-      for (int v : valu) {
-        hl_tune_t t{a, c, v, 0};
+      for (int v : valu)
+        for (int kk : kara) {
+        hl_tune_t t{a, c, v, kk};
         hl_batch B;
         hl_status s = init_batch(ctx, count, inst, &t, plan, plan_bytes, &B);
         if (s == HL_OK) s = build(&B, panels > 0 ? panels : 2);

@@ -178,6 +178,10 @@ struct KaraArgs {
   size_t prod_tiles;   // tiles per product
 };
 hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream);
+// its pieces: the digit panels of every level before the GEMMs, and after them
+// the range carries and the combination into the trailing matrix
+hipError_t launch_kara_prep(const KaraArgs& k, hipStream_t stream);
+hipError_t launch_kara_finish(const KaraArgs& k, const RangeTab& rt, int C_lo, int ntiles, hipStream_t stream);
 // the digit-sum GEMMs alone (k_upd_mfma.hip), 8 x per_xcd work items
 hipError_t launch_kara_gemm(const KaraArgs& k, const RangeTab& rt, int C_lo, int ntiles, int per_xcd,
                             hipStream_t stream);
@@ -195,6 +199,11 @@ struct MfmaEntry {
   RangeTab rt;
   int C_lo;
   int ntiles;
+  // null: the sums are subtracted from the target (m.g); else the exact sums of
+  // launch tile lt are stored at store + lt * tile_words(store_nw) (a Karatsuba
+  // product of the digit panels m.bdig, m.udig)
+  u32* store;
+  int store_nw;
 };
 struct RecodeArgs {
   const u32* src;

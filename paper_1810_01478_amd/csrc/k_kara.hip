@@ -385,14 +385,12 @@ void k_kara_comb(KaraArgs k, int C_lo) {
   }
 }
 
-hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
+// checks of a Karatsuba record against its launch shapes
+static bool kara_ok(const KaraArgs& k) {
   const MfmaArgs& m = k.m;
   const UpdArgs& g = m.g;
-  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
-  if (!g.tri || (g.rsb != 0 && g.rsb != (size_t)g.nl)) return hipErrorInvalidValue;
-  const int L = k.levels, h = m.S / 2;
-  if (L < 1 || L > KA_MAX_LEVELS) return hipErrorInvalidValue;
-  const int np = kara_products(L);
+  const int L = k.levels;
+  if (L < 1 || L > KA_MAX_LEVELS || !g.tri || (g.rsb != 0 && g.rsb != (size_t)g.nl)) return false;
   // the split points on whole 4-limb slabs, padding, 32-bit buffer offsets
   bool ok = m.S % (16 << L) == 0 && m.S >= 4 * g.nl && k.Sk == kara_leaf_digits(m.S, L) &&
             k.nwp == kara_nwp(m.S, L) && m.pad >= MF_PAD_MIN && k.kslices == k.Sk + 2 * m.pad &&
@@ -400,7 +398,17 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
   for (int l = 1; l <= L; ++l)
     ok = ok && k.pan[l] && k.pan_slices[l] == kara_leaf_digits(m.S, l) + 2 * m.pad &&
          (size_t)k.pan_slices[l] * m.NT * 16 <= 0x7fffffffu && k.pan_stride[l] >= (size_t)k.pan_slices[l] * m.NT * 16;
-  if (!ok) return hipErrorInvalidValue;
+  return ok;
+}
+
+// the digit panels of every level: the factors' halves, their sums, and the
+// splits of each level's panels (before the GEMMs)
+hipError_t launch_kara_prep(const KaraArgs& k, hipStream_t stream) {
+  const MfmaArgs& m = k.m;
+  const UpdArgs& g = m.g;
+  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  if (!kara_ok(k)) return hipErrorInvalidValue;
+  const int L = k.levels, h = m.S / 2;
   const size_t rthreads = (size_t)g.nl * m.NT * 16;
   const unsigned rblocks = (unsigned)((rthreads + 255) / 256);
   int8_t* l1[6];
@@ -423,8 +431,31 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
     const size_t mthreads = (size_t)((s + l - 1) / 4 + 1) * m.NT;
     hipLaunchKernelGGL(k_kara_mid_lv, dim3((unsigned)((mthreads + 255) / 256), parents), dim3(256), 0, stream, k, l);
   }
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+// the products' range carries, then their combination into the trailing
+// matrix (after the GEMMs of a launch of ntiles tiles from tile row C_lo)
+hipError_t launch_kara_finish(const KaraArgs& k, const RangeTab& rt, int C_lo, int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  const int L = k.levels, np = kara_products(L);
+  if (rt.n > 1) hipLaunchKernelGGL(k_kara_fix, dim3(4 * ntiles, np), dim3(256), 0, stream, k, rt, C_lo, ntiles);
+  if (L == 1)
+    hipLaunchKernelGGL(k_kara_comb<1>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+  else if (L == 2)
+    hipLaunchKernelGGL(k_kara_comb<2>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+  else
+    hipLaunchKernelGGL(k_kara_comb<3>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
+  const MfmaArgs& m = k.m;
+  const UpdArgs& g = m.g;
+  if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
+  hipError_t e = launch_kara_prep(k, stream);
   if (e != hipSuccess) return e;
+  const int np = kara_products(k.levels);
   const int nt = m.NT / 32;
   const int C_lo = g.c_lo / 32;
   const int ncol = nt - C_lo;
@@ -453,14 +484,7 @@ hipError_t launch_upd_kara(const KaraArgs& k, hipStream_t stream) {
     (void)hipEventRecord(ev0, stream);
   }
   if (e != hipSuccess) return e;
-  if (rt.n > 1) hipLaunchKernelGGL(k_kara_fix, dim3(4 * ntiles, np), dim3(256), 0, stream, k, rt, C_lo, ntiles);
-  if (L == 1)
-    hipLaunchKernelGGL(k_kara_comb<1>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
-  else if (L == 2)
-    hipLaunchKernelGGL(k_kara_comb<2>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
-  else
-    hipLaunchKernelGGL(k_kara_comb<3>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
-  e = hipGetLastError();
+  e = launch_kara_finish(k, rt, C_lo, ntiles, stream);
   if (m.timing) {
     (void)hipEventRecord(ev1, stream);
     (void)hipEventSynchronize(ev1);

@@ -290,8 +290,9 @@ void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   mfma_tile(m, R, C, rt.tb[rg], rt.tb[rg + 1], m.carry + ((size_t)lt * rt.n + rg) * 1024);
 }
 
-// Batch of updates (one entry per instance) in one persistent launch.  Work
-// items (entry, tile, range) sit in 8 queues, one per XCD, each largest first;
+// Batch of updates (one entry per instance, or per Karatsuba product of an
+// instance) in one persistent launch.  Work items (entry, tile, range) sit in 8
+// queues, one per XCD, each largest first;
 // a wave takes the next item of its XCD's queue until the queue is empty (every
 // wave reaches that exit: the queues are finite and nothing waits on another
 // wave).  heads[8] must be zero at launch.
@@ -310,7 +311,12 @@ void k_upd_mfma_b(const MfmaEntry* __restrict__ tab, const int4* __restrict__ it
     int R, C;
     item_tile(e.m.g, e.C_lo, it.y, &R, &C);
     if (R * 32 >= e.m.NT) continue;
-    mfma_tile(e.m, R, C, e.rt.tb[it.z], e.rt.tb[it.z + 1], e.m.carry + ((size_t)it.y * e.rt.n + it.z) * 1024);
+    long long* cb = e.m.carry + ((size_t)it.y * e.rt.n + it.z) * 1024;
+    if (e.store)
+      mfma_tile_t<true>(e.m.g, e.m.bdig, e.m.udig, e.m.slices, e.m.S, e.m.pad, e.m.NT, R, C, e.rt.tb[it.z],
+                        e.rt.tb[it.z + 1], cb, e.store + (size_t)it.y * tile_words(e.store_nw));
+    else
+      mfma_tile(e.m, R, C, e.rt.tb[it.z], e.rt.tb[it.z + 1], cb);
   }
 }
 
@@ -362,7 +368,7 @@ __global__ void k_carry_fix(MfmaArgs m, RangeTab rt, int C_lo) { carry_fix_body(
 // batch: blockIdx.z is the entry
 __global__ void k_carry_fix_b(const MfmaEntry* __restrict__ tab) {
   const MfmaEntry& e = tab[blockIdx.z];
-  if (e.rt.n > 1) carry_fix_body(e.m, e.rt, e.C_lo, blockIdx.x, blockIdx.y);
+  if (e.rt.n > 1 && !e.store) carry_fix_body(e.m, e.rt, e.C_lo, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------

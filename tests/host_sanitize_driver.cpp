@@ -83,12 +83,12 @@ int main() {
     EXPECT(hl_batch_plan_bytes(1, &broken, nullptr, &bytes) == HL_EINVAL);
   }
   // the batch planner under several launch shapes
-  const hl_tune_t tunes[] = {{2, 64, 0, 0}, {4, 16, 0, 0}, {8, 64, 4096, 0}, {1, 1, 1 << 20, 0}};
+  const hl_tune_t tunes[] = {{2, 64, 0, 0}, {4, 16, 0, -1}, {8, 64, 4096, 3}, {1, 1, 1 << 20, 0}, {8, 64, 0, 1}};
   for (const hl_tune_t& t : tunes) {
     bytes = 0;
     EXPECT(hl_batch_plan_bytes((int)v.size(), v.data(), &t, &bytes) == HL_OK);
-    printf("plan %zu bytes (items per SIMD %d, range cap %d, VALU below %d bits)\n", bytes, t.items_per_simd,
-           t.range_cap, t.valu_below_bits);
+    printf("plan %zu bytes (items per SIMD %d, range cap %d, VALU below %d bits, Karatsuba %d)\n", bytes,
+           t.items_per_simd, t.range_cap, t.valu_below_bits, t.karatsuba);
   }
   EXPECT(hl_batch_plan_bytes((int)v.size(), v.data(), nullptr, &bytes) == HL_OK);
   printf("%d instances, %d failures\n", (int)v.size(), fails);

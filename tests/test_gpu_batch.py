@@ -20,8 +20,10 @@ SPECS = [
     (Fraction(1), 40, 5, 1024, 7, "valu"),
     (Fraction(1, 3), 100, 8, 4096, 16, "mfma"),
     (Fraction(2, 3), 33, 3, 1536, 16, "mfma"),
-    (Fraction(1, 2), 130, 16, 8192, 16, "mfma"),
+    (Fraction(1, 2), 130, 16, 8192, 16, "mfma"),      # one Karatsuba level by default
     (Fraction(1), 17, 1, 512, 1, "valu"),
+    (Fraction(1, 3), 96, 8, 17024, 16, "mfma"),       # two levels, digits padded 2128 -> 2176
+    (Fraction(1, 2), 70, 8, 33024, 16, "mfma"),       # three levels, 4128 -> 4224
 ]
 
 
@@ -89,6 +91,28 @@ def test_autotuned_batch_gives_the_same_bits():
         assert r0[j]["lambda1"] == r1[j]["lambda1"]
     batch.close()
     tuned.close()
+
+
+def test_batch_update_forms_give_the_same_bits():
+    # the trailing updates as the digit product (karatsuba -1) and with three
+    # Karatsuba levels for every MFMA instance: the same bits as the default
+    from paper_1810_01478_amd.api import Batch
+    specs = [SPECS[j] for j in (0, 2, 4, 6, 7)]
+    mus = [_mu(b, N, P) for (b, N, k, P, E, f) in specs]
+    runs = []
+    for kk in (0, -1, 3):
+        say("batch karatsuba", kk)
+        bt = Batch(ctx(), [(mu, N, k, P, E, f) for mu, (b, N, k, P, E, f) in zip(mus, specs)],
+                   tune={"items_per_simd": 8, "range_cap": 64, "valu_below_bits": 0, "karatsuba": kk})
+        bt.launch()
+        runs.append((bt, bt.results()))
+    (b0, r0) = runs[0]
+    for bt, r in runs[1:]:
+        for j in range(len(specs)):
+            _same(bt.facs[j], b0.facs[j], specs[j][1])
+            assert r[j]["lambda1"] == r0[j]["lambda1"]
+    for bt, _r in runs:
+        bt.close()
 
 
 @pytest.mark.timeout(600)
