@@ -1,15 +1,17 @@
 """Write the oracle's records of d lambda_1 / d beta at the differentiation
-workload's sizes (N = 128, P = 16384 bits, k = 8, E = 16; beta = 9/20, 1/2,
-11/20).
+workload's sizes (N = 128 and 256, P = 16384 bits, k = 8, E = 16; beta = 9/20,
+1/2, 11/20).
 
 Calls only ``oracle/`` (``oracle.adjoint.grad``: dense mpmath inverse and
 eigen-solve of the definition) and ``hankel_inputs`` for the inputs: the
 moments and their beta-derivatives rounded to P + 64 bits, exactly what the GPU
 test passes to the library.  The oracle works at `prec` bits, far above the
-4,000-odd bits of H_128's condition number, so its lambda_1 and derivative are
-good to more than a thousand digits; the records keep 100.
+condition number of H_N (about 2^4000 at N = 128 and 2^8800 at N = 256), so its
+lambda_1 and derivative are good to more than a thousand digits; the records
+keep 100.
 
-    python tests/golden/make_adjoint_goldens.py [--prec 8192] [--N 128]
+    python tests/golden/make_adjoint_goldens.py --N 128 --prec 8192
+    python tests/golden/make_adjoint_goldens.py --N 256 --prec 20480
 """
 import argparse
 import json
