@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU comparison sample")
     ap.add_argument("--no-grad", action="store_true", help="skip the adjoint (d lambda_1 / d beta)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-instance workload")
-    ap.add_argument("--karatsuba", default="auto", choices=["auto", "0", "1", "2", "3"],
+    ap.add_argument("--karatsuba", default="auto", choices=["auto", "0", "1", "2", "3", "4"],
                     help="Schur-update form of the MFMA path: Karatsuba levels (0: the plain digit product)")
     ap.add_argument("--cpu-cols", type=int, default=4,
                     help="pivots of the oracle sample (about 5 s each on 8 cores at the default workload)")

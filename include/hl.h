@@ -160,12 +160,13 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
  * every form gives the same bits; they differ in speed only.
  *   mode  0: one int8 digit-product GEMM of the P-bit factors (S = P/8 digits);
  *         1: one Karatsuba level: the factors, as S' digits (S rounded up to a
- *            multiple of 128, zero digits on top), split at digit S'/2, three
+ *            multiple of 256, zero digits on top), split at digit S'/2, three
  *            GEMMs of (S'/2 + 1)-digit operands (3/4 of the int8 multiply-adds
  *            when S' = S), their exact sums combined per entry with exact
  *            carries;
  *         2: two levels: nine GEMMs of (S'/4 + 2)-digit operands (9/16);
  *         3: three levels: 27 GEMMs of (S'/8 + 3)-digit operands (27/64);
+ *         4: four levels: 81 GEMMs of (S'/16 + 4)-digit operands (81/256);
  *        -1 (default): 3 from P = 32768 on, 2 from 16384, 1 from 8192, else 0.
  * A mode beyond what the shape allows runs the deepest allowed one (levels
  * deeper than the default are allowed only while their products fit 16 GiB of

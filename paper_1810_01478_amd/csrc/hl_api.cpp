@@ -73,7 +73,7 @@ hl_status make_dims(const hl_shape* sh, Dims* dm) {
   dm->E = sh->exp_block;
   dm->k = sh->k;
   dm->W = 2 * sh->prec_bits - 4;
-  dm->Sk0 = (dm->S + 127) / 128 * 128;
+  dm->Sk0 = (dm->S + 255) / 256 * 256;
   // Karatsuba levels offered: every level splits the Sk0-digit strings on whole
   // slabs; beyond the default level only while the products fit kKaraExtraBytes
   dm->kara = 0;
@@ -286,7 +286,7 @@ extern "C" hl_status hl_set_timing(hl_ctx* ctx, int enable) {
 
 extern "C" hl_status hl_set_karatsuba(hl_ctx* ctx, int32_t mode) {
   if (!ctx) return fail(HL_EINVAL, "null ctx");
-  if (mode < -1 || mode > 3) return fail(HL_EINVAL, "karatsuba mode %d not in {-1, 0, 1, 2, 3}", mode);
+  if (mode < -1 || mode > KA_MAX_LEVELS) return fail(HL_EINVAL, "karatsuba mode %d not in [-1, %d]", mode, KA_MAX_LEVELS);
   ctx->karatsuba = mode;
   return HL_OK;
 }

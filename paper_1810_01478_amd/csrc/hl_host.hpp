@@ -12,12 +12,13 @@ constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 constexpr int kKaraMinPrec = 8192;   // by default one Karatsuba level of the Schur update from this precision on
 constexpr int kKara2MinPrec = 16384; // two levels from this one
 constexpr int kKara3MinPrec = 32768; // three levels from this one
+constexpr int kKara4MinPrec = 1 << 30; // four levels never by default (hl_set_karatsuba(4) asks for them)
 // levels deeper than the default for P are offered only while their products
 // fit in this many bytes (a factorisation at the default level does not carry
 // the deeper levels' buffers)
 constexpr size_t kKaraExtraBytes = (size_t)16 << 30;
 inline int kara_auto_level(int P) {
-  return P >= kKara3MinPrec ? 3 : P >= kKara2MinPrec ? 2 : P >= kKaraMinPrec ? 1 : 0;
+  return P >= kKara4MinPrec ? 4 : P >= kKara3MinPrec ? 3 : P >= kKara2MinPrec ? 2 : P >= kKaraMinPrec ? 1 : 0;
 }
 
 struct Layout {
@@ -42,8 +43,8 @@ struct Layout {
   // Karatsuba form of the Schur update: the digit panels of level l = 1 .. 3
   // (2 x 3^l panels of kara_pan_slices[l] slices, kara_pan_bytes[l] apart) and
   // the products (3^L x kara_tiles tiles for the deepest L the shape allows)
-  size_t kara_pan[4], kara_pan_bytes[4], kara_prod, kara_tiles;
-  int kara_pan_slices[4];
+  size_t kara_pan[KA_MAX_LEVELS + 1], kara_pan_bytes[KA_MAX_LEVELS + 1], kara_prod, kara_tiles;
+  int kara_pan_slices[KA_MAX_LEVELS + 1];
 };
 
 hl_status fail(hl_status s, const char* fmt, ...);

@@ -22,6 +22,9 @@ __device__ __forceinline__ bool has_error(const DevStatus* st) {
   return *((volatile const unsigned long long*)&st->code_index) != 0ull;
 }
 
+// deepest Karatsuba level of the Schur update (3^4 = 81 digit-sum products)
+constexpr int KA_MAX_LEVELS = 4;
+
 // Sizes derived from a shape.
 struct Dims {
   int N;         // order
@@ -34,8 +37,8 @@ struct Dims {
   int E;         // exponent block
   int k;
   int W;         // 2P - 4
-  int kara;      // Karatsuba levels of the Schur update available (MFMA form): 0 .. 3
-  int Sk0;       // digits of a factor in the Karatsuba form: S rounded up to a multiple of 128
+  int kara;      // Karatsuba levels of the Schur update available (MFMA form): 0 .. 4
+  int Sk0;       // digits of a factor in the Karatsuba form: S rounded up to a multiple of 256
                  // (zero digits on top), so every level splits on whole 16-digit slabs
 };
 

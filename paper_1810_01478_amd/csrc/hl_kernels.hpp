@@ -159,7 +159,6 @@ constexpr int MF_BLOCK_DIGITS = 16;
 // then one pass per entry subtracts sum_p c_p(Y) P_p, Y = 256^(S/2^L), c_p the
 // product of the levels' polynomials (1 - z), (z^2 - z), z (children lo, hi,
 // mid) at z = Y^(2^(L-l)), from the trailing matrix with exact carries.
-constexpr int KA_MAX_LEVELS = 3;
 struct KaraArgs {
   MfmaArgs m;          // target, pad, NT, carry slots (np x tiles x ranges), timing; bdig/udig unused;
                        // S here is the digit count of the split strings, a multiple of 16 x 2^L at
@@ -189,7 +188,9 @@ __host__ __device__ __forceinline__ int kara_leaf_digits(int S, int levels) { re
 __host__ __device__ __forceinline__ int kara_nwp(int S, int levels) {
   return 4 * ((2 * kara_leaf_digits(S, levels) - 1 + 15) / 16);
 }
-__host__ __device__ __forceinline__ int kara_products(int levels) { return levels == 1 ? 3 : levels == 2 ? 9 : 27; }
+__host__ __device__ __forceinline__ constexpr int kara_products(int levels) {
+  return levels <= 0 ? 1 : 3 * kara_products(levels - 1);
+}
 
 // Batched form: one entry per instance and step, work items (entry, tile index
 // of the entry's launch, range) in 8 per-XCD queues of per_xcd items (x < 0:

@@ -153,15 +153,15 @@ struct KaTerm {
 };
 template <int LV>
 struct KaPoly {
-  static constexpr int NP = LV == 1 ? 3 : (LV == 2 ? 9 : 27);
-  static constexpr int NT = LV == 1 ? 5 : (LV == 2 ? 25 : 125);
+  static constexpr int NP = kara_products(LV);
+  static constexpr int NT = LV == 1 ? 5 : (LV == 2 ? 25 : (LV == 3 ? 125 : 625));
   KaTerm t[NT];
   int first[NP + 1];
   constexpr KaPoly() : t(), first() {
     int n = 0;
     for (int p = 0; p < NP; ++p) {
       first[p] = n;
-      int pw[8] = {}, cf[8] = {}, m = 1;
+      int pw[16] = {}, cf[16] = {}, m = 1;
       pw[0] = 0;
       cf[0] = 1;
       int div = NP / 3;
@@ -169,7 +169,7 @@ struct KaPoly {
         const int c = (p / div) % 3;
         div = div / 3;
         const int z = 1 << (LV - l);
-        int pw2[8] = {}, cf2[8] = {}, m2 = 0;
+        int pw2[16] = {}, cf2[16] = {}, m2 = 0;
         for (int a = 0; a < m; ++a) {
           if (c == 0) {
             pw2[m2] = pw[a]; cf2[m2++] = cf[a];
@@ -375,13 +375,14 @@ void k_kara_comb(KaraArgs k, int C_lo) {
 #pragma unroll
     for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy[m]);
   } else {
-    i64 cy0[8], cy1[NSEG - 8];
-    ka_pass<LV, 0, 8>(At, P0, voff, pst, O, nq, cy0);
-    ka_pass<LV, 8, NSEG>(At, P0, voff, pst, O, nq, cy1);
+    // 32 segments (four levels): two passes of 16
+    i64 cy0[16], cy1[NSEG - 16];
+    ka_pass<LV, 0, 16>(At, P0, voff, pst, O, nq, cy0);
+    ka_pass<LV, 16, NSEG>(At, P0, voff, pst, O, nq, cy1);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy0[m]);
+    for (int m = 0; m < 16; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy0[m]);
 #pragma unroll
-    for (int m = 0; m + 1 < NSEG - 8; ++m) add_at_limb(At, r, c, 4 * (m + 9) * O, g.nw, cy1[m]);
+    for (int m = 0; m + 1 < NSEG - 16; ++m) add_at_limb(At, r, c, 4 * (m + 17) * O, g.nw, cy1[m]);
   }
 }
 
@@ -444,8 +445,10 @@ hipError_t launch_kara_finish(const KaraArgs& k, const RangeTab& rt, int C_lo, i
     hipLaunchKernelGGL(k_kara_comb<1>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
   else if (L == 2)
     hipLaunchKernelGGL(k_kara_comb<2>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
-  else
+  else if (L == 3)
     hipLaunchKernelGGL(k_kara_comb<3>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+  else
+    hipLaunchKernelGGL(k_kara_comb<4>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
   return hipGetLastError();
 }
 

@@ -173,11 +173,11 @@ def test_mfma_equals_valu_bitwise_c2b_shape():
     (Fraction(1, 2), 80, 1024, 7),    # ragged last tile
     (Fraction(1, 3), 45, 1536, 1),
     (Fraction(1, 2), 100, 4096, 16),
-    (Fraction(1, 3), 20, 256, 1),     # 32 digits split as 128 (zero digits on top)
+    (Fraction(1, 3), 20, 256, 1),     # 32 digits split as 256 (zero digits on top)
     (1, 97, 3072, 4),
-    (Fraction(1, 3), 128, 19072, 16),  # a batched-workload precision: 2384 digits split as 2432
+    (Fraction(1, 3), 128, 19072, 16),  # a batched-workload precision: 2384 digits split as 2560
 ])
-@pytest.mark.parametrize("levels", [1, 2, 3])
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
 def test_factor_karatsuba_bit_exact_vs_oracle(beta, N, P, E, levels):
     # the Karatsuba forms of the trailing update are exact: same bits as the
     # oracle at every level and precision (the split digit strings are the
@@ -209,7 +209,7 @@ def test_karatsuba_equals_digit_product_c2b_shape():
         c.set_karatsuba(0)
         fa = c.factor(mu, N, 8, P, 16, "mfma")
         c.sync(fa)
-        for lv in (1, 2, 3):
+        for lv in (1, 2, 3, 4):
             c.set_karatsuba(lv)
             fb = c.factor(mu, N, 8, P, 16, "mfma")
             c.sync(fb)
@@ -229,7 +229,7 @@ def test_karatsuba_equals_digit_product_c2b_shape():
 @pytest.mark.parametrize("N,P", [(200, 8320), (160, 10368)])
 def test_karatsuba_padded_digits_equal_digit_product(N, P):
     # P not a multiple of 1024: the split strings carry zero digits above the
-    # factors' (1040 -> 1152, 1296 -> 1408 digits); every level gives the digit
+    # factors' (1040 -> 1280, 1296 -> 1536 digits); every level gives the digit
     # product's bits
     import torch
     say("karatsuba padded digits", N, P)
@@ -239,7 +239,7 @@ def test_karatsuba_padded_digits_equal_digit_product(N, P):
         c.set_karatsuba(0)
         fa = c.factor(mu, N, 8, P, 16, "mfma")
         c.sync(fa)
-        for lv in (1, 2, 3):
+        for lv in (1, 2, 3, 4):
             c.set_karatsuba(lv)
             fb = c.factor(mu, N, 8, P, 16, "mfma")
             c.sync(fb)
@@ -251,7 +251,7 @@ def test_karatsuba_padded_digits_equal_digit_product(N, P):
 def test_set_karatsuba_rejects_bad_mode():
     from paper_1810_01478_amd._lib import HLError, HL_EINVAL
     with pytest.raises(HLError) as e:
-        ctx().set_karatsuba(4)
+        ctx().set_karatsuba(5)
     assert e.value.code == HL_EINVAL
 
 
