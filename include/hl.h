@@ -167,7 +167,8 @@ hl_status hl_factor_cols(hl_ctx *ctx, const hl_shape *sh, const uint32_t *mu, co
  *         2: two levels: nine GEMMs of (S'/4 + 2)-digit operands (9/16);
  *         3: three levels: 27 GEMMs of (S'/8 + 3)-digit operands (27/64);
  *         4: four levels: 81 GEMMs of (S'/16 + 4)-digit operands (81/256);
- *        -1 (default): 3 from P = 32768 on, 2 from 16384, 1 from 8192, else 0.
+ *        -1 (default): 4 from P = 40960 on, 3 from 32768, 2 from 16384, 1 from
+ *            8192, else 0.
  * A mode beyond what the shape allows runs the deepest allowed one (levels
  * deeper than the default are allowed only while their products fit 16 GiB of
  * workspace).  Applies to later

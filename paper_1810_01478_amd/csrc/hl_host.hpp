@@ -12,7 +12,7 @@ constexpr int kBlockRows = 16;    // rows per partial sum of the H^-1 block
 constexpr int kKaraMinPrec = 8192;   // by default one Karatsuba level of the Schur update from this precision on
 constexpr int kKara2MinPrec = 16384; // two levels from this one
 constexpr int kKara3MinPrec = 32768; // three levels from this one
-constexpr int kKara4MinPrec = 1 << 30; // four levels never by default (hl_set_karatsuba(4) asks for them)
+constexpr int kKara4MinPrec = 40960; // four levels from this one (between 32768 and 49152 bits)
 // levels deeper than the default for P are offered only while their products
 // fit in this many bytes (a factorisation at the default level does not carry
 // the deeper levels' buffers)

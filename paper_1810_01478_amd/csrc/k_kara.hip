@@ -239,28 +239,37 @@ __global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C
   for (int w = 0; w + 1 < rt.n; ++w) add_at_limb(Q, r, c, MF_LPB * rt.tb[w + 1], k.nwp, cb[(size_t)w * 1024]);
 }
 
-// a -= sum_p c_p(Y) P_p for every live entry of the launch, one thread per
-// entry.  Y is O slabs, the entry 2^(L+1) segments of O slabs, every product
-// 2 O + 1 slabs with a signed top slab.  Output slab m O + jj takes, from term
-// (p, pw), product slab (m - pw) O + jj: slab jj for m = pw, O + jj for m = pw + 1,
-// and the top slab 2 O at jj = 0 for m = pw + 2.  So the thread walks jj, holds
+// a -= sum_p c_p(Y) P_p for every live entry of the launch, two lanes per
+// entry: lane half h (lane & 1) holds limbs 2h, 2h + 1 of every slab.  Y is O
+// slabs, the entry 2^(L+1) segments of O slabs, every product 2 O + 1 slabs
+// with a signed top slab.  Output slab m O + jj takes, from term (p, pw),
+// product slab (m - pw) O + jj: slab jj for m = pw, O + jj for m = pw + 1, and
+// the top slab 2 O at jj = 0 for m = pw + 2.  So the lane pair walks jj, holds
 // slab jj of every segment in registers, streams the two slabs jj and O + jj of
-// every product through once, and stores the segments, each with its own
-// running carry; at the end the carry out of segment m enters at its
-// successor's first slab.
-__device__ __forceinline__ void ka_apply(i64* s, const uint4& v, int sg, bool top) {
-  const i64 v3 = top ? (i64)(int)v.w : (i64)v.w;
+// every product through once (each lane its 8 bytes), and stores the segments,
+// each with its own running carry; at the end the carry out of segment m
+// enters at its successor's first slab.
+__device__ __forceinline__ void ka_apply(i64* s, const uint2& v, int sg, bool top_hi) {
+  // top_hi: this lane holds limbs 2, 3 of the top slab, whose limb 3 is signed
+  const i64 v1 = top_hi ? (i64)(int)v.y : (i64)v.y;
   if (sg > 0) {
-    s[0] += v.x; s[1] += v.y; s[2] += v.z; s[3] += v3;
+    s[0] += v.x; s[1] += v1;
   } else {
-    s[0] -= v.x; s[1] -= v.y; s[2] -= v.z; s[3] -= v3;
+    s[0] -= v.x; s[1] -= v1;
   }
 }
 
-// 16 bytes at the wave-uniform base plus the lane's byte offset (keeps the
-// many product and segment bases in scalar registers)
-__device__ __forceinline__ uint4 ld_lane(const u32* base, u32 voff) {
-  return *(const uint4*)((const char*)base + voff);
+// 8 bytes at the wave-uniform base plus the lane's byte offset (keeps the many
+// product and segment bases in scalar registers)
+__device__ __forceinline__ uint2 ld_lane(const u32* base, u32 voff) {
+  return *(const uint2*)((const char*)base + voff);
+}
+
+// the partner lane's value (lanes 2i and 2i + 1 swap)
+__device__ __forceinline__ i64 partner64(i64 v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(u32)v, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u32)((u64)v >> 32), 0xB1, 0xF, 0xF, false);
+  return (i64)(((u64)(u32)hi << 32) | (u32)lo);
 }
 
 // does product p have a term reaching segments [M0, M1)?
@@ -278,8 +287,8 @@ constexpr bool ka_needed(int p, int M0, int M1) {
 // (the fence keeps the compiler from hoisting later groups' loads into the
 // registers the accumulators need).
 template <int LV, int M0, int M1, int TI>
-__device__ __forceinline__ void ka_term(i64 (&s)[M1 - M0][4], const u32* P0, u32& voff, size_t pst, int O, int jj,
-                                        uint4& lo, uint4& hi, uint4& top) {
+__device__ __forceinline__ void ka_term(i64 (&s)[M1 - M0][2], const u32* P0, u32& voff, size_t pst, int O, int jj,
+                                        bool hi_half, uint2& lo, uint2& hi, uint2& top) {
   constexpr KaTerm TT = KaPoly<LV>().t[TI];
   if constexpr (ka_needed<LV>(TT.p, M0, M1)) {
     if constexpr (TI == KaPoly<LV>().first[TT.p]) {
@@ -289,7 +298,7 @@ __device__ __forceinline__ void ka_term(i64 (&s)[M1 - M0][4], const u32* P0, u32
       if constexpr (TT.p % 3 == 0 && TT.p > 0) {
         u32 dep = 0;
 #pragma unroll
-        for (int m = 0; m < M1 - M0; ++m) dep ^= (u32)s[m][0] ^ (u32)s[m][1] ^ (u32)s[m][2] ^ (u32)s[m][3];
+        for (int m = 0; m < M1 - M0; ++m) dep ^= (u32)s[m][0] ^ (u32)s[m][1];
         asm volatile("" : "+v"(voff) : "v"(dep));
       }
       const u32* Qp = P0 + (size_t)TT.p * pst;
@@ -300,7 +309,7 @@ __device__ __forceinline__ void ka_term(i64 (&s)[M1 - M0][4], const u32* P0, u32
     if constexpr (TT.pw >= M0 && TT.pw < M1) ka_apply(s[TT.pw - M0], lo, TT.sg, false);
     if constexpr (TT.pw + 1 >= M0 && TT.pw + 1 < M1) ka_apply(s[TT.pw + 1 - M0], hi, TT.sg, false);
     if constexpr (TT.pw + 2 >= M0 && TT.pw + 2 < M1) {
-      if (jj == 0) ka_apply(s[TT.pw + 2 - M0], top, TT.sg, true);
+      if (jj == 0) ka_apply(s[TT.pw + 2 - M0], top, TT.sg, hi_half);
     }
   }
 }
@@ -308,81 +317,78 @@ __device__ __forceinline__ void ka_term(i64 (&s)[M1 - M0][4], const u32* P0, u32
 // every term, each a separate inlined call (no recursion, so the accumulators
 // stay in registers)
 template <int LV, int M0, int M1, int... TI>
-__device__ __forceinline__ void ka_terms(std::integer_sequence<int, TI...>, i64 (&s)[M1 - M0][4], const u32* P0,
-                                         u32& voff, size_t pst, int O, int jj) {
-  uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo, top = lo;
-  (ka_term<LV, M0, M1, TI>(s, P0, voff, pst, O, jj, lo, hi, top), ...);
+__device__ __forceinline__ void ka_terms(std::integer_sequence<int, TI...>, i64 (&s)[M1 - M0][2], const u32* P0,
+                                         u32& voff, size_t pst, int O, int jj, bool hi_half) {
+  uint2 lo = make_uint2(0u, 0u), hi = lo, top = lo;
+  (ka_term<LV, M0, M1, TI>(s, P0, voff, pst, O, jj, hi_half, lo, hi, top), ...);
 }
 
-// segments [M0, M1) of the entry: slab jj of each in registers, the products
-// reaching them streamed through once per jj; cy[m - M0] is the carry out of
-// segment m
-// Slabs at or above nq (the entry's nw / 4; there are some when the split
-// strings carry zero digits above the factors') are neither read nor written:
-// they only receive carries, and the entry keeps its value modulo 2^(32 nw).
+// segments [M0, M1) of the entry: this lane's half of slab jj of each in
+// registers, the products reaching them streamed through once per jj; cy[m - M0]
+// (valid in the low-half lane) is the carry out of segment m.  Slabs at or above
+// nq (the entry's nw / 4; there are some when the split strings carry zero
+// digits above the factors') are neither read nor written: they only receive
+// carries, and the entry keeps its value modulo 2^(32 nw).
 template <int LV, int M0, int M1>
-__device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_t pst, int O, int nq,
+__device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_t pst, int O, int nq, bool hi_half,
                                         i64 (&cy)[M1 - M0]) {
   constexpr int NS = M1 - M0;
 #pragma unroll
   for (int m = 0; m < NS; ++m) cy[m] = 0;
   for (int jj = 0; jj < O; ++jj) {
     u32 voff = voff0;
-    i64 s[NS][4];
+    i64 s[NS][2];
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-      uint4 a = make_uint4(0u, 0u, 0u, 0u);
+      uint2 a = make_uint2(0u, 0u);
       if ((M0 + m) * O + jj < nq) a = ld_lane(At + (size_t)((M0 + m) * O + jj) * 4096, voff);
-      s[m][0] = a.x; s[m][1] = a.y; s[m][2] = a.z; s[m][3] = a.w;
+      s[m][0] = a.x; s[m][1] = a.y;
     }
-    ka_terms<LV, M0, M1>(std::make_integer_sequence<int, KaPoly<LV>::NT>{}, s, P0, voff, pst, O, jj);
+    ka_terms<LV, M0, M1>(std::make_integer_sequence<int, KaPoly<LV>::NT>{}, s, P0, voff, pst, O, jj, hi_half);
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
-      i64 s0 = s[m][0] + cy[m], s1 = s[m][1], s2 = s[m][2], s3 = s[m][3];
-      s1 += s0 >> 32;
-      s2 += s1 >> 32;
-      s3 += s2 >> 32;
-      cy[m] = s3 >> 32;
+      // limbs 0, 1 with the segment's running carry (low-half lane), their
+      // carry into limb 2 to the partner, limbs 2, 3 with it (high-half lane),
+      // and the carry out of limb 3 back to the low-half lane
+      const i64 a0 = s[m][0] + (hi_half ? 0 : cy[m]);
+      const i64 a1 = s[m][1] + (a0 >> 32);
+      const i64 cmid = partner64(a1 >> 32);
+      const i64 b0 = s[m][0] + cmid;
+      const i64 b1 = s[m][1] + (b0 >> 32);
+      const i64 x0 = hi_half ? b0 : a0, x1 = hi_half ? b1 : a1;
+      cy[m] = partner64(b1 >> 32);
       if ((M0 + m) * O + jj < nq)
-        *(uint4*)((char*)(At + (size_t)((M0 + m) * O + jj) * 4096) + voff) =
-            make_uint4((u32)s0, (u32)s1, (u32)s2, (u32)s3);
+        *(uint2*)((char*)(At + (size_t)((M0 + m) * O + jj) * 4096) + voff) = make_uint2((u32)x0, (u32)x1);
     }
   }
 }
 
-// a -= sum_p c_p(Y) P_p for every live entry of the launch, one thread per
-// entry (see ka_pass), in passes of at most eight segments; then the carry out
-// of every segment enters at its successor's first slab (the last one leaves
-// the entry).
+// a -= sum_p c_p(Y) P_p for every live entry of the launch, two lanes per
+// entry (see ka_pass), in one pass over the 2^(L+1) segments; then the carry
+// out of every segment enters at its successor's first slab (the last one
+// leaves the entry).
 template <int LV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LV == 1 ? 4 : 2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LV <= 2 ? 4 : 2)))
 void k_kara_comb(KaraArgs k, int C_lo) {
   constexpr int NSEG = 2 << LV;
   const UpdArgs& g = k.m.g;
-  const int lt = blockIdx.x >> 2, e = (blockIdx.x & 3) * 256 + threadIdx.x;
+  const int lt = blockIdx.x >> 3, e = (blockIdx.x & 7) * 128 + (threadIdx.x >> 1);
+  const bool hi_half = (threadIdx.x & 1) != 0;
   int R, C;
+  // both lanes of a pair see the same entry, so they leave together
   if (!kara_entry(k, C_lo, lt, e, &R, &C) || has_error(g.st)) return;
   const int r = e >> 5, c = e & 31;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   const size_t tw = tile_words(k.nwp), pst = k.prod_tiles * tw;
   u32* At = g.A + tix * tile_words(g.nw);   // wave-uniform bases, the lane's offset apart
   const u32* P0 = k.prod + (size_t)lt * tw;
-  const u32 voff = (u32)in_tile(r, c, 0) * 4;
+  const u32 voff = (u32)in_tile(r, c, 0) * 4 + (hi_half ? 8u : 0u);
   const int O = k.m.S / (16 << LV), nq = g.nw / 4;
-  if constexpr (NSEG <= 16) {
-    i64 cy[NSEG];
-    ka_pass<LV, 0, NSEG>(At, P0, voff, pst, O, nq, cy);
+  i64 cy[NSEG];
+  ka_pass<LV, 0, NSEG>(At, P0, voff, pst, O, nq, hi_half, cy);
+  if (!hi_half) {
 #pragma unroll
     for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy[m]);
-  } else {
-    // 32 segments (four levels): two passes of 16
-    i64 cy0[16], cy1[NSEG - 16];
-    ka_pass<LV, 0, 16>(At, P0, voff, pst, O, nq, cy0);
-    ka_pass<LV, 16, NSEG>(At, P0, voff, pst, O, nq, cy1);
-#pragma unroll
-    for (int m = 0; m < 16; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy0[m]);
-#pragma unroll
-    for (int m = 0; m + 1 < NSEG - 16; ++m) add_at_limb(At, r, c, 4 * (m + 17) * O, g.nw, cy1[m]);
   }
 }
 
@@ -441,14 +447,15 @@ hipError_t launch_kara_finish(const KaraArgs& k, const RangeTab& rt, int C_lo, i
   if (ntiles <= 0) return hipSuccess;
   const int L = k.levels, np = kara_products(L);
   if (rt.n > 1) hipLaunchKernelGGL(k_kara_fix, dim3(4 * ntiles, np), dim3(256), 0, stream, k, rt, C_lo, ntiles);
+  // two lanes per entry: 8 blocks of 256 threads per tile
   if (L == 1)
-    hipLaunchKernelGGL(k_kara_comb<1>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+    hipLaunchKernelGGL(k_kara_comb<1>, dim3(8 * ntiles), dim3(256), 0, stream, k, C_lo);
   else if (L == 2)
-    hipLaunchKernelGGL(k_kara_comb<2>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+    hipLaunchKernelGGL(k_kara_comb<2>, dim3(8 * ntiles), dim3(256), 0, stream, k, C_lo);
   else if (L == 3)
-    hipLaunchKernelGGL(k_kara_comb<3>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+    hipLaunchKernelGGL(k_kara_comb<3>, dim3(8 * ntiles), dim3(256), 0, stream, k, C_lo);
   else
-    hipLaunchKernelGGL(k_kara_comb<4>, dim3(4 * ntiles), dim3(256), 0, stream, k, C_lo);
+    hipLaunchKernelGGL(k_kara_comb<4>, dim3(8 * ntiles), dim3(256), 0, stream, k, C_lo);
   return hipGetLastError();
 }
 
