@@ -127,12 +127,14 @@ __device__ __forceinline__ int opaque_i32(int v) {
 // last partial rotation whose steps are skipped past the block's end (no
 // padding steps); the next block's operands are requested before this block's
 // sums are folded, so their latency hides behind the fold.
+constexpr int MF_FOLD = 4;  // entries folded together
+
 template <bool STORE>
 __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig, const int8_t* udig, int slices,
                                             int S, int pad, int NT, int R, int C, int tb0, int tb1, long long* cb,
-                                            u32* Out) {
+                                            u32* Out, int out_nw) {
   if (has_error(g.st)) return;
-  __shared__ i64 carry_s[16 * WAVE];  // carry of each of the lane's 16 entries
+  __shared__ int carry_s[16 * WAVE];  // carry of each of the lane's 16 entries (|carry| < 2^25)
   const int l = lane_id(), h = l >> 5, mm = l & 31;
   const int sst = NT * 16;  // bytes per digit slice
   // A operand (b digits of tile rows), B operand (u digits of tile columns),
@@ -143,6 +145,12 @@ __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig
       __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(bdig), 0, slices * sst, kRawBufferWord3);
   const __amdgpu_buffer_rsrc_t ru =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<int8_t*>(udig), 0, slices * sst, kRawBufferWord3);
+  // the output tile: entry (r, c) of slab tb at byte 16 (1024 tb + 32 r + c);
+  // the lane's part of that offset in a register, the slab's and the
+  // accumulator register's in a scalar one
+  const __amdgpu_buffer_rsrc_t ro =
+      __builtin_amdgcn_make_buffer_rsrc(Out, 0, (int)(tile_words(out_nw) * 4), kRawBufferWord3);
+  const int ooff = (4 * h * 32 + mm) * 16;
   const int aoff = h * sst + R * 512 + mm * 16;
   const int uoff = (1 - h) * sst + C * 512 + mm * 16;
   unsigned live = 0;  // entries of the trailing matrix proper (r >= c, inside the target)
@@ -214,52 +222,74 @@ __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig
     // the next block's first operands, in flight during the fold
     if (tb + 1 < tb1) MF_PROLOGUE(tb + 1);
     // fold the 16 digit sums of each entry into limbs 4 tb .. 4 tb + 3 (one
-    // slab): V = sum_k d_k 2^(32 k) + carry, d_k = sum_m out_(t0+4k+m) 2^(8 m),
-    // resolved 32 bits at a time (|d_k| < 2^53, so every partial sum is exact
-    // in 64 bits); the limbs are V mod 2^128 (or the old limbs minus the sums
-    // plus the carry), the carry V >> 128
+    // slab): V = sum_k d_k 2^(32 k) + carry, d_k = sum_m out_(t0+4k+m) 2^(8 m)
+    // (|d_k| < 2^56, exact in 64 bits), resolved 32 bits at a time: t_0 = d_0 +
+    // carry, t_k = d_k + (t_(k-1) >> 32); the limbs are the low halves of t_k
+    // (or of the old limbs minus d_k plus the carry), the carry t_3 >> 32.
+    // Every step is one 32 x 32 -> 64-bit signed multiply-add (the multipliers
+    // are opaque, the carry enters with multiplier 1).  A product tile (STORE)
+    // is written whole, dead entries included: nothing reads them.
     const int m8 = opaque_i32(1 << 8), m16 = opaque_i32(1 << 16), m24 = opaque_i32(1 << 24);
+    const int one = opaque_i32(1);
+    const int soff_tb = tb * (MF_LPB * 4096);
+    // four entries at a time, so that their independent chains interleave
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      if (!((live >> v) & 1u)) continue;
-      const int r = mf_row(l, v), c = mf_col(l);
-      uint4* p = (uint4*)(Out + in_tile(r, c, MF_LPB * tb));
-      i64 d[4];
+    for (int v0 = 0; v0 < 16; v0 += MF_FOLD) {
+      i64 t[MF_FOLD][4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        i64 x = (i64)acc_elem(acc[4 * k][v]);
-        x = mad_digit(acc_elem(acc[4 * k + 1][v]), m8, x);
-        x = mad_digit(acc_elem(acc[4 * k + 2][v]), m16, x);
-        d[k] = mad_digit(acc_elem(acc[4 * k + 3][v]), m24, x);
-      }
-      i64 cy = carry_s[v * WAVE + l];
-      u32 o[4];
-      if (STORE) {
+      for (int e = 0; e < MF_FOLD; ++e) {
+        const int v = v0 + e;
+        if (STORE) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const i64 t = d[k] + cy;
-          o[k] = (u32)t;
-          cy = t >> 32;
+          for (int k = 0; k < 4; ++k) {
+            i64 x = (i64)acc_elem(acc[4 * k][v]);
+            x = mad_digit(acc_elem(acc[4 * k + 1][v]), m8, x);
+            x = mad_digit(acc_elem(acc[4 * k + 2][v]), m16, x);
+            t[e][k] = mad_digit(acc_elem(acc[4 * k + 3][v]), m24, x);
+          }
+        } else {
+          if (!((live >> v) & 1u)) continue;
+          const int soff = soff_tb + (8 * (v >> 2) + (v & 3)) * 512;
+          const v4i x = __builtin_amdgcn_raw_buffer_load_b128(ro, ooff, soff, 0);
+          const int n1 = opaque_i32(-1), n8 = opaque_i32(-(1 << 8)), n16 = opaque_i32(-(1 << 16)),
+                    n24 = opaque_i32(-(1 << 24));
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            i64 y = (i64)(u32)x[k];
+            y = mad_digit(acc_elem(acc[4 * k][v]), n1, y);
+            y = mad_digit(acc_elem(acc[4 * k + 1][v]), n8, y);
+            y = mad_digit(acc_elem(acc[4 * k + 2][v]), n16, y);
+            t[e][k] = mad_digit(acc_elem(acc[4 * k + 3][v]), n24, y);
+          }
         }
-      } else {
-        const uint4 x = *p;
-        const u32 xa[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const i64 t = (i64)xa[k] - d[k] + cy;
-          o[k] = (u32)t;
-          cy = t >> 32;
-        }
       }
-      *p = make_uint4(o[0], o[1], o[2], o[3]);
-      carry_s[v * WAVE + l] = cy;
+#pragma unroll
+      for (int e = 0; e < MF_FOLD; ++e) {
+        const int v = v0 + e;
+        if (!STORE && !((live >> v) & 1u)) continue;
+        t[e][0] = mad_digit(carry_s[v * WAVE + l], one, t[e][0]);
+      }
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+#pragma unroll
+        for (int e = 0; e < MF_FOLD; ++e) t[e][k] = mad_digit((int)(t[e][k - 1] >> 32), one, t[e][k]);
+      }
+#pragma unroll
+      for (int e = 0; e < MF_FOLD; ++e) {
+        const int v = v0 + e;
+        if (!STORE && !((live >> v) & 1u)) continue;
+        const int soff = soff_tb + (8 * (v >> 2) + (v & 3)) * 512;
+        const v4i o = {(int)(u32)t[e][0], (int)(u32)t[e][1], (int)(u32)t[e][2], (int)(u32)t[e][3]};
+        __builtin_amdgcn_raw_buffer_store_b128(o, ro, ooff, soff, 0);
+        carry_s[v * WAVE + l] = (int)(t[e][3] >> 32);
+      }
     }
   }
 #undef MF_STEP
 #undef MF_PROLOGUE
   // carries out of this range
 #pragma unroll
-  for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = carry_s[v * WAVE + l];
+  for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = (long long)carry_s[v * WAVE + l];
 }
 
 // the Schur update of tile (R, C) of the trailing matrix (see mfma_tile_t)
@@ -267,7 +297,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& m, int R, int C, int t
   const UpdArgs& g = m.g;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
   mfma_tile_t<false>(g, m.bdig, m.udig, m.slices, m.S, m.pad, m.NT, R, C, tb0, tb1, cb,
-                     g.A + tix * tile_words(g.nw));
+                     g.A + tix * tile_words(g.nw), g.nw);
 }
 
 // ---------------------------------------------------------------------------
@@ -314,7 +344,7 @@ void k_upd_mfma_b(const MfmaEntry* __restrict__ tab, const int4* __restrict__ it
     long long* cb = e.m.carry + ((size_t)it.y * e.rt.n + it.z) * 1024;
     if (e.store)
       mfma_tile_t<true>(e.m.g, e.m.bdig, e.m.udig, e.m.slices, e.m.S, e.m.pad, e.m.NT, R, C, e.rt.tb[it.z],
-                        e.rt.tb[it.z + 1], cb, e.store + (size_t)it.y * tile_words(e.store_nw));
+                        e.rt.tb[it.z + 1], cb, e.store + (size_t)it.y * tile_words(e.store_nw), e.store_nw);
     else
       mfma_tile(e.m, R, C, e.rt.tb[it.z], e.rt.tb[it.z + 1], cb);
   }
@@ -393,7 +423,7 @@ void k_upd_kara(KaraArgs k, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   mfma_tile_t<true>(g, leaf + (size_t)p * ls, leaf + (size_t)(np + p) * ls, k.kslices,
                     k.Sk, k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
                     k.m.carry + (((size_t)p * ntiles + lt) * rt.n + rg) * 1024,
-                    k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp));
+                    k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp), k.nwp);
 }
 
 // ---------------------------------------------------------------------------
