@@ -10,13 +10,15 @@ namespace hl {
 
 // Digits of the halves: limb q of a factor holds its balanced digits 4q..4q+3;
 // those below h = 4 hq go to the lo panel, the others to the hi panel at digit
-// 4q - h.  One thread per (limb, row, panel column), as recode_body.
+// 4q - h.  One thread per (limb, row, panel column), as recode_body, for rows
+// r0 .. NT - 1 (the GEMMs of a launch read no row below its first tile row).
 __global__ void k_recode_kara(const u32* __restrict__ src, size_t lds, int npan, int NT, int nrows, int nl, int pad,
-                              int hq, int8_t* __restrict__ lo, int8_t* __restrict__ hi) {
+                              int hq, int8_t* __restrict__ lo, int8_t* __restrict__ hi, int r0) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int il = (int)(gid & 15);
   const size_t t = gid >> 4;
-  const int row = (int)(t % NT), q = (int)(t / NT);
+  const int nr = NT - r0;
+  const int row = r0 + (int)(t % nr), q = (int)(t / nr);
   if (q >= nl) return;
   const size_t rstride = (size_t)NT * 16;
   const int qq = q < hq ? q : q - hq;
@@ -59,9 +61,10 @@ __device__ __forceinline__ int sig_byte(const uint4& a, const uint4& b, int col)
 }
 
 __device__ __forceinline__ void kara_mid_body(const int8_t* __restrict__ lo, const int8_t* __restrict__ hi, int NT,
-                                              int pad, int h, int8_t* __restrict__ mid) {
+                                              int pad, int h, int8_t* __restrict__ mid, int r0) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = (int)(gid % NT), g = (int)(gid / NT);
+  const int nr = NT - r0;
+  const int row = r0 + (int)(gid % nr), g = (int)(gid / nr);
   if (g > h / 4) return;
   const size_t rs = (size_t)NT * 16, off = (size_t)row * 16;
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
@@ -112,27 +115,29 @@ __device__ __forceinline__ void kara_mid_body(const int8_t* __restrict__ lo, con
 }
 
 __global__ void k_kara_mid(const int8_t* __restrict__ lo, const int8_t* __restrict__ hi, int NT, int pad, int h,
-                           int8_t* __restrict__ mid) {
-  kara_mid_body(lo, hi, NT, pad, h, mid);
+                           int8_t* __restrict__ mid, int r0) {
+  kara_mid_body(lo, hi, NT, pad, h, mid, r0);
 }
 
 // the mid children of every level-(l-1) panel (blockIdx.y, both sides): lo and
 // hi child of n = S/2^(l-1) + extra digits, the hi child n - S/2^l of them
-__global__ void k_kara_mid_lv(KaraArgs k, int l) {
+__global__ void k_kara_mid_lv(KaraArgs k, int l, int r0) {
   const int nq = kara_products(l - 1), y = blockIdx.y, side = y / nq, q = y - side * nq;
   const int s = k.m.S >> l;
   int8_t* lo = k.pan[l] + (size_t)(side * 3 * nq + 3 * q) * k.pan_stride[l];
-  kara_mid_body(lo, lo + k.pan_stride[l], k.m.NT, k.m.pad, s + kara_extra(q, l - 1), lo + 2 * k.pan_stride[l]);
+  kara_mid_body(lo, lo + k.pan_stride[l], k.m.NT, k.m.pad, s + kara_extra(q, l - 1), lo + 2 * k.pan_stride[l], r0);
 }
 
 // Level l - 1 to level l: every panel q (blockIdx.y, both sides) has
 // n = S/2^(l-1) + extra digits; slices [0, s) go to its lo child, [s, n) to its hi
-// child (digit j - s), s = S/2^l.  One thread per 16 bytes of a slice.
-__global__ void k_digit_split(KaraArgs k, int l) {
+// child (digit j - s), s = S/2^l.  One thread per 16 bytes of a slice row
+// r0 .. NT - 1.
+__global__ void k_digit_split(KaraArgs k, int l, int r0) {
   const int nq = kara_products(l - 1), y = blockIdx.y, side = y / nq, q = y - side * nq;
   const int s = k.m.S >> l, n = 2 * s + kara_extra(q, l - 1), NT = k.m.NT, pad = k.m.pad;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = (int)(gid / NT), row = (int)(gid % NT);
+  const int nr = NT - r0;
+  const int j = (int)(gid / nr), row = r0 + (int)(gid % nr);
   if (j >= n) return;
   const size_t rs = (size_t)NT * 16;
   const int8_t* src = k.pan[l - 1] + (size_t)y * k.pan_stride[l - 1];
@@ -416,27 +421,31 @@ hipError_t launch_kara_prep(const KaraArgs& k, hipStream_t stream) {
   if (g.r_hi <= g.r_lo || g.c_hi <= g.c_lo || g.npan <= 0) return hipSuccess;
   if (!kara_ok(k)) return hipErrorInvalidValue;
   const int L = k.levels, h = m.S / 2;
-  const size_t rthreads = (size_t)g.nl * m.NT * 16;
+  // rows below the launch's first tile row are read by none of its GEMMs
+  const int r0 = (g.c_lo / 32) * 32, nr = m.NT - r0;
+  const size_t rthreads = (size_t)g.nl * nr * 16;
   const unsigned rblocks = (unsigned)((rthreads + 255) / 256);
   int8_t* l1[6];
   for (int q = 0; q < 6; ++q) l1[q] = k.pan[1] + (size_t)q * k.pan_stride[1];
   hipLaunchKernelGGL(k_recode_kara, dim3(rblocks), dim3(256), 0, stream, g.Bop, g.ldb, g.npan, m.NT, m.NT, g.nl,
-                     m.pad, h / 4, l1[0], l1[1]);
+                     m.pad, h / 4, l1[0], l1[1], r0);
   hipLaunchKernelGGL(k_recode_kara, dim3(rblocks), dim3(256), 0, stream, g.Uop, g.ldu, g.npan, m.NT, m.u_rows,
-                     g.nl, m.pad, h / 4, l1[3], l1[4]);
+                     g.nl, m.pad, h / 4, l1[3], l1[4], r0);
   {
-    const size_t threads = (size_t)(h / 4 + 1) * m.NT;
+    const size_t threads = (size_t)(h / 4 + 1) * nr;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
-    hipLaunchKernelGGL(k_kara_mid, dim3(blocks), dim3(256), 0, stream, l1[0], l1[1], m.NT, m.pad, h, l1[2]);
-    hipLaunchKernelGGL(k_kara_mid, dim3(blocks), dim3(256), 0, stream, l1[3], l1[4], m.NT, m.pad, h, l1[5]);
+    hipLaunchKernelGGL(k_kara_mid, dim3(blocks), dim3(256), 0, stream, l1[0], l1[1], m.NT, m.pad, h, l1[2], r0);
+    hipLaunchKernelGGL(k_kara_mid, dim3(blocks), dim3(256), 0, stream, l1[3], l1[4], m.NT, m.pad, h, l1[5], r0);
   }
   for (int l = 2; l <= L; ++l) {
     // every level-(l-1) panel (at most S/2^(l-1) + l - 1 digits) splits at S/2^l
     const int nmax = (m.S >> (l - 1)) + l - 1, s = m.S >> l, parents = 2 * kara_products(l - 1);
-    const size_t threads = (size_t)nmax * m.NT;
-    hipLaunchKernelGGL(k_digit_split, dim3((unsigned)((threads + 255) / 256), parents), dim3(256), 0, stream, k, l);
-    const size_t mthreads = (size_t)((s + l - 1) / 4 + 1) * m.NT;
-    hipLaunchKernelGGL(k_kara_mid_lv, dim3((unsigned)((mthreads + 255) / 256), parents), dim3(256), 0, stream, k, l);
+    const size_t threads = (size_t)nmax * nr;
+    hipLaunchKernelGGL(k_digit_split, dim3((unsigned)((threads + 255) / 256), parents), dim3(256), 0, stream, k, l,
+                       r0);
+    const size_t mthreads = (size_t)((s + l - 1) / 4 + 1) * nr;
+    hipLaunchKernelGGL(k_kara_mid_lv, dim3((unsigned)((mthreads + 255) / 256), parents), dim3(256), 0, stream, k, l,
+                       r0);
   }
   return hipGetLastError();
 }
