@@ -103,6 +103,25 @@ def sample_limb_macs(N, cols, nl):
     return sum((N - i - 1) * (N - i) / 2 for i in range(cols)) * nl * nl
 
 
+def kara_digit_pairs(S, levels):
+    """Digit pairs one entry-column update multiplies: S^2 for the digit
+    product, else the sum over the 3^L products of their operand lengths
+    squared (lo halves reset the extra digits, hi halves keep them, mid halves
+    add one)."""
+    if levels <= 0:
+        return S * S
+    Sp = (S + 255) // 256 * 256
+    total = 0
+    for p in range(3 ** levels):
+        e, div = 0, 3 ** (levels - 1)
+        for _ in range(levels):
+            c = (p // div) % 3
+            e = 0 if c == 0 else (e if c == 1 else e + 1)
+            div //= 3
+        total += ((Sp >> levels) + e) ** 2
+    return total
+
+
 def valu_roofline(ctx, achieved, what):
     """The VALU form's Schur update against the vector ALU's integer
     multiply-add peak, with the rate the issue-rate probe measures beside it."""
@@ -250,12 +269,14 @@ def main():
         out["stages_ms"]["kara_combine"] = ms[9]
     if a.form == "mfma" and ms[6] > 0:
         # int8 ops the GEMMs need per entry and panel column: the digit product
-        # multiplies S^2 digit pairs (S = P/8, 16 per limb-MAC), L Karatsuba
-        # levels 3^L products of S/2^L + L digits;
+        # multiplies S^2 digit pairs (S = P/8, 16 per limb-MAC); L Karatsuba
+        # levels multiply, for each of the 3^L products, its own operand length
+        # squared: S'/2^L digits plus one per mid half since the last lo half
+        # on its path (S' = S rounded up to a multiple of 256, the split strings);
         # 2 ops per multiply-add
         S = P // 8
         units = stages["schur_limb_macs"] / (nl * nl)   # entry x panel-column updates
-        pairs = 3 ** lv * (S // 2 ** lv + lv) ** 2   # lv = 0: the digit product
+        pairs = kara_digit_pairs(S, lv)
         ops = units * pairs * 2
         achieved = ops / (ms[6] * 1e-3) / 1e12
         kname = "k_upd_kara" if kara else "k_upd_mfma"

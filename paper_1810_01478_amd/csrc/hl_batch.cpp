@@ -307,7 +307,7 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
         E.m.bdig = ka.pan[I.kara] + (size_t)p * ka.pan_stride[I.kara];
         E.m.udig = ka.pan[I.kara] + (size_t)(np + p) * ka.pan_stride[I.kara];
         E.m.slices = ka.kslices;
-        E.m.S = ka.Sk;
+        E.m.S = kara_prod_digits(ka.m.S, I.kara, p);  // its own operand length (<= Sk)
         E.m.carry = ka.m.carry + (size_t)p * u.ntiles * rt.n * 1024;
         E.rt = rt;
         E.C_lo = u.C_lo;

@@ -191,6 +191,21 @@ __host__ __device__ __forceinline__ int kara_nwp(int S, int levels) {
 __host__ __device__ __forceinline__ constexpr int kara_products(int levels) {
   return levels <= 0 ? 1 : 3 * kara_products(levels - 1);
 }
+// digits beyond S/2^l of level-l panel q (base-3 path, most significant digit
+// first): lo children have none, hi children their parent's, mid children one more
+__host__ __device__ __forceinline__ int kara_extra(int q, int l) {
+  int e = 0, div = 1;
+  for (int j = 1; j < l; ++j) div *= 3;
+  for (int j = 0; j < l; ++j) {
+    const int c = (q / div) % 3;
+    e = c == 0 ? 0 : (c == 1 ? e : e + 1);
+    div /= 3;
+  }
+  return e;
+}
+// digits of the operands of product p at the leaf level L (its own length; the
+// panel holds Sk = S/2^L + L, the rest zero)
+__host__ __device__ __forceinline__ int kara_prod_digits(int S, int L, int p) { return (S >> L) + kara_extra(p, L); }
 
 // Batched form: one entry per instance and step, work items (entry, tile index
 // of the entry's launch, range) in 8 per-XCD queues of per_xcd items (x < 0:

@@ -29,19 +29,6 @@ __global__ void k_recode_kara(const u32* __restrict__ src, size_t lds, int npan,
   for (int b = 0; b < 4; ++b) d[(size_t)b * rstride] = (int8_t)(v >> (8 * b));
 }
 
-// digits beyond S/2^l of level-l panel q (base-3 path, most significant digit
-// first): lo children have none, hi children their parent's, mid children one more
-__device__ __forceinline__ int kara_extra(int q, int l) {
-  int e = 0, div = 1;
-  for (int j = 1; j < l; ++j) div *= 3;
-  for (int j = 0; j < l; ++j) {
-    const int c = (q / div) % 3;
-    e = c == 0 ? 0 : (c == 1 ? e : e + 1);
-    div /= 3;
-  }
-  return e;
-}
-
 // floor((x + 128) / 256) for -512 <= x + 128: the balanced carry out of a
 // digit position holding x
 __device__ __forceinline__ int bal_carry(int x) { return (x + 640) / 256 - 2; }

@@ -29,6 +29,9 @@
 // 128-bit value, twice; the low 64 bits are the new limbs and X >> 64 the carry
 // into the next pair of limbs.  The carry out of each wave's limb range is
 // stored and added by k_carry_fix, so ranges of one tile run in parallel.
+#include <type_traits>
+#include <utility>
+
 #include "hl_kernels.hpp"
 
 namespace hl {
@@ -127,6 +130,25 @@ __device__ __forceinline__ int opaque_i32(int v) {
 // last partial rotation whose steps are skipped past the block's end (no
 // padding steps); the next block's operands are requested before this block's
 // sums are folded, so their latency hides behind the fold.
+// MFMAs a step issues: all MF_T, or in the first rotation of a skipping
+// block those whose digit pairs reach an output digit (see mfma_tile_t)
+constexpr int mf_issued(int st, bool skip, bool rev) {
+  int n = 0;
+  for (int q = 0; q < MF_T; ++q)
+    if (!skip || (rev ? q >= MF_T - 2 - 2 * st : q <= 2 * st + 1)) ++n;
+  return n;
+}
+
+// f(integral_constant<int, 0>) .. f(integral_constant<int, N - 1>), in order
+template <typename F, int... I>
+__device__ __forceinline__ void mf_unroll_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void mf_unroll(F&& f) {
+  mf_unroll_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 constexpr int MF_FOLD = 4;  // entries folded together
 
 template <bool STORE>
@@ -160,67 +182,101 @@ __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig
     const int r = R * 32 + mf_row(l, v), c = C * 32 + mf_col(l);
     if ((!g.tri || r >= c) && r >= g.r_lo && r < g.r_hi && c >= g.c_lo && c < g.c_hi) live |= 1u << v;
   }
-  // Window slot (y mod MF_WIN) holds the slice at offset t0 - jlo + y; step s
-  // multiplies y = q - 2s for q = 0..MF_T-1 and loads y = -2 MF_PF - 2s,
-  // -2 MF_PF + 1 - 2s for step s + MF_PF.  A digits are likewise loaded MF_PF
-  // steps ahead into a ring.
+  // The steps of a block are the digit pairs (j, j + 1), j = jlo, jlo + 2, ..,
+  // jtop; forward blocks take them upwards, reverse blocks downwards (the same
+  // pairs, so the same sums).  Forward: window slot (y mod MF_WIN) holds the
+  // u slice at digit t0 - jlo + y (minus the lane half); step s multiplies
+  // y = q - 2s for q = 0..MF_T-1 and loads y = -2 MF_PF - 2s, -2 MF_PF + 1 - 2s
+  // for step s + MF_PF.  Reverse: slot y holds digit t0 - jtop + y; step r
+  // multiplies y = q + 2r and loads y = 2 MF_PF + 2r + 14, + 15.  A digits are
+  // loaded MF_PF steps ahead into a ring either way.
+  //
+  // Output digit t0 + q gets nothing from pair j when t0 + q - j - 1 > S - 1 or
+  // t0 + q - j < 0.  A block with t0 >= S - 1 has jlo >= t0 - S, so its first
+  // steps s = 0..7 (forward) need only q <= 2s + 1; a block with
+  // t0 + MF_T - 1 <= S - 1 has jtop = t0 + 14, so its first steps r = 0..6
+  // (reverse) need only q >= 14 - 2r.  Those blocks run their first rotation
+  // with the other MFMAs left out (at compile time); the block between the two
+  // kinds runs forward with all of them.
   v4i w[MF_WIN];
   v4i an[MF_PF];
-  int ap = 0, un = 0, nsteps = 0;
-  // block tb's steps (pairs of digits j) and its first operands
-#define MF_PROLOGUE(tb_)                                                          \
-  do {                                                                           \
-    const int t0_ = MF_T * (tb_);                                                \
-    int jlo_ = t0_ - (S - 1);                                                    \
-    if (jlo_ < 0) jlo_ = 0;                                                      \
-    jlo_ &= ~1;                                                                  \
-    int jhi_ = t0_ + MF_T - 1;                                                   \
-    if (jhi_ > S - 1) jhi_ = S - 1;                                              \
-    nsteps = (jhi_ - jlo_) / 2 + 1;                                              \
-    const int ub_ = (pad - 1 + t0_ - jlo_) * sst;                                \
-    _Pragma("unroll") for (int y = 0; y < MF_T; ++y) w[y] = bld16(ru, uoff, ub_ + y * sst); \
-    _Pragma("unroll") for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = bld16(ru, uoff, ub_ + y * sst); \
-    ap = (pad + jlo_) * sst;                                                     \
-    _Pragma("unroll") for (int q = 0; q < MF_PF; ++q) an[q] = bld16(rb, aoff, ap + 2 * q * sst); \
-    ap += 2 * MF_PF * sst;                                                       \
-    un = ub_ - 2 * MF_PF * sst;                                                  \
-  } while (0)
-  // one step (st: its place in the rotation, a compile-time constant)
-#define MF_STEP(st)                                                               \
-  do {                                                                           \
-    const v4i a_ = an[(st) % MF_PF];                                             \
-    an[(st) % MF_PF] = bld16(rb, aoff, ap);                                      \
-    const int k0_ = (MF_WIN * 4 - 2 * MF_PF - 2 * (st)) % MF_WIN;                \
-    w[k0_] = bld16(ru, uoff, un);                                                \
-    w[k0_ + 1] = bld16(ru, uoff, un + sst);                                      \
-    _Pragma("unroll") for (int q = 0; q < MF_T; ++q)                             \
-      acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_, w[(q - 2 * (st) + MF_WIN * 4) % MF_WIN], acc[q], 0, 0, 0); \
-    ap += 2 * sst;                                                               \
-    un -= 2 * sst;                                                               \
-    __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);                           \
-    __builtin_amdgcn_sched_group_barrier(0x008, MF_T, 0);                        \
-  } while (0)
-
-  if (tb0 < tb1) MF_PROLOGUE(tb0);
-  for (int tb = tb0; tb < tb1; ++tb) {
-    v16i acc[MF_T];
+  int ap = 0, un = 0, nsteps = 0, dir = 0;  // dir: 0 forward, 1 forward skipping, 2 reverse skipping
+  // block tb's steps and its first operands (REV: a block of the first kind
+  // below, run downwards)
+  auto prologue = [&](int tb_, auto revc) {
+    constexpr bool REV = decltype(revc)::value;
+    const int t0_ = MF_T * tb_;
+    int jlo_ = t0_ - (S - 1);
+    if (jlo_ < 0) jlo_ = 0;
+    jlo_ &= ~1;
+    int jhi_ = t0_ + MF_T - 1;
+    if (jhi_ > S - 1) jhi_ = S - 1;
+    nsteps = (jhi_ - jlo_) / 2 + 1;
+    if (!REV) {
+      dir = t0_ >= S - 1 ? 1 : 0;
+      const int ub_ = (pad - 1 + t0_ - jlo_) * sst;
 #pragma unroll
-    for (int q = 0; q < MF_T; ++q) acc[q] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    // Let the prologue's loads land here, once per block: the loop header then
-    // only sees the loads in flight from the previous rotation, and its wait
-    // keeps the MF_PF steps of prefetch instead of draining them every rotation.
-    __builtin_amdgcn_s_waitcnt(kVmcntZero);
-    const int nfull = nsteps / MF_ROT, rem = nsteps - nfull * MF_ROT;
-    for (int rot = 0; rot < nfull; ++rot) {
+      for (int y = 0; y < MF_T; ++y) w[y] = bld16(ru, uoff, ub_ + y * sst);
 #pragma unroll
-      for (int st = 0; st < MF_ROT; ++st) MF_STEP(st);
+      for (int y = -2 * (MF_PF - 1); y < 0; ++y) w[MF_WIN + y] = bld16(ru, uoff, ub_ + y * sst);
+      ap = (pad + jlo_) * sst;
+#pragma unroll
+      for (int q = 0; q < MF_PF; ++q) an[q] = bld16(rb, aoff, ap + 2 * q * sst);
+      ap += 2 * MF_PF * sst;
+      un = ub_ - 2 * MF_PF * sst;
+    } else {
+      dir = 2;
+      const int jtop_ = jlo_ + 2 * (nsteps - 1);
+      const int ub_ = (pad - 1 + t0_ - jtop_) * sst;
+#pragma unroll
+      for (int y = 0; y < MF_T + 2 * (MF_PF - 1); ++y) w[y] = bld16(ru, uoff, ub_ + y * sst);
+      ap = (pad + jtop_) * sst;
+#pragma unroll
+      for (int q = 0; q < MF_PF; ++q) an[q] = bld16(rb, aoff, ap - 2 * q * sst);
+      ap -= 2 * MF_PF * sst;
+      un = ub_ + (MF_T + 2 * (MF_PF - 1)) * sst;
     }
-    // the last partial rotation: steps past the block's end are skipped
+  };
+  v16i acc[MF_T];
+  // one step (its place st in the rotation and the skip, compile-time constants)
+  auto step_f = [&](auto stc, auto skc) {
+    constexpr int st = decltype(stc)::value;
+    constexpr bool SK = decltype(skc)::value;
+    const v4i a_ = an[st % MF_PF];
+    an[st % MF_PF] = bld16(rb, aoff, ap);
+    constexpr int k0 = (MF_WIN * 4 - 2 * MF_PF - 2 * st) % MF_WIN;
+    w[k0] = bld16(ru, uoff, un);
+    w[k0 + 1] = bld16(ru, uoff, un + sst);
 #pragma unroll
-    for (int st = 0; st < MF_ROT - 1; ++st)
-      if (st < rem) MF_STEP(st);
-    // the next block's first operands, in flight during the fold
-    if (tb + 1 < tb1) MF_PROLOGUE(tb + 1);
+    for (int q = 0; q < MF_T; ++q)
+      if (!SK || q <= 2 * st + 1)
+        acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_, w[(q - 2 * st + MF_WIN * 4) % MF_WIN], acc[q], 0, 0, 0);
+    ap += 2 * sst;
+    un -= 2 * sst;
+    __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, mf_issued(st, SK, false), 0);
+  };
+  auto step_r = [&](auto stc, auto skc) {
+    constexpr int st = decltype(stc)::value;
+    constexpr bool SK = decltype(skc)::value;
+    const v4i a_ = an[st % MF_PF];
+    an[st % MF_PF] = bld16(rb, aoff, ap);
+    constexpr int k0 = (2 * st + MF_T + 2 * (MF_PF - 1)) % MF_WIN;
+    w[k0] = bld16(ru, uoff, un);
+    w[k0 + 1] = bld16(ru, uoff, un + sst);
+#pragma unroll
+    for (int q = 0; q < MF_T; ++q)
+      if (!SK || q >= MF_T - 2 - 2 * st)
+        acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_, w[(q + 2 * st) % MF_WIN], acc[q], 0, 0, 0);
+    ap -= 2 * sst;
+    un += 2 * sst;
+    __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, mf_issued(st, SK, true), 0);
+  };
+  using SkipOn = std::integral_constant<bool, true>;
+  using SkipOff = std::integral_constant<bool, false>;
+
+  auto fold = [&](int tb) {
     // fold the 16 digit sums of each entry into limbs 4 tb .. 4 tb + 3 (one
     // slab): V = sum_k d_k 2^(32 k) + carry, d_k = sum_m out_(t0+4k+m) 2^(8 m)
     // (|d_k| < 2^56, exact in 64 bits), resolved 32 bits at a time: t_0 = d_0 +
@@ -284,9 +340,54 @@ __device__ __forceinline__ void mfma_tile_t(const UpdArgs& g, const int8_t* bdig
         carry_s[v * WAVE + l] = (int)(t[e][3] >> 32);
       }
     }
-  }
-#undef MF_STEP
-#undef MF_PROLOGUE
+  };
+  // blocks [ta, te) of one kind, each its steps and then its fold
+  auto run_blocks = [&](int ta, int te, auto revc) {
+    constexpr bool REV = decltype(revc)::value;
+    if (ta >= te) return;
+    prologue(ta, revc);
+    for (int tb = ta; tb < te; ++tb) {
+#pragma unroll
+      for (int q = 0; q < MF_T; ++q) acc[q] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      // Let the prologue's loads land here, once per block: the loop header
+      // then only sees the loads in flight from the previous rotation, and its
+      // wait keeps the MF_PF steps of prefetch instead of draining them every
+      // rotation.
+      __builtin_amdgcn_s_waitcnt(kVmcntZero);
+      // the first rotation of a skipping block (steps past the block's end
+      // left out), then whole rotations, then one partial rotation
+      int left = nsteps;
+      if (REV) {
+        mf_unroll<MF_ROT>([&](auto stc) {
+          if (decltype(stc)::value < left) step_r(stc, SkipOn{});
+        });
+        left -= MF_ROT;
+        for (; left >= MF_ROT; left -= MF_ROT) mf_unroll<MF_ROT>([&](auto stc) { step_r(stc, SkipOff{}); });
+        mf_unroll<MF_ROT - 1>([&](auto stc) {
+          if (decltype(stc)::value < left) step_r(stc, SkipOff{});
+        });
+      } else {
+        if (dir == 1) {
+          mf_unroll<MF_ROT>([&](auto stc) {
+            if (decltype(stc)::value < left) step_f(stc, SkipOn{});
+          });
+          left -= MF_ROT;
+        }
+        for (; left >= MF_ROT; left -= MF_ROT) mf_unroll<MF_ROT>([&](auto stc) { step_f(stc, SkipOff{}); });
+        mf_unroll<MF_ROT - 1>([&](auto stc) {
+          if (decltype(stc)::value < left) step_f(stc, SkipOff{});
+        });
+      }
+      // the next block's first operands, in flight during the fold
+      if (tb + 1 < te) prologue(tb + 1, revc);
+      fold(tb);
+    }
+  };
+  // blocks with t0 + MF_T - 1 <= S - 1 run downwards, the others upwards; the
+  // two loops share no registers, so each keeps its own window in place
+  const int tb_rev = S >= MF_T ? (S - MF_T) / MF_T + 1 : 0;
+  run_blocks(tb0, tb1 < tb_rev ? tb1 : tb_rev, std::integral_constant<bool, true>{});
+  run_blocks(tb0 > tb_rev ? tb0 : tb_rev, tb1, std::integral_constant<bool, false>{});
   // carries out of this range
 #pragma unroll
   for (int v = 0; v < 16; ++v) cb[mf_row(l, v) * 32 + mf_col(l)] = (long long)carry_s[v * WAVE + l];
@@ -420,8 +521,9 @@ void k_upd_kara(KaraArgs k, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   if (R * 32 >= k.m.NT) return;
   const int8_t* leaf = k.pan[k.levels];
   const size_t ls = k.pan_stride[k.levels];
+  // the product's own operand length: the steps and blocks past it are empty
   mfma_tile_t<true>(g, leaf + (size_t)p * ls, leaf + (size_t)(np + p) * ls, k.kslices,
-                    k.Sk, k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
+                    kara_prod_digits(k.m.S, k.levels, p), k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
                     k.m.carry + (((size_t)p * ntiles + lt) * rt.n + rg) * 1024,
                     k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp), k.nwp);
 }
