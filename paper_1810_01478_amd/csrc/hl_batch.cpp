@@ -312,8 +312,9 @@ void record_update_step(hl_batch* B, Blob& blob, std::vector<StepUpd>& ups) {
         E.rt = rt;
         E.C_lo = u.C_lo;
         E.ntiles = u.ntiles;
-        E.store = ka.prod + (size_t)p * ka.prod_tiles * tile_words(ka.nwp);
+        E.store = ka.prod + (size_t)p * tile_words(ka.nwp);  // tile lt's products at lt np
         E.store_nw = ka.nwp;
+        E.store_ts = (size_t)np * tile_words(ka.nwp);
         kents.push_back(E);
       }
       Op o;

@@ -92,6 +92,7 @@ hipError_t launch_upd_valu_batch(const UpdArgs* tab, int count, int nr_max, int 
 namespace hl {
 // exact update with int8-digit MFMA GEMMs
 // register window of the int8 MFMA tile loop (k_upd_mfma.hip)
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
 constexpr int MF_T = 16;             // output digits per accumulation block
 constexpr int MF_LPB = MF_T / 4;     // limbs per block (one 16-byte slab of an entry)
 constexpr int MF_PF = 8;             // operands are loaded this many steps ahead
@@ -172,7 +173,7 @@ struct KaraArgs {
   int pan_slices[KA_MAX_LEVELS + 1];
   int Sk;              // digits per operand of a product (kara_leaf_digits)
   int kslices;         // Sk + 2 pad
-  u32* prod;           // products: [np][prod_tiles] tiles of nwp limbs per entry
+  u32* prod;           // products: [prod_tiles][np] tiles of nwp limbs per entry (a launch tile's np together)
   int nwp;             // limbs per product entry: 4 x output blocks of a (2 Sk - 1)-digit product
   size_t prod_tiles;   // tiles per product
 };
@@ -216,10 +217,11 @@ struct MfmaEntry {
   int C_lo;
   int ntiles;
   // null: the sums are subtracted from the target (m.g); else the exact sums of
-  // launch tile lt are stored at store + lt * tile_words(store_nw) (a Karatsuba
-  // product of the digit panels m.bdig, m.udig)
+  // launch tile lt are stored at store + lt * store_ts, tiles of store_nw limbs
+  // per entry (a Karatsuba product of the digit panels m.bdig, m.udig)
   u32* store;
   int store_nw;
+  size_t store_ts;
 };
 struct RecodeArgs {
   const u32* src;

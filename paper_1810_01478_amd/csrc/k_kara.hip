@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C
   int R, C;
   if (!kara_entry(k, C_lo, lt, e, &R, &C) || has_error(k.m.g.st)) return;
   const int r = e >> 5, c = e & 31;
-  u32* Q = k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp);
+  u32* Q = k.prod + ((size_t)lt * kara_products(k.levels) + p) * tile_words(k.nwp);
   const long long* cb = k.m.carry + ((size_t)p * ntiles + lt) * rt.n * 1024 + e;
   for (int w = 0; w + 1 < rt.n; ++w) add_at_limb(Q, r, c, MF_LPB * rt.tb[w + 1], k.nwp, cb[(size_t)w * 1024]);
 }
@@ -241,7 +241,23 @@ __global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C
 // every product through once (each lane its 8 bytes), and stores the segments,
 // each with its own running carry; at the end the carry out of segment m
 // enters at its successor's first slab.
-__device__ __forceinline__ void ka_apply(i64* s, const uint2& v, int sg, bool top_hi) {
+//
+// Memory: the launch tile's products are contiguous (tile lt holds its np
+// products, tw words apart) and read through one buffer descriptor: a lane
+// offset (the entry, the product) in a register, the slab in a scalar.  The
+// products go in groups of KA_G; the loads of group g + 1 are issued before
+// group g is added in (two groups of slabs in registers), and the lane offset
+// passes an empty asm that depends on the accumulators after group g - 1, so the
+// compiler neither hoists later loads into the accumulators' registers nor keeps
+// 3^L product offsets live.
+template <int LV>
+struct KaComb {
+  static constexpr int NP = kara_products(LV);
+  static constexpr int G = LV <= 2 ? NP : 3;  // products per load group
+  static constexpr int NG = (NP + G - 1) / G;
+};
+
+__device__ __forceinline__ void ka_apply(i64 (&s)[2], const uint2& v, int sg, bool top_hi) {
   // top_hi: this lane holds limbs 2, 3 of the top slab, whose limb 3 is signed
   const i64 v1 = top_hi ? (i64)(int)v.y : (i64)v.y;
   if (sg > 0) {
@@ -251,118 +267,92 @@ __device__ __forceinline__ void ka_apply(i64* s, const uint2& v, int sg, bool to
   }
 }
 
-// 8 bytes at the wave-uniform base plus the lane's byte offset (keeps the many
-// product and segment bases in scalar registers)
-__device__ __forceinline__ uint2 ld_lane(const u32* base, u32 voff) {
-  return *(const uint2*)((const char*)base + voff);
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint2 bld8(__amdgpu_buffer_rsrc_t r, u32 voff, int soff) {
+  const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0);
+  return make_uint2(v.x, v.y);
 }
 
 // the partner lane's value (lanes 2i and 2i + 1 swap)
-__device__ __forceinline__ i64 partner64(i64 v) {
-  const int lo = __builtin_amdgcn_mov_dpp((int)(u32)v, 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(u32)((u64)v >> 32), 0xB1, 0xF, 0xF, false);
-  return (i64)(((u64)(u32)hi << 32) | (u32)lo);
+__device__ __forceinline__ int partner32(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+
+// Group g's slabs: product p = g G + i at lane offset vo + i tw4; lo slab jj,
+// hi slab O + jj, the top slab 2 O at jj = 0.
+template <int LV, int GI>
+__device__ __forceinline__ void ka_load(__amdgpu_buffer_rsrc_t rp, u32 vo, u32 tw4, int s_lo, int s_hi, int s_top,
+                                        bool jj0, uint2 (&b)[KaComb<LV>::G][3]) {
+  constexpr int G = KaComb<LV>::G;
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    if (GI * G + i < KaComb<LV>::NP) {
+      const u32 v = vo + (u32)i * tw4;
+      b[i][0] = bld8(rp, v, s_lo);
+      b[i][1] = bld8(rp, v, s_hi);
+      if (jj0) b[i][2] = bld8(rp, v, s_top);
+    }
+  }
 }
 
-// does product p have a term reaching segments [M0, M1)?
-template <int LV>
-constexpr bool ka_needed(int p, int M0, int M1) {
-  const KaPoly<LV> T{};
-  for (int t = T.first[p]; t < T.first[p + 1]; ++t)
-    if (T.t[t].pw < M1 && T.t[t].pw + 2 >= M0) return true;
-  return false;
-}
-
-// Term TI onwards for the segments [M0, M1) held in s (s[0] is segment M0),
-// every index a compile-time constant: the slabs of a product are loaded at its
-// first term, products in groups of three whose loads are in flight together
-// (the fence keeps the compiler from hoisting later groups' loads into the
-// registers the accumulators need).
-template <int LV, int M0, int M1, int TI>
-__device__ __forceinline__ void ka_term(i64 (&s)[M1 - M0][2], const u32* P0, u32& voff, size_t pst, int O, int jj,
-                                        bool hi_half, uint2& lo, uint2& hi, uint2& top) {
+// the terms of group g's products, every index a compile-time constant
+template <int LV, int GI, int TI>
+__device__ __forceinline__ void ka_apply_term(i64 (&s)[2 << LV][2], const uint2 (&b)[KaComb<LV>::G][3], bool jj0,
+                                              bool hi_half) {
   constexpr KaTerm TT = KaPoly<LV>().t[TI];
-  if constexpr (ka_needed<LV>(TT.p, M0, M1)) {
-    if constexpr (TI == KaPoly<LV>().first[TT.p]) {
-      // a new group of three products: its addresses take a (void) dependence
-      // on every accumulator, so its loads issue after the previous group has
-      // been added in and at most one group's slabs occupy registers
-      if constexpr (TT.p % 3 == 0 && TT.p > 0) {
-        u32 dep = 0;
-#pragma unroll
-        for (int m = 0; m < M1 - M0; ++m) dep ^= (u32)s[m][0] ^ (u32)s[m][1];
-        asm volatile("" : "+v"(voff) : "v"(dep));
-      }
-      const u32* Qp = P0 + (size_t)TT.p * pst;
-      lo = ld_lane(Qp + (size_t)jj * 4096, voff);
-      hi = ld_lane(Qp + (size_t)(O + jj) * 4096, voff);
-      if (jj == 0) top = ld_lane(Qp + (size_t)(2 * O) * 4096, voff);
-    }
-    if constexpr (TT.pw >= M0 && TT.pw < M1) ka_apply(s[TT.pw - M0], lo, TT.sg, false);
-    if constexpr (TT.pw + 1 >= M0 && TT.pw + 1 < M1) ka_apply(s[TT.pw + 1 - M0], hi, TT.sg, false);
-    if constexpr (TT.pw + 2 >= M0 && TT.pw + 2 < M1) {
-      if (jj == 0) ka_apply(s[TT.pw + 2 - M0], top, TT.sg, hi_half);
+  if constexpr (TT.p / KaComb<LV>::G == GI) {
+    // (slabs that land above the entry's 2^(L+1) segments leave it)
+    constexpr int i = TT.p - GI * KaComb<LV>::G, NSEG = 2 << LV;
+    if constexpr (TT.pw < NSEG) ka_apply(s[TT.pw], b[i][0], TT.sg, false);
+    if constexpr (TT.pw + 1 < NSEG) ka_apply(s[TT.pw + 1], b[i][1], TT.sg, false);
+    if constexpr (TT.pw + 2 < NSEG) {
+      if (jj0) ka_apply(s[TT.pw + 2], b[i][2], TT.sg, hi_half);
     }
   }
 }
-
-// every term, each a separate inlined call (no recursion, so the accumulators
-// stay in registers)
-template <int LV, int M0, int M1, int... TI>
-__device__ __forceinline__ void ka_terms(std::integer_sequence<int, TI...>, i64 (&s)[M1 - M0][2], const u32* P0,
-                                         u32& voff, size_t pst, int O, int jj, bool hi_half) {
-  uint2 lo = make_uint2(0u, 0u), hi = lo, top = lo;
-  (ka_term<LV, M0, M1, TI>(s, P0, voff, pst, O, jj, hi_half, lo, hi, top), ...);
+template <int LV, int GI, int... TI>
+__device__ __forceinline__ void ka_apply_group(std::integer_sequence<int, TI...>, i64 (&s)[2 << LV][2],
+                                               const uint2 (&b)[KaComb<LV>::G][3], bool jj0, bool hi_half) {
+  (ka_apply_term<LV, GI, TI>(s, b, jj0, hi_half), ...);
 }
 
-// segments [M0, M1) of the entry: this lane's half of slab jj of each in
-// registers, the products reaching them streamed through once per jj; cy[m - M0]
-// (valid in the low-half lane) is the carry out of segment m.  Slabs at or above
-// nq (the entry's nw / 4; there are some when the split strings carry zero
-// digits above the factors') are neither read nor written: they only receive
-// carries, and the entry keeps its value modulo 2^(32 nw).
-template <int LV, int M0, int M1>
-__device__ __forceinline__ void ka_pass(u32* At, const u32* P0, u32 voff0, size_t pst, int O, int nq, bool hi_half,
-                                        i64 (&cy)[M1 - M0]) {
-  constexpr int NS = M1 - M0;
+// group GI: fence, the next group's loads, then this group's terms
+template <int LV, int GI>
+__device__ __forceinline__ void ka_group(i64 (&s)[2 << LV][2], uint2 (&b0)[KaComb<LV>::G][3],
+                                         uint2 (&b1)[KaComb<LV>::G][3], __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4,
+                                         int s_lo, int s_hi, int s_top, bool jj0, bool hi_half) {
+  constexpr int G = KaComb<LV>::G, NG = KaComb<LV>::NG;
+  uint2(&cur)[G][3] = (GI % 2 == 0) ? b0 : b1;
+  uint2(&nxt)[G][3] = (GI % 2 == 0) ? b1 : b0;
+  if constexpr (GI + 1 < NG) {
+    // the accumulators after group GI - 1 (the registers of nxt are free)
+    u32 dep = 0;
 #pragma unroll
-  for (int m = 0; m < NS; ++m) cy[m] = 0;
-  for (int jj = 0; jj < O; ++jj) {
-    u32 voff = voff0;
-    i64 s[NS][2];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      uint2 a = make_uint2(0u, 0u);
-      if ((M0 + m) * O + jj < nq) a = ld_lane(At + (size_t)((M0 + m) * O + jj) * 4096, voff);
-      s[m][0] = a.x; s[m][1] = a.y;
-    }
-    ka_terms<LV, M0, M1>(std::make_integer_sequence<int, KaPoly<LV>::NT>{}, s, P0, voff, pst, O, jj, hi_half);
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      // limbs 0, 1 with the segment's running carry (low-half lane), their
-      // carry into limb 2 to the partner, limbs 2, 3 with it (high-half lane),
-      // and the carry out of limb 3 back to the low-half lane
-      const i64 a0 = s[m][0] + (hi_half ? 0 : cy[m]);
-      const i64 a1 = s[m][1] + (a0 >> 32);
-      const i64 cmid = partner64(a1 >> 32);
-      const i64 b0 = s[m][0] + cmid;
-      const i64 b1 = s[m][1] + (b0 >> 32);
-      const i64 x0 = hi_half ? b0 : a0, x1 = hi_half ? b1 : a1;
-      cy[m] = partner64(b1 >> 32);
-      if ((M0 + m) * O + jj < nq)
-        *(uint2*)((char*)(At + (size_t)((M0 + m) * O + jj) * 4096) + voff) = make_uint2((u32)x0, (u32)x1);
-    }
+    for (int m = 0; m < (2 << LV); ++m) dep ^= (u32)s[m][0] ^ (u32)s[m][1];
+    asm volatile("" : "+v"(vo) : "v"(dep));
+    ka_load<LV, GI + 1>(rp, vo, tw4, s_lo, s_hi, s_top, jj0, nxt);
+    vo += (u32)G * tw4;
   }
+  ka_apply_group<LV, GI>(std::make_integer_sequence<int, KaPoly<LV>::NT>{}, s, cur, jj0, hi_half);
+}
+template <int LV, int... GI>
+__device__ __forceinline__ void ka_groups(std::integer_sequence<int, GI...>, i64 (&s)[2 << LV][2],
+                                          uint2 (&b0)[KaComb<LV>::G][3], uint2 (&b1)[KaComb<LV>::G][3],
+                                          __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4, int s_lo, int s_hi,
+                                          int s_top, bool jj0, bool hi_half) {
+  (ka_group<LV, GI>(s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top, jj0, hi_half), ...);
 }
 
 // a -= sum_p c_p(Y) P_p for every live entry of the launch, two lanes per
-// entry (see ka_pass), in one pass over the 2^(L+1) segments; then the carry
-// out of every segment enters at its successor's first slab (the last one
-// leaves the entry).
+// entry, in one pass over the 2^(L+1) segments; then the carry out of every
+// segment enters at its successor's first slab (the last one leaves the
+// entry).  Slabs at or above nq (the entry's nw / 4; there are some when the
+// split strings carry zero digits above the factors') are neither read nor
+// written: they only receive carries, and the entry keeps its value modulo
+// 2^(32 nw).
 template <int LV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LV <= 2 ? 4 : 2)))
 void k_kara_comb(KaraArgs k, int C_lo) {
-  constexpr int NSEG = 2 << LV;
+  constexpr int NSEG = 2 << LV, G = KaComb<LV>::G;
   const UpdArgs& g = k.m.g;
   const int lt = blockIdx.x >> 3, e = (blockIdx.x & 7) * 128 + (threadIdx.x >> 1);
   const bool hi_half = (threadIdx.x & 1) != 0;
@@ -371,16 +361,57 @@ void k_kara_comb(KaraArgs k, int C_lo) {
   if (!kara_entry(k, C_lo, lt, e, &R, &C) || has_error(g.st)) return;
   const int r = e >> 5, c = e & 31;
   const size_t tix = g.tri ? tri_tile_index(R, C) : (size_t)R * g.ntc + C;
-  const size_t tw = tile_words(k.nwp), pst = k.prod_tiles * tw;
-  u32* At = g.A + tix * tile_words(g.nw);   // wave-uniform bases, the lane's offset apart
-  const u32* P0 = k.prod + (size_t)lt * tw;
+  const size_t tw = tile_words(k.nwp);
+  u32* At = g.A + tix * tile_words(g.nw);
+  const u32* P0 = k.prod + (size_t)lt * KaComb<LV>::NP * tw;  // this tile's np products
+  const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(At, 0, (int)(tile_words(g.nw) * 4), kRawBufferWord3);
+  const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(const_cast<u32*>(P0), 0,
+                                                                      (int)(KaComb<LV>::NP * tw * 4), kRawBufferWord3);
+  const u32 tw4 = (u32)(tw * 4);
   const u32 voff = (u32)in_tile(r, c, 0) * 4 + (hi_half ? 8u : 0u);
   const int O = k.m.S / (16 << LV), nq = g.nw / 4;
-  i64 cy[NSEG];
-  ka_pass<LV, 0, NSEG>(At, P0, voff, pst, O, nq, hi_half, cy);
+  int cy[NSEG];
+#pragma unroll
+  for (int m = 0; m < NSEG; ++m) cy[m] = 0;
+  for (int jj = 0; jj < O; ++jj) {
+    i64 s[NSEG][2];
+#pragma unroll
+    for (int m = 0; m < NSEG; ++m) {
+      uint2 a = make_uint2(0u, 0u);
+      if (m * O + jj < nq) a = bld8(ra, voff, (m * O + jj) * 16384);
+      s[m][0] = a.x;
+      s[m][1] = a.y;
+    }
+    const bool jj0 = jj == 0;
+    const int s_lo = jj * 16384, s_hi = (O + jj) * 16384, s_top = 2 * O * 16384;
+    uint2 b0[G][3], b1[G][3];
+    u32 vo = voff;
+    ka_load<LV, 0>(rp, vo, tw4, s_lo, s_hi, s_top, jj0, b0);
+    vo += (u32)G * tw4;
+    ka_groups<LV>(std::make_integer_sequence<int, KaComb<LV>::NG>{}, s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top, jj0,
+                  hi_half);
+#pragma unroll
+    for (int m = 0; m < NSEG; ++m) {
+      // limbs 0, 1 with the segment's running carry (low-half lane), their
+      // carry into limb 2 to the partner, limbs 2, 3 with it (high-half lane),
+      // and the carry out of limb 3 back to the low-half lane (the carries fit
+      // 32 bits: a slab sums at most 5^L <= 625 terms of two 32-bit limbs each)
+      const i64 a0 = s[m][0] + (hi_half ? 0 : cy[m]);
+      const i64 a1 = s[m][1] + (a0 >> 32);
+      const int cmid = partner32((int)(a1 >> 32));
+      const i64 b0_ = s[m][0] + cmid;
+      const i64 b1_ = s[m][1] + (b0_ >> 32);
+      const i64 x0 = hi_half ? b0_ : a0, x1 = hi_half ? b1_ : a1;
+      cy[m] = partner32((int)(b1_ >> 32));
+      if (m * O + jj < nq) {
+        const v2u o = {(u32)x0, (u32)x1};
+        __builtin_amdgcn_raw_buffer_store_b64(o, ra, (int)voff, (m * O + jj) * 16384, 0);
+      }
+    }
+  }
   if (!hi_half) {
 #pragma unroll
-    for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, cy[m]);
+    for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, (i64)cy[m]);
   }
 }
 

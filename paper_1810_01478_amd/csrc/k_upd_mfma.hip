@@ -80,7 +80,6 @@ __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
 __device__ __forceinline__ v4i bld16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
 }
-constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
 
 // s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left at their
 // maxima (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
@@ -445,7 +444,7 @@ void k_upd_mfma_b(const MfmaEntry* __restrict__ tab, const int4* __restrict__ it
     long long* cb = e.m.carry + ((size_t)it.y * e.rt.n + it.z) * 1024;
     if (e.store)
       mfma_tile_t<true>(e.m.g, e.m.bdig, e.m.udig, e.m.slices, e.m.S, e.m.pad, e.m.NT, R, C, e.rt.tb[it.z],
-                        e.rt.tb[it.z + 1], cb, e.store + (size_t)it.y * tile_words(e.store_nw), e.store_nw);
+                        e.rt.tb[it.z + 1], cb, e.store + (size_t)it.y * e.store_ts, e.store_nw);
     else
       mfma_tile(e.m, R, C, e.rt.tb[it.z], e.rt.tb[it.z + 1], cb);
   }
@@ -525,7 +524,7 @@ void k_upd_kara(KaraArgs k, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   mfma_tile_t<true>(g, leaf + (size_t)p * ls, leaf + (size_t)(np + p) * ls, k.kslices,
                     kara_prod_digits(k.m.S, k.levels, p), k.m.pad, k.m.NT, R, C, rt.tb[rg], rt.tb[rg + 1],
                     k.m.carry + (((size_t)p * ntiles + lt) * rt.n + rg) * 1024,
-                    k.prod + ((size_t)p * k.prod_tiles + lt) * tile_words(k.nwp), k.nwp);
+                    k.prod + ((size_t)lt * np + p) * tile_words(k.nwp), k.nwp);
 }
 
 // ---------------------------------------------------------------------------
