@@ -420,6 +420,16 @@ void k_upd_mfma(MfmaArgs m, RangeTab rt, int C_lo, int ntiles, int per_xcd) {
   mfma_tile(m, R, C, rt.tb[rg], rt.tb[rg + 1], m.carry + ((size_t)lt * rt.n + rg) * 1024);
 }
 
+// The batch kernel's two kinds of work item, each its own function: inlined
+// together, the two tile loops would share one register allocation and spill.
+__device__ __noinline__ void batch_tile_store(const MfmaEntry& e, int R, int C, int lt, int rg, long long* cb) {
+  mfma_tile_t<true>(e.m.g, e.m.bdig, e.m.udig, e.m.slices, e.m.S, e.m.pad, e.m.NT, R, C, e.rt.tb[rg], e.rt.tb[rg + 1],
+                    cb, e.store + (size_t)lt * e.store_ts, e.store_nw);
+}
+__device__ __noinline__ void batch_tile_sub(const MfmaEntry& e, int R, int C, int rg, long long* cb) {
+  mfma_tile(e.m, R, C, e.rt.tb[rg], e.rt.tb[rg + 1], cb);
+}
+
 // Batch of updates (one entry per instance, or per Karatsuba product of an
 // instance) in one persistent launch.  Work items (entry, tile, range) sit in 8
 // queues, one per XCD, each largest first;
@@ -443,10 +453,9 @@ void k_upd_mfma_b(const MfmaEntry* __restrict__ tab, const int4* __restrict__ it
     if (R * 32 >= e.m.NT) continue;
     long long* cb = e.m.carry + ((size_t)it.y * e.rt.n + it.z) * 1024;
     if (e.store)
-      mfma_tile_t<true>(e.m.g, e.m.bdig, e.m.udig, e.m.slices, e.m.S, e.m.pad, e.m.NT, R, C, e.rt.tb[it.z],
-                        e.rt.tb[it.z + 1], cb, e.store + (size_t)it.y * e.store_ts, e.store_nw);
+      batch_tile_store(e, R, C, it.y, it.z, cb);
     else
-      mfma_tile(e.m, R, C, e.rt.tb[it.z], e.rt.tb[it.z + 1], cb);
+      batch_tile_sub(e, R, C, it.z, cb);
   }
 }
 
