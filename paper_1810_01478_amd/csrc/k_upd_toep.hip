@@ -80,6 +80,21 @@ __device__ __forceinline__ u32* tp_entry(const ToepArgs& a, int r, int c, int Lq
   return g.A + tix * tile_words(g.nw) + in_tile(r, c, Lq);
 }
 
+// one accumulator register, read by itself (taking an element of the vector
+// otherwise copies the whole vector out of the accumulation registers)
+__device__ __forceinline__ int tp_acc(int v) {
+  int o;
+  asm("v_accvgpr_read_b32 %0, %1" : "=v"(o) : "a"(v));
+  return o;
+}
+// acc * m + d as one 32 x 32 -> 64-bit signed multiply-add (m opaque, so that
+// a power of two does not become 64-bit shifts)
+__device__ __forceinline__ i64 tp_mad(int acc, int m, i64 d) { return (i64)acc * (i64)m + d; }
+__device__ __forceinline__ int tp_opaque(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 // One work item: rows 32 RB .. 32 RB + 31, column c_lo + cc, output digits
 // [512 rg, 512 rg + 512); the carry out of the range goes to cb[0..31].
 __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int cc, long long* cb) {
@@ -149,7 +164,8 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
       }
     }
   }
-  // entry (r, c) of this lane; lane half h holds chunks (q, h): limbs t0/4 + 8q + 4h .. + 3
+  // entry (r, c) of this lane; lane half h holds chunks (q, h): limbs L0 + 8 q ..
+  // L0 + 8 q + 3
   const int r = RB * 32 + n, c = g.c_lo + cc;
   const bool live = r >= g.r_lo && r < g.r_hi && c < g.c_hi && (!g.tri || r >= c);
   const int L0 = t0 / 4 + 4 * h;
@@ -159,23 +175,30 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
     const int Lq = L0 + 8 * q;
     x[q] = (live && Lq < g.nw && a.add != 2) ? *(const uint4*)tp_entry(a, r, c, Lq) : make_uint4(0, 0, 0, 0);
   }
-  if (a.add) {
-#pragma unroll
-    for (int q = 0; q < TP_Q; ++q) acc[q] = -acc[q];
-  }
-  // x - sum_v 256^v out_v per chunk: 128 bits in x, the rest in zc
-  i64 zc[TP_Q];
+  // x -/+ sum_v 256^v out_v per chunk, 32 bits at a time: limb k takes the
+  // digit sums 4k .. 4k + 3 (one 32 x 32 -> 64-bit multiply-add each, the
+  // multipliers +-2^(8m) opaque) and the carry of limb k - 1; the chunk's carry
+  // (below 2^25 in magnitude) goes to zc
+  const int sg = a.add ? 1 : -1;
+  const int m0 = tp_opaque(sg), m8 = tp_opaque(sg << 8), m16 = tp_opaque(sg << 16), m24 = tp_opaque(sg * (1 << 24));
+  const int one = tp_opaque(1);
+  int zc[TP_Q];
 #pragma unroll
   for (int q = 0; q < TP_Q; ++q) {
-    i64 dd[4] = {0, 0, 0, 0};
+    const u32 xa[4] = {x[q].x, x[q].y, x[q].z, x[q].w};
+    i64 t[4];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) dd[v >> 2] += (i64)acc[q][v] << (8 * (v & 3));
-    const __int128 X = (__int128)(((u64)x[q].y << 32) | x[q].x) - (__int128)dd[0] - ((__int128)dd[1] << 32);
-    const __int128 Y = (__int128)(((u64)x[q].w << 32) | x[q].z) - (__int128)dd[2] - ((__int128)dd[3] << 32) +
-                       (__int128)(i64)(X >> 64);
-    const u64 lo = (u64)X, hi = (u64)Y;
-    x[q] = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
-    zc[q] = (i64)(Y >> 64);
+    for (int k = 0; k < 4; ++k) {
+      i64 y = (i64)xa[k];
+      y = tp_mad(tp_acc(acc[q][4 * k]), m0, y);
+      y = tp_mad(tp_acc(acc[q][4 * k + 1]), m8, y);
+      y = tp_mad(tp_acc(acc[q][4 * k + 2]), m16, y);
+      t[k] = tp_mad(tp_acc(acc[q][4 * k + 3]), m24, y);
+    }
+#pragma unroll
+    for (int k = 1; k < 4; ++k) t[k] = tp_mad((int)(t[k - 1] >> 32), one, t[k]);
+    x[q] = make_uint4((u32)t[0], (u32)t[1], (u32)t[2], (u32)t[3]);
+    zc[q] = (int)(t[3] >> 32);
   }
   // carries through the chunks in limb order: (0,0), (0,1), (1,0), ...
   i64 carry = 0;
@@ -190,7 +213,7 @@ __device__ __forceinline__ void toep_item(const ToepArgs& a, int rg, int RB, int
       const int delta = carry >= 0 ? (V < U ? 1 : 0) : (V > U ? -1 : 0);
       const u64 lo = (u64)V, hi = (u64)(V >> 64);
       x[q] = make_uint4((u32)lo, (u32)(lo >> 32), (u32)hi, (u32)(hi >> 32));
-      cout = zc[q] + delta;
+      cout = (i64)zc[q] + delta;
     }
     carry = __shfl(cout, half * 32 + n, WAVE);
   }
