@@ -407,9 +407,9 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
   }
 
   const size_t ldb = (size_t)dm.NT * dm.nl;
-  // MFMA form: pivot i + 1 runs on the aux stream while column i's in-panel
-  // update runs on the caller's; it subtracts b_{i+1} u_{i+1} itself, so that
-  // update leaves out the diagonal row i + 1
+  // MFMA form: pivot i + 1 runs on the aux stream while column i's step and
+  // in-panel update run on the caller's; it forms b_{i+1} u_{i+1} of column i
+  // itself and subtracts it, so that update leaves out the diagonal row i + 1
   const bool look = sh->form == HL_FORM_MFMA8;
   if (look) HIPCHK(ensure_aux(ctx));
   for (int i0 = col_begin; i0 < col_end; i0 += 16) {
@@ -421,6 +421,16 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
         HIPCHK(launch_pivot(A, dm, i, out->d, out->h, omega, L.omega_stride, dst, st));
       } else {
         HIPCHK(hipStreamWaitEvent(st, ctx->ev_piv, 0));
+      }
+      if (look && il + 1 < npan) {
+        // pivot i + 1 needs pivot i and row i + 1 as the previous columns'
+        // updates left it: it forms row i + 1's factors of column i itself and
+        // runs beside this column's step and update
+        HIPCHK(hipEventRecord(ctx->ev_col, st));
+        HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_col, 0));
+        HIPCHK(launch_pivot(A, dm, i + 1, out->d, out->h, omega, L.omega_stride, dst, ctx->aux, nullptr, nullptr,
+                            1));
+        HIPCHK(hipEventRecord(ctx->ev_piv, ctx->aux));
       }
       if (sh->form == HL_FORM_MFMA8) {
         u32* ucol = up + (size_t)il * ldb;
@@ -461,14 +471,6 @@ extern "C" hl_status hl_factor_cols(hl_ctx* ctx, const hl_shape* sh, const uint3
                           out->l + (size_t)i * ldb, dst, st));
       }
       if (il + 1 < npan) {
-        if (look) {
-          HIPCHK(hipEventRecord(ctx->ev_col, st));
-          HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_col, 0));
-          HIPCHK(launch_pivot(A, dm, i + 1, out->d, out->h, omega, L.omega_stride, dst, ctx->aux,
-                              out->l + (size_t)i * ldb + (size_t)(i + 1) * dm.nl,
-                              up + (size_t)il * ldb + (size_t)(i + 1) * dm.nl));
-          HIPCHK(hipEventRecord(ctx->ev_piv, ctx->aux));
-        }
         UpdArgs g{};
         g.A = A;
         g.tri = 1;

@@ -14,7 +14,8 @@ hipError_t launch_scales(const u32* mu, const i64* mu_exp, int w, int N, int E, 
 hipError_t launch_load(const u32* mu, const i64* mu_exp, int w, const i32* s, const Dims& dm, u32* A,
                        DevStatus* st, hipStream_t stream);
 hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
-                        DevStatus* st, hipStream_t stream, const u32* sub_b = nullptr, const u32* sub_u = nullptr);
+                        DevStatus* st, hipStream_t stream, const u32* sub_b = nullptr, const u32* sub_u = nullptr,
+                        int from_row = 0);
 hipError_t launch_col(const u32* A, const Dims& dm, int i, int r0, const i32* h, const u32* omega,
                       int ostride, u32* u_out, u32* l_col, DevStatus* st, hipStream_t stream);
 hipError_t launch_fill(u32* p, size_t n, u32 v, hipStream_t stream);
@@ -44,6 +45,11 @@ struct PivotArgs {
   // column's in-panel update (nl limbs each, two's complement)
   const u32* sub_b = nullptr;
   const u32* sub_u = nullptr;
+  // nonzero (with no sub_b, sub_u): the pivot is a_ii - b u with b, u the
+  // previous column's factors of row i, formed here from a_(i,i-1), h_(i-1)
+  // and w_(i-1) exactly as the column step forms them (so it need not wait for
+  // that column step)
+  int from_row = 0;
 };
 struct ColArgs {
   const u32* A;

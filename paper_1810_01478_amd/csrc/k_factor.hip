@@ -287,7 +287,51 @@ __device__ void pivot_body(const PivotArgs& a) {
   const u32* src = A + tri_tile_index(i >> 5, i >> 5) * tile_words(nw);
   for (int l = threadIdx.x; l < nw; l += blockDim.x) dl[l] = src[in_tile(i, i, l)];
   __syncthreads();
-  if (a.sub_b) {
+  if (a.from_row) {
+    // u = rnd(a_(i,j) / 2^h_j), b = rnd(u w_j / 2^P) for j = i - 1, the same
+    // steps as the column step of column j for row i (col_body), then
+    // a_ii - b u = a_ii - |b| |u| (b is zero or has the sign of u)
+    const int NB = nl + 8, j = i - 1;
+    u32* As = lds;              // a_ij, nw limbs
+    u32* Us = lds + 2 * NB;     // |u|, nl + 1 limbs
+    u32* Ws = lds + 3 * NB;     // w_j
+    u32* Pr = lds + 4 * NB;     // |u| w_j + 2^(P-1), 2 nl + 1 limbs
+    u32* Pt = lds + 6 * NB;     // |b| |u|, nw limbs
+    int* flag = (int*)(lds + 8 * NB);
+    u32* buf = lds + 9 * NB;    // 6 NB: product scratch and carry chains
+    const size_t cap = (size_t)6 * NB * 4;
+    const u32 lim_top = 0x60000000u;  // 3 * 2^(P-3) in the top limb
+    const u32* srcj = A + tri_tile_index(i >> 5, j >> 5) * tile_words(nw);
+    for (int l = threadIdx.x; l < nw; l += blockDim.x) As[l] = srcj[in_tile(i, j, l)];
+    const u32* om = omega_tab + (size_t)j * omega_stride;
+    for (int l = threadIdx.x; l < nl + 4; l += blockDim.x) Ws[l] = l < omega_stride ? om[l] : 0u;
+    __syncthreads();
+    if (wave_id() == 0) {
+      const bool nega = (As[nw - 1] >> 31) != 0;
+      if (nega) w_neg(As, nw);
+      wsync();
+      const int hj = h_out[j];
+      if (hj > 0) w_add_word(As, nw, (hj - 1) >> 5, 1u << ((hj - 1) & 31));
+      wsync();
+      w_shift_right(As, nw, hj, Us, nl + 1);
+      wsync();
+      if (lane_id() == 0) flag[0] = (Us[nl] != 0 || Us[nl - 1] >= lim_top) ? 1 : 0;
+    }
+    __syncthreads();
+    // an overflow is reported by the column step of column j, which sees the
+    // same row: this pivot leaves everything as it is
+    if (flag[0]) return;
+    pv_mul(Us, nl, Ws, nl + 1, Pr, 2 * nl + 1, buf, cap);
+    if (wave_id() == 0) {
+      w_add_word(Pr, 2 * nl + 1, nl - 1, 0x80000000u);
+      wsync();
+      if (lane_id() == 0) flag[1] = (Pr[2 * nl] != 0 || Pr[2 * nl - 1] >= lim_top) ? 1 : 0;
+    }
+    __syncthreads();
+    if (flag[1]) return;
+    pv_mul(Pr + nl, nl, Us, nl, Pt, nw, buf, cap);
+    wg_sub(dl, Pt, dl, nw, buf);
+  } else if (a.sub_b) {
     // a_ii - b u, exact: |b| |u| by the workgroup product, then subtracted or
     // added by the signs (the scratch regions of the reciprocal are free here)
     const int NB = nl + 8;
@@ -627,11 +671,12 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
 }
 
 hipError_t launch_pivot(u32* A, const Dims& dm, int i, u32* d_out, i32* h_out, u32* omega, int ostride,
-                        DevStatus* st, hipStream_t stream, const u32* sub_b, const u32* sub_u) {
+                        DevStatus* st, hipStream_t stream, const u32* sub_b, const u32* sub_u, int from_row) {
   hipError_t e = allow_lds((const void*)k_pivot, pivot_lds_bytes(dm.nl));
   if (e != hipSuccess) return e;
   if ((sub_b == nullptr) != (sub_u == nullptr)) return hipErrorInvalidValue;
-  const PivotArgs a{A, dm, i, d_out, h_out, omega, ostride, st, sub_b, sub_u};
+  if (from_row && (sub_b || i < 1)) return hipErrorInvalidValue;
+  const PivotArgs a{A, dm, i, d_out, h_out, omega, ostride, st, sub_b, sub_u, from_row};
   hipLaunchKernelGGL(k_pivot, dim3(1), dim3(PIVOT_THREADS), pivot_lds_bytes(dm.nl), stream, a);
   return hipGetLastError();
 }
