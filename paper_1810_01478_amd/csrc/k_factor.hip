@@ -120,10 +120,13 @@ __device__ void wg_add_i32(u32* x, int n, int d, u32* rip) {
 // Product for the reciprocal's steps (non-negative operands): the one-workgroup
 // MFMA form once the operands are large and its scratch fits in the column-sum
 // buffer (cap bytes), else the product scan on the vector ALU.  Same bits.
+// lo_limb > 0 (the MFMA form only): limbs below lo_limb need not be formed and
+// the limbs from there on may lack the carry out of the part below (see
+// wg_mfma_mul); the product scan forms the whole product.
 __device__ __forceinline__ void pv_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout, u32* buf,
-                                       size_t cap) {
+                                       size_t cap, int lo_limb = 0) {
   if ((long)na * nb >= 16384 && wm_scratch_bytes(na, nb) <= cap)
-    wg_mfma_mul(a, na, b, nb, out, nout, buf);
+    wg_mfma_mul(a, na, b, nb, out, nout, buf, lo_limb);
   else
     g_mul(a, na, b, nb, out, nout, buf);
 }
@@ -173,11 +176,15 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
     const int nq = (int)(q / 32) + 2;
     // dq = floor(D * 2^(q - LD))
     wg_shift_right(D, nd, LD - q, dq, nq);
-    // T = dq * Y
-    const int nT = nq + ny;
+    // T = dq * Y, E = 2^(p+q) - T.  A converging step has |E| < 2^(32 (nq + 2))
+    // (checked below), so once p + q reaches 32 (nq + 3), E is T's low nq + 3
+    // limbs negated, read as a signed number: only those limbs of the product
+    // are formed
+    const bool short_t = p + q >= 32L * (nq + 3);
+    const int nT = short_t ? nq + 3 : nq + ny;
     pv_mul(dq, nq, Y, ny, T, nT, colbuf, cap);
-    // E = 2^(p+q) - T  (two's complement over nT + 1 limbs)
-    const int nE = nT + 1;
+    // E = 2^(p+q) - T  (two's complement over nE limbs)
+    const int nE = short_t ? nT : nT + 1;
     wg_sub_from_pow2(p + q, T, nT, T, nE, rip);
     const bool neg = (T[nE - 1] >> 31) != 0;
     __syncthreads();
@@ -189,8 +196,12 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
       res.ok = 0;
       break;
     }
+    // T2 = Y |E|, of which only the bits from 2p + q - pn up are used: the
+    // limbs more than two below them are not formed (Z may come out one unit
+    // low or high, within the step's guard bits)
     const int nT2 = ny + ne;
-    pv_mul(Y, ny, T, ne, T2, nT2, colbuf, cap);
+    const long zlo = (2 * p + q - pn) / 32 - 2;
+    pv_mul(Y, ny, T, ne, T2, nT2, colbuf, cap, zlo > 0 ? (int)zlo : 0);
     const int nyn = (int)((pn + 2) / 32) + 2;
     // Yn = Y << (pn - p);   Z = T2 >> (2p + q - pn)
     wg_shift_right(Y, ny, -(pn - p), Yn, nyn);
@@ -208,8 +219,10 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   // Z = Y >> (pf - (e - LD))  ~ 2^e / D
   const int nz = nl + 3;
   wg_shift_right(Y, ny, pf - (e - LD), Z, nz);
-  // R = 2^e - Z D, exact, over nR limbs
-  const int nR = (int)(e / 32) + 3;
+  // R = 2^e - Z D, exact, over nR limbs.  Z is within a few units of 2^e / D,
+  // so |R| < 2^(32 nd + 3): R is Z D's low nd + 2 limbs negated (e reaches
+  // 32 (nd + 2)), and only those limbs of the product are formed
+  const int nR = e >= 32L * (nd + 2) ? nd + 2 : (int)(e / 32) + 3;
   pv_mul(Z, nz, D, nd, T, nR, colbuf, cap);
   wg_sub_from_pow2(e, T, nR, T, nR, rip);
   // T2 = D zero-extended to nR (and zero up to NB for the comparison below)

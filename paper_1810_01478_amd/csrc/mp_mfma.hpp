@@ -80,10 +80,21 @@ __device__ __forceinline__ wm_v4i wm_window(wm_v4i lo, wm_v4i hi, int aw, int ab
 
 // out[0..nout) = a b mod 2^(32 nout); a, b, out and scratch in LDS (out may not
 // alias a or b); every thread of the workgroup calls it; ends with a barrier.
-__device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout, u32* scratch) {
+// Only the output sets (256 limbs each) below nout are formed.  lo_limb > 0:
+// the sets below the one holding limb lo_limb are left out too, and limbs lo ..
+// nout - 1 (lo = lo_limb rounded down to a set) receive the product's limbs
+// without the carry out of the part below lo (a 16-digit chunk's value is below
+// 2^151 in magnitude, so the result differs from (a b) >> 32 lo, modulo
+// 2^(32 (nout - lo)), by less than 2^24 units of limb lo); out[0..lo) is not
+// written.
+__device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, int nb, u32* out, int nout, u32* scratch,
+                                            int lo_limb = 0) {
   const int nth = blockDim.x, tid = threadIdx.x;
   const int nwv = nth / WAVE, w = wave_id(), l = lane_id(), h = l >> 5, n = l & 31;
   const int nJa = wm_chunks(na), nJb = wm_chunks(nb), nsets = wm_sets(na, nb);
+  const int set0 = lo_limb > 0 ? lo_limb / 256 : 0;
+  const int set1 = (nout + 255) / 256 < nsets ? (nout + 255) / 256 : nsets;
+  const int lo = 256 * set0;
   const int SA = 32 * nJa;
   int8_t* ar = (int8_t*)scratch;                 // WM_PAD + SA + WM_PAD
   int8_t* bf = ar + 2 * WM_PAD + SA;             // 32 nJb
@@ -113,7 +124,7 @@ __device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, 
   const int yb = WM_PAD + SA - 1 - tm + 16 * h;
   const int abase = yb & ~15, aw = (yb & 15) >> 2, ab = yb & 3;
   const wm_v4i zero4 = (wm_v4i){0, 0, 0, 0};
-  for (int set = w; set < nsets; set += nwv) {
+  for (int set = set0 + w; set < set1; set += nwv) {
     const int O = 32 * set;
     // window J holds a digits 32 J - 31 .. 32 J + 31, so J runs to nJa
     int J0 = O - nJb + 1;
@@ -167,37 +178,42 @@ __device__ __forceinline__ void wg_mfma_mul(const u32* a, int na, const u32* b, 
   }
   __syncthreads();
   // out = sum_ch (olo_ch + ocw_ch 2^128) 2^(128 ch): the chunk limbs plus the
-  // positive carries plus the complement of the negative ones, plus one
-  const int nch = 64 * nsets;
-  auto value = [=](int p) -> u64 {
-    u64 v = p < 4 * nch ? olo[p] : 0u;
+  // positive carries plus the complement of the negative ones, plus one at the
+  // lowest limb formed (chunks 64 set0 .. 64 set1 - 1; limb q of the result is
+  // value(q - lo))
+  const int ch0 = 64 * set0, ch1 = 64 * set1;
+  auto value = [=](int q) -> u64 {
+    const int p = q + lo;
+    u64 v = p < 4 * ch1 ? olo[p] : 0u;
     u32 pos = 0, neg = 0;
     const int c = (p >> 2) - 1, j = p & 3;
-    if (c >= 0 && c < nch && j < 2) {
+    if (c >= ch0 && c < ch1 && j < 2) {
       const i64 cw = ocw[c];
       const u64 m = cw < 0 ? (u64)(-cw) : (u64)cw;
       const u32 word = (u32)(m >> (32 * j));
       if (cw < 0) neg = word; else pos = word;
     }
     v += (u64)pos + (u64)(~neg);
-    if (p == 0) v += 1;
+    if (q == 0) v += 1;
     return v;
   };
+  const int nres = nout - lo;
+  u32* const outl = out + lo;
   // resolved by the whole workgroup, the digit strings (no longer needed) holding
   // the ripple table; one wave if they are too short for it
-  if ((size_t)8 * ((nout + WAVE - 1) / WAVE) <= (size_t)2 * WM_PAD + 32 * (nJa + nJb)) {
-    wg_resolve(nout, value, out, (u32*)ar);
+  if ((size_t)8 * ((nres + WAVE - 1) / WAVE) <= (size_t)2 * WM_PAD + 32 * (nJa + nJb)) {
+    wg_resolve(nres, value, outl, (u32*)ar);
     return;
   }
   if (w == 0) {
     u32 carry = 0;
     u64 vn = value(l);
-    for (int base = 0; base < nout; base += WAVE) {
+    for (int base = 0; base < nres; base += WAVE) {
       const int p = base + l;
       const u64 v = vn;
-      vn = p + WAVE < nout ? value(p + WAVE) : 0ull;
+      vn = p + WAVE < nres ? value(p + WAVE) : 0ull;
       const u32 limb = w_resolve(v, carry);
-      if (p < nout) out[p] = limb;
+      if (p < nres) outl[p] = limb;
     }
   }
   __syncthreads();
