@@ -117,6 +117,8 @@ __device__ void wg_add_i32(u32* x, int n, int d, u32* rip) {
   wg_resolve(n, [=](int p) -> u64 { return (u64)x[p] + (p == 0 ? (u32)d : ext); }, x, rip);
 }
 
+constexpr long kPivWaveBits = 2048;  // Newton steps up to this precision run in one wave
+
 // Product for the reciprocal's steps (non-negative operands): the one-workgroup
 // MFMA form once the operands are large and its scratch fits in the column-sum
 // buffer (cap bytes), else the product scan on the vector ALU.  Same bits.
@@ -166,7 +168,71 @@ __device__ PivotOut pivot_recip(const u32* d, int nw, int P, u32* omega, int n_o
   __syncthreads();
   long p = 30;
   int ny = 1;
-  while (p < pf) {
+  // The steps up to kPivWaveBits of precision, whose operands have at most 66
+  // limbs, run in wave 0 alone with the wave's own carry chains (the same
+  // arithmetic as the workgroup steps below, without a workgroup barrier per
+  // operation); the other waves wait at one barrier.
+  __shared__ long wv_p;
+  __shared__ int wv_ny, wv_fail;
+  if (wave_id() == 0) {
+    long pw = p;
+    int nyw = ny, fail = 0;
+    while (pw < pf) {
+      long pn = pf;
+      while ((pn + 13) / 2 > pw) pn = (pn + 13) / 2;
+      if (pn > kPivWaveBits) break;
+      const long q = pn + 8;
+      const int nq = (int)(q / 32) + 2;
+      w_shift_right(D, nd, LD - q, dq, nq);
+      wsync();
+      // T = dq Y, then E = 2^(p+q) - T over nT + 1 limbs
+      const int nT = nq + nyw, nE = nT + 1;
+      w_mul(dq, nq, Y, nyw, T, nT);
+      if (lane_id() == 0) T[nT] = 0;
+      wsync();
+      w_neg(T, nE);
+      wsync();
+      w_add_word(T, nE, (int)((pw + q) >> 5), 1u << ((pw + q) & 31));
+      wsync();
+      const bool neg = (T[nE - 1] >> 31) != 0;
+      if (neg) {
+        w_neg(T, nE);
+        wsync();
+      }
+      int ne = (w_bitlen(T, nE) + 31) / 32;
+      if (ne < 1) ne = 1;
+      if (ne > nq + 2) {
+        fail = 1;
+        break;
+      }
+      const int nT2 = nyw + ne;
+      w_mul(Y, nyw, T, ne, T2, nT2);
+      wsync();
+      const int nyn = (int)((pn + 2) / 32) + 2;
+      w_shift_right(Y, nyw, -(pn - pw), Yn, nyn);
+      w_shift_right(T2, nT2, 2 * pw + q - pn, Z, nyn);
+      wsync();
+      if (neg) {
+        w_sub(Yn, Z, Y, nyn);
+      } else {
+        w_add(Yn, nyn, Z, nyn, Y, nyn);
+      }
+      w_fill(Y + nyn, NB - nyn, 0u);
+      wsync();
+      nyw = nyn;
+      pw = pn;
+    }
+    if (lane_id() == 0) {
+      wv_p = pw;
+      wv_ny = nyw;
+      wv_fail = fail;
+    }
+  }
+  __syncthreads();
+  p = wv_p;
+  ny = wv_ny;
+  if (wv_fail) res.ok = 0;
+  while (p < pf && res.ok) {
     // precisions planned back from pf, each step at most doubling (less 12
     // guard bits): pn is the smallest of pf, c(pf), c(c(pf)), ... above p,
     // c(t) = ceil((t + 12) / 2), so the last step starts near pf / 2
