@@ -294,11 +294,17 @@ __device__ __forceinline__ void ka_load(__amdgpu_buffer_rsrc_t rp, u32 vo, u32 t
   }
 }
 
+// the term table of L levels, evaluated once
+template <int LV>
+struct KaTab {
+  static constexpr KaPoly<LV> P{};
+};
+
 // the terms of group g's products, every index a compile-time constant
 template <int LV, int GI, int TI>
 __device__ __forceinline__ void ka_apply_term(i64 (&s)[2 << LV][2], const uint2 (&b)[KaComb<LV>::G][3], bool jj0,
                                               bool hi_half) {
-  constexpr KaTerm TT = KaPoly<LV>().t[TI];
+  constexpr KaTerm TT = KaTab<LV>::P.t[TI];
   if constexpr (TT.p / KaComb<LV>::G == GI) {
     // (slabs that land above the entry's 2^(L+1) segments leave it)
     constexpr int i = TT.p - GI * KaComb<LV>::G, NSEG = 2 << LV;
@@ -309,11 +315,18 @@ __device__ __forceinline__ void ka_apply_term(i64 (&s)[2 << LV][2], const uint2 
     }
   }
 }
-template <int LV, int GI, int... TI>
-__device__ __forceinline__ void ka_apply_group(std::integer_sequence<int, TI...>, i64 (&s)[2 << LV][2],
+template <int LV, int GI, int T0, int... I>
+__device__ __forceinline__ void ka_apply_group(std::integer_sequence<int, I...>, i64 (&s)[2 << LV][2],
                                                const uint2 (&b)[KaComb<LV>::G][3], bool jj0, bool hi_half) {
-  (ka_apply_term<LV, GI, TI>(s, b, jj0, hi_half), ...);
+  (ka_apply_term<LV, GI, T0 + I>(s, b, jj0, hi_half), ...);
 }
+// the term range of group GI's products (the table is sorted by product)
+template <int LV, int GI>
+struct KaGroupTerms {
+  static constexpr int p0 = GI * KaComb<LV>::G;
+  static constexpr int p1 = p0 + KaComb<LV>::G < KaComb<LV>::NP ? p0 + KaComb<LV>::G : KaComb<LV>::NP;
+  static constexpr int t0 = KaTab<LV>::P.first[p0], t1 = KaTab<LV>::P.first[p1];
+};
 
 // group GI: fence, the next group's loads, then this group's terms
 template <int LV, int GI>
@@ -332,7 +345,8 @@ __device__ __forceinline__ void ka_group(i64 (&s)[2 << LV][2], uint2 (&b0)[KaCom
     ka_load<LV, GI + 1>(rp, vo, tw4, s_lo, s_hi, s_top, jj0, nxt);
     vo += (u32)G * tw4;
   }
-  ka_apply_group<LV, GI>(std::make_integer_sequence<int, KaPoly<LV>::NT>{}, s, cur, jj0, hi_half);
+  using GT = KaGroupTerms<LV, GI>;
+  ka_apply_group<LV, GI, GT::t0>(std::make_integer_sequence<int, GT::t1 - GT::t0>{}, s, cur, jj0, hi_half);
 }
 template <int LV, int... GI>
 __device__ __forceinline__ void ka_groups(std::integer_sequence<int, GI...>, i64 (&s)[2 << LV][2],
