@@ -683,8 +683,26 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
     // MFMA GEMMs of rank 16 accumulated into M (rows b, columns a <= b)
     u32* Y = (u32*)(base + L.blk_y);
     u32* M = (u32*)(base + L.blk_m);
-    HIPCHK(launch_fill(M, (size_t)dm.k * dm.k * L.blk_nm, 0u, st));
+    // The rank-16 launches over r leave half the GPU idle (k rows per 32-row
+    // item), so the odd row chunks run on the second stream into an
+    // accumulator and Toeplitz scratch of their own, carved from the
+    // trailing-matrix region (dead once the solve above has run); the gather
+    // adds the two accumulators.
+    const size_t mwords = (size_t)dm.k * dm.k * L.blk_nm;
+    const size_t o_bd = al(mwords * 4), o_ud = o_bd + al(L.toep_b_bytes), o_cy = o_ud + al(L.toep_u_bytes);
+    const bool two = dm.N > 16 && o_cy + L.toep_carry_words * 8 <= L.upanel - L.tiles;
+    char* t2 = base + L.tiles;
+    u32* M2 = two ? (u32*)t2 : nullptr;
+    HIPCHK(launch_fill(M, mwords, 0u, st));
+    if (two) {
+      HIPCHK(ensure_aux(ctx));
+      HIPCHK(launch_fill(M2, mwords, 0u, st));
+    }
     HIPCHK(launch_block_y(x, dm, omega, L.omega_stride, Y, L.blk_ny, dst, st));
+    if (two) {
+      HIPCHK(hipEventRecord(ctx->ev_col, st));
+      HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_col, 0));
+    }
     for (int r0 = 0; r0 < dm.N; r0 += 16) {
       UpdArgs g{};
       g.A = M;
@@ -711,10 +729,21 @@ extern "C" hl_status hl_inv_block(hl_ctx* ctx, const hl_shape* sh, const hl_fact
       ta.ldr = (size_t)dm.k * L.blk_nm;
       ta.ldc = (size_t)L.blk_nm;
       ta.add = 1;
-      HIPCHK(launch_upd_toep(ta, st));
+      const bool odd = two && ((r0 / 16) & 1);
+      if (odd) {
+        ta.g.A = M2;
+        ta.bd = (int8_t*)(t2 + o_bd);
+        ta.ud = (int8_t*)(t2 + o_ud);
+        ta.carry = (long long*)(t2 + o_cy);
+      }
+      HIPCHK(launch_upd_toep(ta, odd ? ctx->aux : st));
+    }
+    if (two) {
+      HIPCHK(hipEventRecord(ctx->ev_piv, ctx->aux));
+      HIPCHK(hipStreamWaitEvent(st, ctx->ev_piv, 0));
     }
     u32* part = (u32*)(base + L.blk_part);
-    HIPCHK(launch_block_gather(M, L.blk_nm, dm, part, L.blk_stride, dst, st));
+    HIPCHK(launch_block_gather(M, M2, L.blk_nm, dm, part, L.blk_stride, dst, st));
     HIPCHK(launch_block_sums(dm, f->s, part, L.blk_stride, 1, (u32*)(base + L.blk_sum), L.blk_stride + 64, blk,
                              blk_exp, dst, st));
   } else {

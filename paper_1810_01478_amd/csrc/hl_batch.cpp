@@ -835,7 +835,7 @@ hl_status issue(hl_batch* B, hipStream_t st) {
       case Op::BLOCKSUM: {
         const Inst& I = B->inst[o.inst];
         u32* part = (u32*)(I.base + I.L.blk_part);
-        HIPCHK(launch_block_gather((const u32*)(I.base + I.L.blk_m), I.L.blk_nm, I.dm, part, I.L.blk_stride, I.st,
+        HIPCHK(launch_block_gather((const u32*)(I.base + I.L.blk_m), nullptr, I.L.blk_nm, I.dm, part, I.L.blk_stride, I.st,
                                    st));
         HIPCHK(launch_block_sums(I.dm, I.in.f.s, part, I.L.blk_stride, 1, (u32*)(I.base + I.L.blk_sum),
                                  I.L.blk_stride + 64, I.in.blk, I.in.blk_exp, I.st, st));

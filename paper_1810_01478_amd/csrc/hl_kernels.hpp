@@ -263,7 +263,7 @@ hipError_t launch_block_sums(const Dims& dm, const i32* s, const u32* part, int 
 // MFMA form of the block sums (see k_block_y)
 hipError_t launch_block_y(const u32* X, const Dims& dm, const u32* omega, int ostride, u32* Y, int ny,
                           DevStatus* st, hipStream_t stream);
-hipError_t launch_block_gather(const u32* M, int nm, const Dims& dm, u32* part, int ns, DevStatus* st,
+hipError_t launch_block_gather(const u32* M, const u32* M2, int nm, const Dims& dm, u32* part, int ns, DevStatus* st,
                                hipStream_t stream);
 hipError_t launch_eig(const u32* blk, const Dims& dm, void* eig_ws, DevStatus* st, hipStream_t stream);
 struct EigArgs {

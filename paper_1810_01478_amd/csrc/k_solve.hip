@@ -269,17 +269,24 @@ __global__ __launch_bounds__(BY_THREADS) void k_block_y(const u32* __restrict__ 
   for (int l = threadIdx.x; l < ny; l += blockDim.x) yo[l] = l < 2 * nl + 1 ? pr[l] : ext;
 }
 
-// part[p][0] = M_(b, a) (nm limbs, sign-extended to ns), p = b (b + 1) / 2 + a
-__global__ __launch_bounds__(64) void k_block_gather(const u32* __restrict__ M, int nm, Dims dm,
-                                                     u32* __restrict__ part, int ns, DevStatus* st) {
+// part[p][0] = M_(b, a) (nm limbs, sign-extended to ns), p = b (b + 1) / 2 + a;
+// with M2 (the sums over the other half of the rows r), M_(b, a) + M2_(b, a)
+// (two's complement over nm limbs, which hold the exact sum)
+__global__ __launch_bounds__(64) void k_block_gather(const u32* __restrict__ M, const u32* __restrict__ M2, int nm,
+                                                     Dims dm, u32* __restrict__ part, int ns, DevStatus* st) {
   if (has_error(st)) return;
   const int p = blockIdx.x;
   int b = 0;
   while ((b + 1) * (b + 2) / 2 <= p) ++b;
   const int a = p - b * (b + 1) / 2;
   const u32* m = M + ((size_t)b * dm.k + a) * nm;
-  const u32 ext = (m[nm - 1] >> 31) ? 0xffffffffu : 0u;
   u32* o = part + (size_t)p * ns;
+  if (M2) {
+    w_add(m, nm, M2 + ((size_t)b * dm.k + a) * nm, nm, o, nm);
+    wsync();
+    m = o;
+  }
+  const u32 ext = (m[nm - 1] >> 31) ? 0xffffffffu : 0u;
   for (int l = lane_id(); l < ns; l += WAVE) o[l] = l < nm ? m[l] : ext;
 }
 
@@ -326,10 +333,10 @@ hipError_t launch_block_y(const u32* X, const Dims& dm, const u32* omega, int os
   return hipGetLastError();
 }
 
-hipError_t launch_block_gather(const u32* M, int nm, const Dims& dm, u32* part, int ns, DevStatus* st,
+hipError_t launch_block_gather(const u32* M, const u32* M2, int nm, const Dims& dm, u32* part, int ns, DevStatus* st,
                                hipStream_t stream) {
   if (ns < nm) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_block_gather, dim3(dm.k * (dm.k + 1) / 2), dim3(64), 0, stream, M, nm, dm, part, ns, st);
+  hipLaunchKernelGGL(k_block_gather, dim3(dm.k * (dm.k + 1) / 2), dim3(64), 0, stream, M, M2, nm, dm, part, ns, st);
   return hipGetLastError();
 }
 

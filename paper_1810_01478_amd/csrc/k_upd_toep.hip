@@ -450,13 +450,13 @@ hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
   const long items = (long)a.nrg * a.nrb * a.ncols;
   {
     const size_t n = (size_t)g.npan * rows * (tp_bstride(a.Sb) / 4);
-    hipLaunchKernelGGL(k_toep_recode_b, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_toep_recode_b, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
     const size_t n = (size_t)g.npan * a.ncols * (tp_ustride(a.Su) / 4);
-    hipLaunchKernelGGL(k_toep_recode_u, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_toep_recode_u, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -464,7 +464,7 @@ hipError_t launch_upd_toep(const ToepArgs& a0, hipStream_t stream) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.nrg < 2) return e;
   const size_t ne = rows * a.ncols;
-  hipLaunchKernelGGL(k_toep_carry, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(k_toep_carry, dim3((unsigned)((ne + 63) / 64)), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 
