@@ -184,6 +184,10 @@ hl_status hl_set_karatsuba(hl_ctx *ctx, int32_t mode);
  *            entries of L^-1 (x_mm = 2^(Q - h_m), Q = W - G, G = max_{m<k} s_m + 64)
  *   blk      device, k x k x nl limbs: (H^-1)_ab ~= blk_ab * 2^blk_exp, |blk_ab| <= 2^(P-2)
  *   blk_exp  device, 1 int64
+ * Uses the workspace's trailing-matrix region as scratch (the factorisation
+ * must be complete) and, in the MFMA form, the context's second stream for
+ * half of the block sums; the caller's stream waits for it, so the call stays
+ * ordered on that stream.
  * Device errors: HL_EOVERFLOW (index = row of L^-1).
  */
 hl_status hl_inv_block(hl_ctx *ctx, const hl_shape *sh, const hl_factor_t *f, void *ws,
