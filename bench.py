@@ -154,7 +154,7 @@ def main():
                     help="only copy 1 GiB device to device three times (calibrates HBM byte counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus %d)" % a.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (asked for --gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
 
