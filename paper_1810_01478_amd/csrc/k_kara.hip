@@ -245,11 +245,14 @@ __global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C
 // Memory: the launch tile's products are contiguous (tile lt holds its np
 // products, tw words apart) and read through one buffer descriptor: a lane
 // offset (the entry, the product) in a register, the slab in a scalar.  The
-// products go in groups of KA_G; the loads of group g + 1 are issued before
-// group g is added in (two groups of slabs in registers), and the lane offset
-// passes an empty asm that depends on the accumulators after group g - 1, so the
-// compiler neither hoists later loads into the accumulators' registers nor keeps
-// 3^L product offsets live.
+// products go in groups of G; the loads of group g + 1 are issued before
+// group g is added in (two groups of slabs in registers).  Before those loads
+// the accumulators pass through empty asm statements (they must hold their
+// values after group g - 1 there) and then the lane offset through one more,
+// so the compiler neither hoists later loads into the accumulators' registers
+// nor keeps 3^L product offsets live; the fence emits no instruction.  Slab
+// position 0, the only one that reads the products' top slabs, runs as its own
+// copy of the loop body, so the others carry no test for it.
 template <int LV>
 struct KaComb {
   static constexpr int NP = kara_products(LV);
@@ -279,9 +282,9 @@ __device__ __forceinline__ int partner32(int v) { return __builtin_amdgcn_mov_dp
 
 // Group g's slabs: product p = g G + i at lane offset vo + i tw4; lo slab jj,
 // hi slab O + jj, the top slab 2 O at jj = 0.
-template <int LV, int GI>
+template <int LV, int GI, bool J0>
 __device__ __forceinline__ void ka_load(__amdgpu_buffer_rsrc_t rp, u32 vo, u32 tw4, int s_lo, int s_hi, int s_top,
-                                        bool jj0, uint2 (&b)[KaComb<LV>::G][3]) {
+                                        uint2 (&b)[KaComb<LV>::G][3]) {
   constexpr int G = KaComb<LV>::G;
 #pragma unroll
   for (int i = 0; i < G; ++i) {
@@ -289,7 +292,7 @@ __device__ __forceinline__ void ka_load(__amdgpu_buffer_rsrc_t rp, u32 vo, u32 t
       const u32 v = vo + (u32)i * tw4;
       b[i][0] = bld8(rp, v, s_lo);
       b[i][1] = bld8(rp, v, s_hi);
-      if (jj0) b[i][2] = bld8(rp, v, s_top);
+      if constexpr (J0) b[i][2] = bld8(rp, v, s_top);
     }
   }
 }
@@ -301,8 +304,8 @@ struct KaTab {
 };
 
 // the terms of group g's products, every index a compile-time constant
-template <int LV, int GI, int TI>
-__device__ __forceinline__ void ka_apply_term(i64 (&s)[2 << LV][2], const uint2 (&b)[KaComb<LV>::G][3], bool jj0,
+template <int LV, int GI, int TI, bool J0>
+__device__ __forceinline__ void ka_apply_term(i64 (&s)[2 << LV][2], const uint2 (&b)[KaComb<LV>::G][3],
                                               bool hi_half) {
   constexpr KaTerm TT = KaTab<LV>::P.t[TI];
   if constexpr (TT.p / KaComb<LV>::G == GI) {
@@ -310,15 +313,13 @@ __device__ __forceinline__ void ka_apply_term(i64 (&s)[2 << LV][2], const uint2 
     constexpr int i = TT.p - GI * KaComb<LV>::G, NSEG = 2 << LV;
     if constexpr (TT.pw < NSEG) ka_apply(s[TT.pw], b[i][0], TT.sg, false);
     if constexpr (TT.pw + 1 < NSEG) ka_apply(s[TT.pw + 1], b[i][1], TT.sg, false);
-    if constexpr (TT.pw + 2 < NSEG) {
-      if (jj0) ka_apply(s[TT.pw + 2], b[i][2], TT.sg, hi_half);
-    }
+    if constexpr (J0 && TT.pw + 2 < NSEG) ka_apply(s[TT.pw + 2], b[i][2], TT.sg, hi_half);
   }
 }
-template <int LV, int GI, int T0, int... I>
+template <int LV, int GI, int T0, bool J0, int... I>
 __device__ __forceinline__ void ka_apply_group(std::integer_sequence<int, I...>, i64 (&s)[2 << LV][2],
-                                               const uint2 (&b)[KaComb<LV>::G][3], bool jj0, bool hi_half) {
-  (ka_apply_term<LV, GI, T0 + I>(s, b, jj0, hi_half), ...);
+                                               const uint2 (&b)[KaComb<LV>::G][3], bool hi_half) {
+  (ka_apply_term<LV, GI, T0 + I, J0>(s, b, hi_half), ...);
 }
 // the term range of group GI's products (the table is sorted by product)
 template <int LV, int GI>
@@ -329,31 +330,73 @@ struct KaGroupTerms {
 };
 
 // group GI: fence, the next group's loads, then this group's terms
-template <int LV, int GI>
+template <int LV, int GI, bool J0>
 __device__ __forceinline__ void ka_group(i64 (&s)[2 << LV][2], uint2 (&b0)[KaComb<LV>::G][3],
                                          uint2 (&b1)[KaComb<LV>::G][3], __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4,
-                                         int s_lo, int s_hi, int s_top, bool jj0, bool hi_half) {
+                                         int s_lo, int s_hi, int s_top, bool hi_half) {
   constexpr int G = KaComb<LV>::G, NG = KaComb<LV>::NG;
   uint2(&cur)[G][3] = (GI % 2 == 0) ? b0 : b1;
   uint2(&nxt)[G][3] = (GI % 2 == 0) ? b1 : b0;
   if constexpr (GI + 1 < NG) {
     // the accumulators after group GI - 1 (the registers of nxt are free)
-    u32 dep = 0;
 #pragma unroll
-    for (int m = 0; m < (2 << LV); ++m) dep ^= (u32)s[m][0] ^ (u32)s[m][1];
-    asm volatile("" : "+v"(vo) : "v"(dep));
-    ka_load<LV, GI + 1>(rp, vo, tw4, s_lo, s_hi, s_top, jj0, nxt);
+    for (int m = 0; m < (2 << LV); m += 2)
+      asm volatile("" : "+v"(s[m][0]), "+v"(s[m][1]), "+v"(s[m + 1][0]), "+v"(s[m + 1][1]));
+    asm volatile("" : "+v"(vo));
+    ka_load<LV, GI + 1, J0>(rp, vo, tw4, s_lo, s_hi, s_top, nxt);
     vo += (u32)G * tw4;
   }
   using GT = KaGroupTerms<LV, GI>;
-  ka_apply_group<LV, GI, GT::t0>(std::make_integer_sequence<int, GT::t1 - GT::t0>{}, s, cur, jj0, hi_half);
+  ka_apply_group<LV, GI, GT::t0, J0>(std::make_integer_sequence<int, GT::t1 - GT::t0>{}, s, cur, hi_half);
 }
-template <int LV, int... GI>
+template <int LV, bool J0, int... GI>
 __device__ __forceinline__ void ka_groups(std::integer_sequence<int, GI...>, i64 (&s)[2 << LV][2],
                                           uint2 (&b0)[KaComb<LV>::G][3], uint2 (&b1)[KaComb<LV>::G][3],
                                           __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4, int s_lo, int s_hi,
-                                          int s_top, bool jj0, bool hi_half) {
-  (ka_group<LV, GI>(s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top, jj0, hi_half), ...);
+                                          int s_top, bool hi_half) {
+  (ka_group<LV, GI, J0>(s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top, hi_half), ...);
+}
+
+// One slab position jj of every segment: load the segments' slabs, add in the
+// terms of every product, resolve the lane pair's carries and store.  J0: jj = 0,
+// the only position that also reads the products' top slabs.
+template <int LV, bool J0>
+__device__ __forceinline__ void ka_slab(int jj, int O, int nq, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rp,
+                                        u32 voff, u32 tw4, bool hi_half, int (&cy)[2 << LV]) {
+  constexpr int NSEG = 2 << LV, G = KaComb<LV>::G;
+  i64 s[NSEG][2];
+#pragma unroll
+  for (int m = 0; m < NSEG; ++m) {
+    uint2 a = make_uint2(0u, 0u);
+    if (m * O + jj < nq) a = bld8(ra, voff, (m * O + jj) * 16384);
+    s[m][0] = a.x;
+    s[m][1] = a.y;
+  }
+  const int s_lo = jj * 16384, s_hi = (O + jj) * 16384, s_top = 2 * O * 16384;
+  uint2 b0[G][3], b1[G][3];
+  u32 vo = voff;
+  ka_load<LV, 0, J0>(rp, vo, tw4, s_lo, s_hi, s_top, b0);
+  vo += (u32)G * tw4;
+  ka_groups<LV, J0>(std::make_integer_sequence<int, KaComb<LV>::NG>{}, s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top,
+                    hi_half);
+#pragma unroll
+  for (int m = 0; m < NSEG; ++m) {
+    // limbs 0, 1 with the segment's running carry (low-half lane), their
+    // carry into limb 2 to the partner, limbs 2, 3 with it (high-half lane),
+    // and the carry out of limb 3 back to the low-half lane (the carries fit
+    // 32 bits: a slab sums at most 5^L <= 625 terms of two 32-bit limbs each)
+    const i64 a0 = s[m][0] + (hi_half ? 0 : cy[m]);
+    const i64 a1 = s[m][1] + (a0 >> 32);
+    const int cmid = partner32((int)(a1 >> 32));
+    const i64 b0_ = s[m][0] + cmid;
+    const i64 b1_ = s[m][1] + (b0_ >> 32);
+    const i64 x0 = hi_half ? b0_ : a0, x1 = hi_half ? b1_ : a1;
+    cy[m] = partner32((int)(b1_ >> 32));
+    if (m * O + jj < nq) {
+      const v2u o = {(u32)x0, (u32)x1};
+      __builtin_amdgcn_raw_buffer_store_b64(o, ra, (int)voff, (m * O + jj) * 16384, 0);
+    }
+  }
 }
 
 // a -= sum_p c_p(Y) P_p for every live entry of the launch, two lanes per
@@ -366,7 +409,7 @@ __device__ __forceinline__ void ka_groups(std::integer_sequence<int, GI...>, i64
 template <int LV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LV <= 2 ? 4 : 2)))
 void k_kara_comb(KaraArgs k, int C_lo) {
-  constexpr int NSEG = 2 << LV, G = KaComb<LV>::G;
+  constexpr int NSEG = 2 << LV;
   const UpdArgs& g = k.m.g;
   const int lt = blockIdx.x >> 3, e = (blockIdx.x & 7) * 128 + (threadIdx.x >> 1);
   const bool hi_half = (threadIdx.x & 1) != 0;
@@ -387,42 +430,8 @@ void k_kara_comb(KaraArgs k, int C_lo) {
   int cy[NSEG];
 #pragma unroll
   for (int m = 0; m < NSEG; ++m) cy[m] = 0;
-  for (int jj = 0; jj < O; ++jj) {
-    i64 s[NSEG][2];
-#pragma unroll
-    for (int m = 0; m < NSEG; ++m) {
-      uint2 a = make_uint2(0u, 0u);
-      if (m * O + jj < nq) a = bld8(ra, voff, (m * O + jj) * 16384);
-      s[m][0] = a.x;
-      s[m][1] = a.y;
-    }
-    const bool jj0 = jj == 0;
-    const int s_lo = jj * 16384, s_hi = (O + jj) * 16384, s_top = 2 * O * 16384;
-    uint2 b0[G][3], b1[G][3];
-    u32 vo = voff;
-    ka_load<LV, 0>(rp, vo, tw4, s_lo, s_hi, s_top, jj0, b0);
-    vo += (u32)G * tw4;
-    ka_groups<LV>(std::make_integer_sequence<int, KaComb<LV>::NG>{}, s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top, jj0,
-                  hi_half);
-#pragma unroll
-    for (int m = 0; m < NSEG; ++m) {
-      // limbs 0, 1 with the segment's running carry (low-half lane), their
-      // carry into limb 2 to the partner, limbs 2, 3 with it (high-half lane),
-      // and the carry out of limb 3 back to the low-half lane (the carries fit
-      // 32 bits: a slab sums at most 5^L <= 625 terms of two 32-bit limbs each)
-      const i64 a0 = s[m][0] + (hi_half ? 0 : cy[m]);
-      const i64 a1 = s[m][1] + (a0 >> 32);
-      const int cmid = partner32((int)(a1 >> 32));
-      const i64 b0_ = s[m][0] + cmid;
-      const i64 b1_ = s[m][1] + (b0_ >> 32);
-      const i64 x0 = hi_half ? b0_ : a0, x1 = hi_half ? b1_ : a1;
-      cy[m] = partner32((int)(b1_ >> 32));
-      if (m * O + jj < nq) {
-        const v2u o = {(u32)x0, (u32)x1};
-        __builtin_amdgcn_raw_buffer_store_b64(o, ra, (int)voff, (m * O + jj) * 16384, 0);
-      }
-    }
-  }
+  ka_slab<LV, true>(0, O, nq, ra, rp, voff, tw4, hi_half, cy);
+  for (int jj = 1; jj < O; ++jj) ka_slab<LV, false>(jj, O, nq, ra, rp, voff, tw4, hi_half, cy);
   if (!hi_half) {
 #pragma unroll
     for (int m = 0; m + 1 < NSEG; ++m) add_at_limb(At, r, c, 4 * (m + 1) * O, g.nw, (i64)cy[m]);
