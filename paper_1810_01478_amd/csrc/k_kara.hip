@@ -259,6 +259,15 @@ struct KaComb {
   static constexpr int G = LV <= 2 ? NP : 3;  // products per load group
   static constexpr int NG = (NP + G - 1) / G;
 };
+// load groups in registers, NB - 1 of them in flight while one is added in: three
+// in the four-level main loop, two where more registers would cost occupancy
+// (three levels) or spill (slab position 0, which also holds the top slabs)
+template <int LV, bool J0>
+struct KaNb {
+  static constexpr int NB = LV >= 4 && !J0 ? 3 : 2;
+};
+template <int LV, bool J0>
+using KaBuf = uint2[KaNb<LV, J0>::NB][KaComb<LV>::G][3];
 
 __device__ __forceinline__ void ka_apply(i64 (&s)[2], const uint2& v, int sg, bool top_hi) {
   // top_hi: this lane holds limbs 2, 3 of the top slab, whose limb 3 is signed
@@ -271,6 +280,10 @@ __device__ __forceinline__ void ka_apply(i64 (&s)[2], const uint2& v, int sg, bo
 }
 
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+// a lane offset beyond every descriptor's size here: raw buffer loads from it
+// return zero (range check on the lane offset)
+constexpr u32 kBufferOutOfRange = 0x80000000u;
 
 __device__ __forceinline__ uint2 bld8(__amdgpu_buffer_rsrc_t r, u32 voff, int soff) {
   const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0);
@@ -331,30 +344,38 @@ struct KaGroupTerms {
 
 // group GI: fence, the next group's loads, then this group's terms
 template <int LV, int GI, bool J0>
-__device__ __forceinline__ void ka_group(i64 (&s)[2 << LV][2], uint2 (&b0)[KaComb<LV>::G][3],
-                                         uint2 (&b1)[KaComb<LV>::G][3], __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4,
-                                         int s_lo, int s_hi, int s_top, bool hi_half) {
+__device__ __forceinline__ void ka_group(i64 (&s)[2 << LV][2], KaBuf<LV, J0>& b,
+                                         __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4, int s_lo, int s_hi, int s_top,
+                                         bool hi_half) {
   constexpr int G = KaComb<LV>::G, NG = KaComb<LV>::NG;
-  uint2(&cur)[G][3] = (GI % 2 == 0) ? b0 : b1;
-  uint2(&nxt)[G][3] = (GI % 2 == 0) ? b1 : b0;
-  if constexpr (GI + 1 < NG) {
-    // the accumulators after group GI - 1 (the registers of nxt are free)
+  constexpr int NB = KaNb<LV, J0>::NB;
+  if constexpr (GI + NB - 1 < NG) {
+    // the accumulators after group GI - 1 (whose registers group GI + NB - 1 reuses)
 #pragma unroll
     for (int m = 0; m < (2 << LV); m += 2)
       asm volatile("" : "+v"(s[m][0]), "+v"(s[m][1]), "+v"(s[m + 1][0]), "+v"(s[m + 1][1]));
     asm volatile("" : "+v"(vo));
-    ka_load<LV, GI + 1, J0>(rp, vo, tw4, s_lo, s_hi, s_top, nxt);
+    ka_load<LV, GI + NB - 1, J0>(rp, vo, tw4, s_lo, s_hi, s_top, b[(GI + NB - 1) % NB]);
     vo += (u32)G * tw4;
   }
   using GT = KaGroupTerms<LV, GI>;
-  ka_apply_group<LV, GI, GT::t0, J0>(std::make_integer_sequence<int, GT::t1 - GT::t0>{}, s, cur, hi_half);
+  ka_apply_group<LV, GI, GT::t0, J0>(std::make_integer_sequence<int, GT::t1 - GT::t0>{}, s, b[GI % NB],
+                                     hi_half);
 }
 template <int LV, bool J0, int... GI>
 __device__ __forceinline__ void ka_groups(std::integer_sequence<int, GI...>, i64 (&s)[2 << LV][2],
-                                          uint2 (&b0)[KaComb<LV>::G][3], uint2 (&b1)[KaComb<LV>::G][3],
-                                          __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4, int s_lo, int s_hi,
-                                          int s_top, bool hi_half) {
-  (ka_group<LV, GI, J0>(s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top, hi_half), ...);
+                                          KaBuf<LV, J0>& b, __amdgpu_buffer_rsrc_t rp, u32& vo,
+                                          u32 tw4, int s_lo, int s_hi, int s_top, bool hi_half) {
+  (ka_group<LV, GI, J0>(s, b, rp, vo, tw4, s_lo, s_hi, s_top, hi_half), ...);
+}
+// the first NB - 1 groups' loads, before any is added in
+template <int LV, bool J0, int... GI>
+__device__ __forceinline__ void ka_prologue(std::integer_sequence<int, GI...>, KaBuf<LV, J0>& b,
+                                            __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4, int s_lo, int s_hi,
+                                            int s_top) {
+  constexpr int G = KaComb<LV>::G, NG = KaComb<LV>::NG;
+  ((GI < NG ? (ka_load<LV, (GI < NG ? GI : 0), J0>(rp, vo, tw4, s_lo, s_hi, s_top, b[GI]), vo += (u32)G * tw4)
+            : vo), ...);
 }
 
 // One slab position jj of every segment: load the segments' slabs, add in the
@@ -364,20 +385,27 @@ template <int LV, bool J0>
 __device__ __forceinline__ void ka_slab(int jj, int O, int nq, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rp,
                                         u32 voff, u32 tw4, bool hi_half, int (&cy)[2 << LV]) {
   constexpr int NSEG = 2 << LV, G = KaComb<LV>::G;
+  // The segments' slabs start the accumulators: one 4-byte load per limb
+  // straight into the low half of its accumulator, with no branch and no use
+  // before the first term, so all of them are in flight at once (the second
+  // limb's slab offset goes in the lane offset, which keeps the two loads from
+  // being merged into one whose halves would need copies, and waits, to reach
+  // the accumulators).  A slab at or above nq reads zero through the
+  // descriptor's range check (lane offset past its size).
   i64 s[NSEG][2];
 #pragma unroll
   for (int m = 0; m < NSEG; ++m) {
-    uint2 a = make_uint2(0u, 0u);
-    if (m * O + jj < nq) a = bld8(ra, voff, (m * O + jj) * 16384);
-    s[m][0] = a.x;
-    s[m][1] = a.y;
+    const int q = m * O + jj;
+    const u32 v = q < nq ? voff : kBufferOutOfRange;
+    const int so = (q < nq ? q : nq - 1) * 16384;
+    s[m][0] = (u32)__builtin_amdgcn_raw_buffer_load_b32(ra, (int)v, so, 0);
+    s[m][1] = (u32)__builtin_amdgcn_raw_buffer_load_b32(ra, (int)(v + 4 + (u32)so), 0, 0);
   }
   const int s_lo = jj * 16384, s_hi = (O + jj) * 16384, s_top = 2 * O * 16384;
-  uint2 b0[G][3], b1[G][3];
+  KaBuf<LV, J0> b;
   u32 vo = voff;
-  ka_load<LV, 0, J0>(rp, vo, tw4, s_lo, s_hi, s_top, b0);
-  vo += (u32)G * tw4;
-  ka_groups<LV, J0>(std::make_integer_sequence<int, KaComb<LV>::NG>{}, s, b0, b1, rp, vo, tw4, s_lo, s_hi, s_top,
+  ka_prologue<LV, J0>(std::make_integer_sequence<int, KaNb<LV, J0>::NB - 1>{}, b, rp, vo, tw4, s_lo, s_hi, s_top);
+  ka_groups<LV, J0>(std::make_integer_sequence<int, KaComb<LV>::NG>{}, s, b, rp, vo, tw4, s_lo, s_hi, s_top,
                     hi_half);
 #pragma unroll
   for (int m = 0; m < NSEG; ++m) {
