@@ -245,10 +245,11 @@ __global__ __launch_bounds__(256) void k_kara_fix(KaraArgs k, RangeTab rt, int C
 // Memory: the launch tile's products are contiguous (tile lt holds its np
 // products, tw words apart) and read through one buffer descriptor: a lane
 // offset (the entry, the product) in a register, the slab in a scalar.  The
-// products go in groups of G; the loads of group g + 1 are issued before
-// group g is added in (two groups of slabs in registers).  Before those loads
-// the accumulators pass through empty asm statements (they must hold their
-// values after group g - 1 there) and then the lane offset through one more,
+// products go in groups of G; the loads of group g + NB - 1 are issued before
+// group g is added in (NB groups of slabs in registers, NB below), into the
+// registers group g - 1 has just used.  Before those loads the accumulators
+// pass through empty asm statements (they must hold their values after group
+// g - 1 there) and then the lane offset through one more,
 // so the compiler neither hoists later loads into the accumulators' registers
 // nor keeps 3^L product offsets live; the fence emits no instruction.  Slab
 // position 0, the only one that reads the products' top slabs, runs as its own
