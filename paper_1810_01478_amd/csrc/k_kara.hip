@@ -343,7 +343,7 @@ struct KaGroupTerms {
   static constexpr int t0 = KaTab<LV>::P.first[p0], t1 = KaTab<LV>::P.first[p1];
 };
 
-// group GI: fence, the next group's loads, then this group's terms
+// group GI: fence, the loads of group GI + NB - 1, then this group's terms
 template <int LV, int GI, bool J0>
 __device__ __forceinline__ void ka_group(i64 (&s)[2 << LV][2], KaBuf<LV, J0>& b,
                                          __amdgpu_buffer_rsrc_t rp, u32& vo, u32 tw4, int s_lo, int s_hi, int s_top,
@@ -432,7 +432,7 @@ __device__ __forceinline__ void ka_slab(int jj, int O, int nq, __amdgpu_buffer_r
 // entry, in one pass over the 2^(L+1) segments; then the carry out of every
 // segment enters at its successor's first slab (the last one leaves the
 // entry).  Slabs at or above nq (the entry's nw / 4; there are some when the
-// split strings carry zero digits above the factors') are neither read nor
+// split strings carry zero digits above the factors') read as zero and are not
 // written: they only receive carries, and the entry keeps its value modulo
 // 2^(32 nw).
 template <int LV>
