@@ -1,7 +1,8 @@
 """Batched path (hl_batch_*): a batch of uneven instances gives, on every replay
 of its captured graph, the same bits as the single-instance path (itself
 bit-exact with the oracle), and the oracle's pivots and block directly for the
-small instances; the autotuner's choice gives the same bits."""
+small instances and, for two N = 256 instances, every bit of the oracle's
+records; the autotuner's choice gives the same bits."""
 import math
 from fractions import Fraction
 
@@ -113,6 +114,34 @@ def test_batch_update_forms_give_the_same_bits():
             assert r[j]["lambda1"] == r0[j]["lambda1"]
     for bt, _r in runs:
         bt.close()
+
+
+def test_batch_instances_bit_exact_vs_oracle_records():
+    # the oracle's records at N = 256 (beta = 1/2, k = 8: P = 8192 with one
+    # Karatsuba level, P = 32768 with three) as instances of one uneven batch:
+    # every pivot, multiplier, column of L^-1 and the block bit for bit, and
+    # lambda_1 from the batch's block against the record
+    from paper_1810_01478_amd.api import Batch
+    from test_gpu_goldens import check_factor_bits, check_solve_block, digits, record
+    recs = [record("c2b"), record("n256_p32768")]
+    specs = [(moments(Fraction(1, 2), 2 * r["N"] - 1), r["N"], r["k"], r["P"], r["E"], "mfma") for r in recs]
+    b, N, k, P, E, f = SPECS[2]
+    specs.append((_mu(b, N, P), N, k, P, E, f))
+    say("batch with the N = 256 oracle records")
+    batch = Batch(ctx(), specs)
+    batch.launch()
+    res = batch.results()
+    for j, rec in enumerate(recs):
+        assert res[j]["status"] == 0, j
+        fac = batch.facs[j]
+        check_factor_bits(fac, rec)
+        check_solve_block(fac, rec)
+        assert abs(res[j]["lambda1"] / float(rec["lam1"]) - 1) < 1e-14, j
+        dl, dt = digits(ctx().lambda_min(fac), rec, 2 * rec["P"])
+        say("  record", j, "lambda_1 digits %.0f, truncation digits %.0f" % (min(dl, 1e9), min(dt, 1e9)))
+        assert dl >= 150 and dt >= 100, j
+    assert res[2]["status"] == 0
+    batch.close()
 
 
 @pytest.mark.timeout(600)
